@@ -1,0 +1,202 @@
+#!/usr/bin/env python3
+"""Throughput of the fused QLA time step on one MI355X.
+
+Workload (default): the cylinder run -- a 4096 x 4096 periodic lattice,
+delta = 0.3, Eq. (28) potentials, an E_z Gaussian pulse of width 160 cells
+moving in +x toward a centred anisotropic cylinder of radius 400 cells
+(tanh edge width 6, n_x, n_y, n_z drawn U[1.2, 3.0] with seed 2), with the
+energy and div B diagnostics taken every 500 steps. One "step" is one full
+QLA time step of the whole lattice. Inputs are resident in HBM before the
+timed region starts.
+
+Prints one JSON line with the site-update rate, the roofline of the step
+kernel (algorithmic bytes: 24 B read + 24 B written of FP32 state and 12 B
+of FP32 index per site-update) and the FP64 oracle timed on the host cores
+on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0            # MI355X HBM3E, published
+ALGO_BYTES_PER_SITE = 60         # 6*4 read + 6*4 written + 3*4 index read
+DIAG_EVERY = 500
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_cylinder_4096_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2301_13601_amd", "csrc", "qla.hip")
+
+
+def kernel_source_hash() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per step-kernel launch from the committed rocprofv3 counter
+    runs, if they were taken on the current kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def make_workload(name: str, steps: int):
+    from paper_2301_13601_amd import scenes
+    if name == "cylinder_4096":
+        sc = scenes.config_scale(seed=2, N=4096, steps=steps)
+        desc = ("cylinder_4096: 4096x4096 periodic lattice, delta=0.3, Eq.(28) potentials, "
+                "E_z pulse width 160 at x0=1024, disk radius 400 edge 6, n~U[1.2,3.0] seed 2, "
+                "energy+divB every 500 steps")
+    elif name == "single_256":
+        sc = scenes.config_single()
+        desc = ("single_256: 256x256 periodic lattice, delta=0.3, Eq.(28) potentials, E_z pulse "
+                "width 20 at x0=48, ellipse 30x20 edge 6, n=(1.5,2.0,3.0), energy+divB every 500 steps")
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    return sc, desc
+
+
+def cpu_baseline(sc, sample_steps: int, sample_n: int):
+    """The FP64 oracle on the host cores, on a sample of the workload: the
+    same scene generator at sample_n x sample_n for sample_steps steps."""
+    from oracle import oracle as O
+    from paper_2301_13601_amd import scenes
+    if sample_n == sc.nx:
+        n, q = sc.n, sc.q
+    else:
+        s2 = scenes.config_scale(seed=2, N=sample_n, steps=sample_steps)
+        n, q = s2.n, s2.q
+    n32 = n.astype(np.float32).astype(np.float64)
+    q32 = q.astype(np.float32).astype(np.float64)
+    threads = O.threads(0)
+    t0 = time.perf_counter()
+    O.run(n32, q32, sc.delta, sample_steps, sc.pot_mode, "phys")
+    dt = time.perf_counter() - t0
+    rate = sample_n * sample_n * sample_steps / dt
+    return {"value": rate, "unit": "site-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{sample_n}x{sample_n} lattice of the same scene family, {sample_steps} steps, "
+                      f"{dt:.1f} s wall, FP64, OpenMP over {threads} threads"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--workload", default="cylinder_4096", choices=["cylinder_4096", "single_256"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-steps", type=int, default=6)
+    ap.add_argument("--cpu-sample-n", type=int, default=4096)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="also run one device copy of this many MiB (counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the lattice step is a single-GPU kernel here).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2301_13601_amd import qla
+
+    sc, desc = make_workload(args.workload, args.steps)
+    n32, q32 = sc.as_f32()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    sim = qla.Simulation(n32, q32, sc.delta, sc.pot_mode, "phys", device="cuda:0", stream=stream)
+    sites = sc.nx * sc.ny
+
+    # warmup (then restore the initial state so the timed run is the workload)
+    sim.step(args.warmup)
+    torch.cuda.synchronize()
+    sim.close()
+    sim = qla.Simulation(n32, q32, sc.delta, sc.pot_mode, "phys", device="cuda:0", stream=stream)
+    del n32, q32
+    diag0 = sim.diagnostics()
+    torch.cuda.synchronize()
+
+    # timed region: the whole job, diagnostics included
+    ev_pairs = []
+    log = []
+    done = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while done < args.steps:
+        k = min(DIAG_EVERY, args.steps - done)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        sim.step(k)
+        e1.record(stream)
+        ev_pairs.append((e0, e1, k))
+        done += k
+        if done % DIAG_EVERY == 0 or done == args.steps:
+            d = sim.diagnostics()
+            log.append({"step": d["step"], "energy": d["energy"],
+                        "divB_ratio": d["divB_max"] / d["B_max"] if d["B_max"] > 0 else 0.0})
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+    kernel_ms = sum(a.elapsed_time(b) for a, b, _ in ev_pairs)
+    launches = sum(k for _, _, k in ev_pairs)
+    avg_launch_s = kernel_ms / 1e3 / launches
+
+    if args.calib_copy_mib > 0:
+        nb = args.calib_copy_mib * (1 << 20)
+        a = torch.empty(nb // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    value = sites * args.steps / wall
+    achieved = sites * ALGO_BYTES_PER_SITE / avg_launch_s / 1e9
+    traffic = measured_traffic()
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                "kernel": "qla_step_kernel", "avg_launch_us": avg_launch_s * 1e6,
+                "algo_bytes_per_launch": sites * ALGO_BYTES_PER_SITE}
+
+    out = {
+        "metric": "lattice site-updates/s",
+        "value": value,
+        "unit": "site-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": desc, "nx": sc.nx, "ny": sc.ny, "delta": sc.delta,
+                   "pot_mode": sc.pot_mode, "sites": sites,
+                   "energy_drift": log[-1]["energy"] / diag0["energy"] - 1 if log else 0.0,
+                   "divB_ratio_final": log[-1]["divB_ratio"] if log else 0.0},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        sample_n = min(args.cpu_sample_n, sc.nx)
+        out["cpu_baseline"] = cpu_baseline(sc, args.cpu_sample_steps, sample_n)
+    sim.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

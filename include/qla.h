@@ -1,0 +1,129 @@
+/*
+ * qla.h -- C ABI of libqla, a gfx950 (MI355X) implementation of the qubit
+ * lattice algorithm (QLA) for the 2D curl-Maxwell equations in a diagonal
+ * tensor dielectric, after G. Vahala et al., "Qubit Lattice Algorithm
+ * Simulations of Maxwell's Equations for Scattering from Anisotropic
+ * Dielectric Objects", arXiv:2301.13601 (2023).
+ *
+ * The library advances the Dyson-mapped field
+ *     Q = (n_x E_x, n_y E_y, n_z E_z, B_x, B_y, B_z)            (Eq. (15))
+ * on a periodic nx-by-ny lattice with the collide-stream sequences U_X,
+ * U_Y (Eq. (17)-(20)) and the refractive-index potentials V_X, V_Y
+ * (Eq. (21), (22)), in the arrangement of Eq. (23) or Eq. (28), with the
+ * angles of Eq. (24) and (25). One call to qla_step performs whole time
+ * steps; every sub-operator of a step runs in one fused kernel pass.
+ *
+ * Conventions shared by every entry point:
+ *  - Arrays are structure-of-arrays FP32 planes in device memory,
+ *    component-major, then row (y), then column (x), x fastest:
+ *    element (c, y, x) is at index (c * ny + y) * nx + x.
+ *    Q has 6 planes (q0..q5 as above), n has 3 planes (n_x, n_y, n_z).
+ *  - Streaming pulls: S^{+x}_{ab} replaces q_a, q_b at column x by their
+ *    values at column x+1 (S^{-x}: x-1); likewise along y. This is the
+ *    direction under which Eq. (17)-(20) reproduce the signs of Eq. (16).
+ *  - Eq. (19) row 2 is read with sin(theta_2) in column 3; Eq. (22) is read
+ *    with 0 for the "o" of row 0 and q3' = sin(b3) q2 + cos(b3) q3.
+ *  - Eq. (25) derivatives are periodic central differences in cells, times
+ *    kappa (see qla_beta_scale).
+ *  - The library never allocates or frees device memory: the caller owns
+ *    every buffer (n, both state buffers, the workspace) and keeps them
+ *    alive until qla_free. All device work is enqueued on the caller's HIP
+ *    stream. No entry point throws; each returns a qla_status and records
+ *    a message retrievable with qla_last_error() (per thread).
+ */
+#ifndef QLA_H
+#define QLA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    QLA_OK = 0,
+    QLA_EINVAL = -1,   /* bad argument: null pointer, size, delta, mode, n <= 0 or not finite */
+    QLA_ENOMEM = -2,   /* host-side allocation failed, or the workspace is too small */
+    QLA_EDEVICE = -3,  /* a HIP call failed; the message holds hipGetErrorString */
+    QLA_ESTATE = -4    /* context unusable (null, freed, or poisoned by an earlier device error) */
+} qla_status;
+
+/* Placement of the potentials: Eq. (23) applies V_X(beta) then V_Y(beta)
+ * after U_Y U_X; Eq. (28) applies V_X(beta/2) after the 8th and after the
+ * 16th operator of U_X, and V_Y(beta/2) likewise within U_Y. */
+typedef enum { QLA_POT_EQ23 = 0, QLA_POT_EQ28 = 1 } qla_pot_mode;
+
+/* Scale kappa of the index derivative in Eq. (25):
+ *   PHYS:    kappa = delta   (lattice spacing delta in the coordinates of
+ *                             Eq. (25); the reading consistent with Eq. (26))
+ *   LATTICE: kappa = delta^2 (derivative taken per cell)
+ *   OFF:     kappa = 0       (no potentials: the unitary collide-stream
+ *                             sequence alone) */
+typedef enum { QLA_BETA_PHYS = 0, QLA_BETA_LATTICE = 1, QLA_BETA_OFF = 2 } qla_beta_scale;
+
+typedef struct {
+    int32_t nx, ny;       /* lattice size, each >= 1 */
+    double delta;         /* the perturbation parameter delta > 0 (Sec. 3) */
+    int32_t pot_mode;     /* qla_pot_mode */
+    int32_t beta_scale;   /* qla_beta_scale */
+} qla_params;
+
+/* Diagnostics of the current state (Sec. 3.1 and 4), all accumulated in FP64.
+ *   energy   = (1/(nx ny)) sum over sites of Q.Q                     (Eq. (27))
+ *   divB     = D_x B_x + D_y B_y,  D the periodic central difference in cells
+ *   divD     = D_x (n_x q0) + D_y (n_y q1)   (D_c = eps_c E_c = n_c q_c)
+ *   *_max are maxima of absolute values over the lattice, *_l2 Euclidean
+ *   norms over the lattice; B_max, D_max are max |B| and max |D|. */
+typedef struct {
+    int64_t step;         /* whole steps taken since qla_init */
+    double energy;
+    double divB_max, divB_l2, B_max, B_l2;
+    double divD_max, divD_l2, D_max;
+} qla_diag;
+
+typedef struct qla_ctx qla_ctx;   /* opaque */
+
+/* Bytes of device workspace qla_init needs for these parameters. */
+qla_status qla_workspace_size(const qla_params *p, size_t *bytes);
+
+/* Bind the caller's buffers and validate n.
+ *   d_n        3*ny*nx FP32, n_x, n_y, n_z; read by every step, never written
+ *   d_q        6*ny*nx FP32, holds Q at step 0 on entry
+ *   d_q_pong   6*ny*nx FP32 scratch state; steps alternate between the two
+ *   d_work     qla_workspace_size() bytes, 256-byte aligned
+ *   hip_stream a hipStream_t (NULL: the default stream); all work is
+ *              enqueued on it
+ * Every n must be > 0 and finite (QLA_EINVAL otherwise). Synchronises the
+ * stream once (to read the validation result). On success *out owns only
+ * host memory. */
+qla_status qla_init(const qla_params *p, const float *d_n, float *d_q, float *d_q_pong,
+                    void *d_work, void *hip_stream, qla_ctx **out);
+
+/* Enqueue nsteps >= 0 whole time steps (Eq. (23) or Eq. (28)) on the
+ * context's stream. Asynchronous; launch errors are reported. */
+qla_status qla_step(qla_ctx *ctx, int64_t nsteps);
+
+/* Compute qla_diag for the current state. Synchronises the stream. */
+qla_status qla_energy(qla_ctx *ctx, qla_diag *out);
+
+/* Copy the current state to dst (6*ny*nx FP32).
+ *   what = 0: Q as stored;  what = 1: (E, B) with E_c = q_c / n_c (Eq. (15))
+ *   dst_is_host = 1: dst is host memory; 0: device memory
+ * Synchronises the stream. */
+qla_status qla_fields(qla_ctx *ctx, float *dst, int32_t what, int32_t dst_is_host);
+
+/* Device pointer of the buffer holding the current state (d_q or d_q_pong). */
+qla_status qla_state(qla_ctx *ctx, float **d_current);
+
+/* Release the context's host memory. Safe on NULL. Does not synchronise. */
+void qla_free(qla_ctx *ctx);
+
+/* Message describing the last failure on this thread ("" if none). */
+const char *qla_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QLA_H */

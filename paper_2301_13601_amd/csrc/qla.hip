@@ -1,0 +1,987 @@
+// libqla: the qubit lattice algorithm (QLA) time step of Vahala et al.,
+// arXiv:2301.13601, as hand-written HIP for gfx950 (MI355X), behind the C ABI
+// declared in include/qla.h.
+//
+// One time step is one launch of qla_step_kernel, which applies, for every
+// site, the whole operator sequence of Eq. (23) or Eq. (28): U_X (Eq. (18),
+// 16 factors), U_Y (Eq. (20), 16 factors) and the potentials V_X, V_Y
+// (Eq. (21), (22)), with the collision angles of Eq. (24) and potential
+// angles of Eq. (25) computed on the fly from n. State is FP32; the
+// diagnostics (Eq. (27), div B, div D) accumulate in FP64.
+//
+// Work decomposition of the fused step (see the design notes for the why):
+//  * a wave owns a strip of 64*C consecutive columns (C per lane) and a
+//    segment of rows; it marches down its segment one row per iteration;
+//  * the x sweep of the ingested row runs in registers: a streaming shift
+//    along x is a register rename for C-1 of the lane's columns and one DPP
+//    whole-wave shift for the last; the outermost ceil(4/C) lanes on each
+//    side are halo (one step's x support is +-4 cells) and store nothing;
+//  * the y sweep is a 16-stage register pipeline: a stage that streams from
+//    y-1 reads a one-row delay register, a stage that streams from y+1
+//    delays the other two active components by one row instead, so the
+//    pipeline emits the fully stepped row R-4 after ingesting row R;
+//  * the loop is unrolled four times so that every ring of per-row data
+//    (collision coefficients, potential coefficients) is indexed by
+//    compile-time slots and stays in registers.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <type_traits>
+
+#include "qla.h"
+
+namespace {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------------------
+// Cross-lane moves (DPP whole-wave shifts by one lane; the lane with no
+// source receives 0, which only ever lands in halo lanes).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float from_next_lane(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float from_prev_lane(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+}
+
+// Streaming along x in pull form: S^{+x} sets v(x) = v(x + 1).
+template <int C>
+__device__ __forceinline__ void pull_from_right(float (&v)[C]) {
+  const float nb = from_next_lane(v[0]);
+#pragma unroll
+  for (int k = 0; k < C - 1; ++k) v[k] = v[k + 1];
+  v[C - 1] = nb;
+}
+// S^{-x}: v(x) = v(x - 1).
+template <int C>
+__device__ __forceinline__ void pull_from_left(float (&v)[C]) {
+  const float nb = from_prev_lane(v[C - 1]);
+#pragma unroll
+  for (int k = C - 1; k > 0; --k) v[k] = v[k - 1];
+  v[0] = nb;
+}
+
+// ---------------------------------------------------------------------------
+// Rotation R(phi) of the pair (a, b): a' = cos a - sin b, b' = sin a + cos b,
+// as three shears with t = tan(phi/2), s = sin(phi). SGN = -1 rotates by
+// -phi. Both coefficients are small numbers carried at full relative
+// precision, which keeps cos^2 + sin^2 = 1 to FP32 rounding (a cos(phi)
+// rounded to FP32 does not, and that bias compounds over the 32 rotations
+// of every step).
+// ---------------------------------------------------------------------------
+template <int SGN>
+__device__ __forceinline__ void rot(float& a, float& b, float t, float s) {
+  if constexpr (SGN > 0) {
+    a = fmaf(-t, b, a);
+    b = fmaf(s, a, b);
+    a = fmaf(-t, b, a);
+  } else {
+    a = fmaf(t, b, a);
+    b = fmaf(-s, a, b);
+    a = fmaf(t, b, a);
+  }
+}
+
+// (t, s) = (tan(theta/2), sin(theta)). The short series is accurate to well
+// below an FP32 ulp for |theta| <= kNarrowAngle; wider angles use libm.
+constexpr float kNarrowAngle = 0.12f;
+
+template <bool WIDE>
+__device__ __forceinline__ void rot_coef(float th, float& t, float& s) {
+  if constexpr (WIDE) {
+    s = sinf(th);
+    t = tanf(0.5f * th);
+  } else {
+    const float th2 = th * th;
+    s = th * fmaf(th2, fmaf(th2, 1.0f / 120.0f, -1.0f / 6.0f), 1.0f);
+    t = th * fmaf(th2, fmaf(th2, 1.0f / 240.0f, 1.0f / 24.0f), 0.5f);
+  }
+}
+
+// Potential coefficients (sin b, 1 - cos b) for an applied angle b.
+template <bool WIDE>
+__device__ __forceinline__ void pot_coef(float b, float& sb, float& hb) {
+  if constexpr (WIDE) {
+    sb = sinf(b);
+    const float h = sinf(0.5f * b);
+    hb = 2.0f * h * h;
+  } else {
+    const float b2 = b * b;
+    sb = b * fmaf(b2, fmaf(b2, 1.0f / 120.0f, -1.0f / 6.0f), 1.0f);
+    hb = b2 * fmaf(b2, fmaf(b2, 1.0f / 720.0f, -1.0f / 24.0f), 0.5f);
+  }
+}
+
+// a' = cos(b) a + sgn * sin(b) p  ==  a - (1 - cos b) a + sgn sin(b) p
+__device__ __forceinline__ float pot_row(float a, float p, float sb, float hb) {
+  return fmaf(sb, p, fmaf(-hb, a, a));
+}
+
+// ---------------------------------------------------------------------------
+// Step kernel.
+// ---------------------------------------------------------------------------
+struct StepArgs {
+  const float* __restrict__ qin;   // 6 planes
+  float* __restrict__ qout;        // 6 planes
+  const float* __restrict__ n;     // 3 planes
+  int64_t plane;                   // nx * ny
+  int nx, ny;
+  int seg_rows;                    // rows per wave segment (multiple of 4)
+  int nstrips, nsegs;
+  int waves_per_block;
+  float a4;                        // delta / 4                    (Eq. (24))
+  float kb;                        // kappa * frac / 2             (Eq. (25))
+};
+
+template <int C>
+struct Cols {
+  static constexpr int kHaloLanes = (4 + C - 1) / C;
+  static constexpr int kOut = (kWave - 2 * kHaloLanes) * C;   // output columns per strip
+};
+
+__device__ __forceinline__ int wrap_index(int64_t i, int n) {
+  int64_t r = i % n;
+  return static_cast<int>(r < 0 ? r + n : r);
+}
+
+template <int C, bool VEC>
+__device__ __forceinline__ void load_row(const float* __restrict__ base, const int (&xk)[C],
+                                         float (&out)[C]) {
+  if constexpr (VEC && C == 4) {
+    const float4 v = *reinterpret_cast<const float4*>(base + xk[0]);
+    out[0] = v.x; out[1] = v.y; out[2] = v.z; out[3] = v.w;
+  } else if constexpr (VEC && C == 2) {
+    const float2 v = *reinterpret_cast<const float2*>(base + xk[0]);
+    out[0] = v.x; out[1] = v.y;
+  } else {
+#pragma unroll
+    for (int k = 0; k < C; ++k) out[k] = base[xk[k]];
+  }
+}
+
+template <int C, bool VEC>
+__device__ __forceinline__ void store_row(float* __restrict__ base, const int (&xk)[C],
+                                          const float (&v)[C], const bool (&ok)[C]) {
+  if constexpr (VEC && C == 4) {
+    if (ok[0]) *reinterpret_cast<float4*>(base + xk[0]) = make_float4(v[0], v[1], v[2], v[3]);
+  } else if constexpr (VEC && C == 2) {
+    if (ok[0]) *reinterpret_cast<float2*>(base + xk[0]) = make_float2(v[0], v[1]);
+  } else {
+#pragma unroll
+    for (int k = 0; k < C; ++k)
+      if (ok[k]) base[xk[k]] = v[k];
+  }
+}
+
+// Everything a wave carries from one row iteration to the next.
+template <int C>
+struct Pipe {
+  // y-sweep stream stages (ops 2,4,6,8,10,12,14,16 of Eq. (20) in the
+  // order they act): one-row delay registers for two components each
+  float d[8][2][C];
+  // collision coefficients (tan(theta_0/2), sin theta_0, tan(theta_2/2),
+  // sin theta_2) of the last four rows, slot = row mod 4
+  float th[4][4][C];
+  // V_Y coefficients (sin b1, 1-cos b1, sin b3, 1-cos b3) per row slot
+  float vy[4][4][C];
+  // Eq. (23) only: V_X coefficients and the (q1, q4) pair per row slot,
+  // both applied after U_Y
+  float vx[4][4][C];
+  float q14[4][2][C];
+  // the ingested row R: Q, and n for rows R-1 (x, z), R, R+1
+  float q[6][C];
+  float nprev[2][C];
+  float ncur[3][C];
+  float nnext[3][C];
+};
+
+// MODE: 0 = Eq. (23), 1 = Eq. (28). POT: potentials present (kappa != 0).
+template <int C, bool VEC, bool WIDE, int MODE, bool POT, int SLOT>
+__device__ __forceinline__ void row_iteration(Pipe<C>& p, const StepArgs& g, const int (&xk)[C],
+                                              const bool (&lane_out)[C], int i, int seg_h,
+                                              int y0, int64_t off_q_next, int64_t off_n_next2) {
+  // ---- prefetch Q of row R+1 and n of row R+2 -----------------------------
+  float qn[6][C];
+  float nn2[3][C];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) load_row<C, VEC>(g.qin + c * g.plane + off_q_next, xk, qn[c]);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) load_row<C, VEC>(g.n + c * g.plane + off_n_next2, xk, nn2[c]);
+
+  // ---- coefficients of row R (Eq. (24), (25)) -----------------------------
+  float u[3][C];
+  float tc[3][C], sc[3][C];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+      u[c][k] = __builtin_amdgcn_rcpf(p.ncur[c][k]);
+      rot_coef<WIDE>(g.a4 * u[c][k], tc[c][k], sc[c][k]);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < C; ++k) {
+    p.th[SLOT][0][k] = tc[0][k];
+    p.th[SLOT][1][k] = sc[0][k];
+    p.th[SLOT][2][k] = tc[2][k];
+    p.th[SLOT][3][k] = sc[2][k];
+  }
+  // V_X coefficients from the x-differences of n_y (beta_0) and n_z (beta_2)
+  float vxs0[C], vxh0[C], vxs2[C], vxh2[C];
+  if constexpr (POT) {
+    float nyr[C], nyl[C], nzr[C], nzl[C];
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+      nyr[k] = p.ncur[1][k]; nyl[k] = p.ncur[1][k];
+      nzr[k] = p.ncur[2][k]; nzl[k] = p.ncur[2][k];
+    }
+    pull_from_right<C>(nyr); pull_from_left<C>(nyl);
+    pull_from_right<C>(nzr); pull_from_left<C>(nzl);
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+      const float b0 = g.kb * (nyr[k] - nyl[k]) * (u[1][k] * u[1][k]);
+      const float b2 = g.kb * (nzr[k] - nzl[k]) * (u[2][k] * u[2][k]);
+      pot_coef<WIDE>(b0, vxs0[k], vxh0[k]);
+      pot_coef<WIDE>(b2, vxs2[k], vxh2[k]);
+    }
+  }
+
+  // ---- U_X (Eq. (18)) with V_X' interleaved (Eq. (28)) on row R ------------
+  float (&q)[6][C] = p.q;
+  const float (&t1)[C] = tc[1];
+  const float (&s1)[C] = sc[1];
+  const float (&t2)[C] = tc[2];
+  const float (&s2)[C] = sc[2];
+  auto cx = [&](auto sgn) {
+    constexpr int S = decltype(sgn)::value;
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+      rot<S>(q[1][k], q[5][k], t1[k], s1[k]);
+      rot<S>(q[2][k], q[4][k], t2[k], s2[k]);
+    }
+  };
+  using P_ = std::integral_constant<int, 1>;
+  using M_ = std::integral_constant<int, -1>;
+  auto vx_apply = [&]() {
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+      q[4][k] = pot_row(q[4][k], -q[2][k], vxs2[k], vxh2[k]);
+      q[5][k] = pot_row(q[5][k], q[1][k], vxs0[k], vxh0[k]);
+    }
+  };
+  cx(M_{}); pull_from_left<C>(q[1]);  pull_from_left<C>(q[4]);
+  cx(P_{}); pull_from_right<C>(q[1]); pull_from_right<C>(q[4]);
+  cx(M_{}); pull_from_right<C>(q[2]); pull_from_right<C>(q[5]);
+  cx(P_{}); pull_from_left<C>(q[2]);  pull_from_left<C>(q[5]);
+  if constexpr (MODE == 1 && POT) vx_apply();
+  cx(P_{}); pull_from_right<C>(q[1]); pull_from_right<C>(q[4]);
+  cx(M_{}); pull_from_left<C>(q[1]);  pull_from_left<C>(q[4]);
+  cx(P_{}); pull_from_left<C>(q[2]);  pull_from_left<C>(q[5]);
+  cx(M_{}); pull_from_right<C>(q[2]); pull_from_right<C>(q[5]);
+  if constexpr (MODE == 1 && POT) vx_apply();
+
+  const int R_rel = i - 4;     // row R relative to y0
+  const int O_rel = i - 8;     // row R-4 relative to y0
+  if constexpr (MODE == 1) {
+    // q1 and q4 are final once U_X and V_X' are done: U_Y and V_Y leave them
+    if (R_rel >= 0 && R_rel < seg_h) {
+      const int64_t off = static_cast<int64_t>(y0 + R_rel) * g.nx;
+      store_row<C, VEC>(g.qout + 1 * g.plane + off, xk, q[1], lane_out);
+      store_row<C, VEC>(g.qout + 4 * g.plane + off, xk, q[4], lane_out);
+    }
+  }
+
+  // ---- U_Y (Eq. (20)) as a pipeline over rows ------------------------------
+  // active components: a0 = q0, a5 = q5 (angle theta_0), b2 = q2, b3 = q3
+  // (angle theta_2); C_Y rotates both pairs by -theta (Eq. (19)).
+  float (&a0)[C] = q[0];
+  float (&a5)[C] = q[5];
+  float (&b2)[C] = q[2];
+  float (&b3)[C] = q[3];
+  auto cy = [&](auto sgn, auto lag) {
+    constexpr int S = decltype(sgn)::value;
+    constexpr int sl = (SLOT - decltype(lag)::value) & 3;
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+      rot<-S>(a0[k], a5[k], p.th[sl][0][k], p.th[sl][1][k]);
+      rot<-S>(b2[k], b3[k], p.th[sl][2][k], p.th[sl][3][k]);
+    }
+  };
+  auto swap_in = [&](float (&cur)[C], float (&dly)[C]) {
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+      const float t = cur[k];
+      cur[k] = dly[k];
+      dly[k] = t;
+    }
+  };
+  auto vy_apply = [&](auto lag) {
+    constexpr int sl = (SLOT - decltype(lag)::value) & 3;
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+      b3[k] = pot_row(b3[k], b2[k], p.vy[sl][2][k], p.vy[sl][3][k]);
+      a5[k] = pot_row(a5[k], -a0[k], p.vy[sl][0][k], p.vy[sl][1][k]);
+    }
+  };
+  using L0 = std::integral_constant<int, 0>;
+  using L1 = std::integral_constant<int, 1>;
+  using L2 = std::integral_constant<int, 2>;
+  using L3 = std::integral_constant<int, 3>;
+  using L4 = std::integral_constant<int, 4>;
+  // Operators in the order they act; a stage streaming from y-1 swaps its
+  // two shifted components with the delay line, a stage streaming from y+1
+  // swaps the two it leaves in place (and adds one row of lag).
+  cy(M_{}, L0{});                                   // C_Y^dagger
+  swap_in(a0, p.d[0][0]); swap_in(b3, p.d[0][1]);   // S^{-y}_{03}
+  cy(P_{}, L0{});                                   // C_Y
+  swap_in(a5, p.d[1][0]); swap_in(b2, p.d[1][1]);   // S^{+y}_{03}
+  cy(M_{}, L1{});                                   // C_Y^dagger
+  swap_in(a0, p.d[2][0]); swap_in(b3, p.d[2][1]);   // S^{+y}_{25}
+  cy(P_{}, L2{});                                   // C_Y
+  swap_in(b2, p.d[3][0]); swap_in(a5, p.d[3][1]);   // S^{-y}_{25}
+  if constexpr (MODE == 1 && POT) vy_apply(L2{});   // V_Y' (Eq. (28))
+  cy(P_{}, L2{});                                   // C_Y
+  swap_in(a5, p.d[4][0]); swap_in(b2, p.d[4][1]);   // S^{+y}_{03}
+  cy(M_{}, L3{});                                   // C_Y^dagger
+  swap_in(a0, p.d[5][0]); swap_in(b3, p.d[5][1]);   // S^{-y}_{03}
+  cy(P_{}, L3{});                                   // C_Y
+  swap_in(b2, p.d[6][0]); swap_in(a5, p.d[6][1]);   // S^{-y}_{25}
+  cy(M_{}, L3{});                                   // C_Y^dagger
+  swap_in(a0, p.d[7][0]); swap_in(b3, p.d[7][1]);   // S^{+y}_{25}
+  // the pipeline now holds row R-4
+  float o1[C], o4[C];
+  if constexpr (MODE == 1) {
+    if constexpr (POT) vy_apply(L4{});              // V_Y' (Eq. (28))
+  } else {
+    // Eq. (23): V_X then V_Y after U_Y, on row R-4
+    constexpr int sl = (SLOT - 4) & 3;
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+      o1[k] = p.q14[sl][0][k];
+      o4[k] = p.q14[sl][1][k];
+      if constexpr (POT) {
+        o4[k] = pot_row(o4[k], -b2[k], p.vx[sl][2][k], p.vx[sl][3][k]);
+        a5[k] = pot_row(a5[k], o1[k], p.vx[sl][0][k], p.vx[sl][1][k]);
+      }
+    }
+    if constexpr (POT) vy_apply(L4{});
+  }
+  if (O_rel >= 0 && O_rel < seg_h) {
+    const int64_t off = static_cast<int64_t>(y0 + O_rel) * g.nx;
+    store_row<C, VEC>(g.qout + 0 * g.plane + off, xk, a0, lane_out);
+    store_row<C, VEC>(g.qout + 2 * g.plane + off, xk, b2, lane_out);
+    store_row<C, VEC>(g.qout + 3 * g.plane + off, xk, b3, lane_out);
+    store_row<C, VEC>(g.qout + 5 * g.plane + off, xk, a5, lane_out);
+    if constexpr (MODE == 0) {
+      store_row<C, VEC>(g.qout + 1 * g.plane + off, xk, o1, lane_out);
+      store_row<C, VEC>(g.qout + 4 * g.plane + off, xk, o4, lane_out);
+    }
+  }
+
+  // ---- per-row data kept for later rows --------------------------------
+  if constexpr (MODE == 0) {
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+      // q1, q4 of row R after U_X (the pipeline above consumed slot R-4)
+      // are written back into the same slot; see the note on slot reuse.
+      p.q14[SLOT][0][k] = p.q[1][k];
+      p.q14[SLOT][1][k] = p.q[4][k];
+      if constexpr (POT) {
+        p.vx[SLOT][0][k] = vxs0[k];
+        p.vx[SLOT][1][k] = vxh0[k];
+        p.vx[SLOT][2][k] = vxs2[k];
+        p.vx[SLOT][3][k] = vxh2[k];
+      }
+    }
+  }
+  if constexpr (POT) {
+    // V_Y coefficients of row R from the y-differences of n_x (beta_1) and
+    // n_z (beta_3); slot R mod 4 was last read above (as row R-4)
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+      const float b1 = g.kb * (p.nnext[0][k] - p.nprev[0][k]) * (u[0][k] * u[0][k]);
+      const float b3c = g.kb * (p.nnext[2][k] - p.nprev[1][k]) * (u[2][k] * u[2][k]);
+      pot_coef<WIDE>(b1, p.vy[SLOT][0][k], p.vy[SLOT][1][k]);
+      pot_coef<WIDE>(b3c, p.vy[SLOT][2][k], p.vy[SLOT][3][k]);
+    }
+  }
+  // advance the row window
+#pragma unroll
+  for (int k = 0; k < C; ++k) {
+    p.nprev[0][k] = p.ncur[0][k];
+    p.nprev[1][k] = p.ncur[2][k];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      p.ncur[c][k] = p.nnext[c][k];
+      p.nnext[c][k] = nn2[c][k];
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) p.q[c][k] = qn[c][k];
+  }
+}
+
+template <int C, bool VEC, bool WIDE, int MODE, bool POT>
+__global__ void __launch_bounds__(256) qla_step_kernel(StepArgs g) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x / kWave;
+  // blocks are dealt round-robin to the 8 XCDs; regroup them so that each
+  // XCD gets a contiguous band of the lattice (neighbouring strips share
+  // halo columns through that XCD's L2)
+  const int nblk = gridDim.x;
+  const int b = blockIdx.x;
+  const int per = nblk / 8;
+  const int rem = nblk % 8;
+  const int xcd = b % 8;
+  const int k8 = b / 8;
+  const int logical = (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + k8;
+  const int strip = logical % g.nstrips;
+  const int seg = (logical / g.nstrips) * g.waves_per_block + wave;
+  if (seg >= g.nsegs) return;
+
+  const int y0 = seg * g.seg_rows;
+  const int seg_h = min(g.seg_rows, g.ny - y0);
+  const int x0 = strip * Cols<C>::kOut;
+  const int64_t col0 = static_cast<int64_t>(x0) - Cols<C>::kHaloLanes * C + lane * C;
+  int xk[C];
+  bool ok[C];
+  const bool lane_in = lane >= Cols<C>::kHaloLanes && lane < kWave - Cols<C>::kHaloLanes;
+#pragma unroll
+  for (int k = 0; k < C; ++k) {
+    xk[k] = wrap_index(col0 + k, g.nx);
+    ok[k] = lane_in && (col0 + k < g.nx);
+  }
+
+  Pipe<C> p;
+#pragma unroll
+  for (int s = 0; s < 8; ++s)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int k = 0; k < C; ++k) p.d[s][c][k] = 0.0f;
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int k = 0; k < C; ++k) {
+        p.th[s][c][k] = 0.0f;
+        p.vy[s][c][k] = 0.0f;
+        p.vx[s][c][k] = 0.0f;
+      }
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+#pragma unroll
+    for (int k = 0; k < C; ++k) p.q14[s][0][k] = p.q14[s][1][k] = 0.0f;
+
+  // prologue: Q of row y0-4, n of rows y0-5 .. y0-3
+  const int64_t R0 = static_cast<int64_t>(y0) - 4;
+  const int64_t nx64 = g.nx;
+  {
+    const int64_t oq = wrap_index(R0, g.ny) * nx64;
+    const int64_t om = wrap_index(R0 - 1, g.ny) * nx64;
+    const int64_t on = wrap_index(R0 + 1, g.ny) * nx64;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) load_row<C, VEC>(g.qin + c * g.plane + oq, xk, p.q[c]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      load_row<C, VEC>(g.n + c * g.plane + oq, xk, p.ncur[c]);
+      load_row<C, VEC>(g.n + c * g.plane + on, xk, p.nnext[c]);
+    }
+    load_row<C, VEC>(g.n + 0 * g.plane + om, xk, p.nprev[0]);
+    load_row<C, VEC>(g.n + 2 * g.plane + om, xk, p.nprev[1]);
+  }
+  // row R+1 for Q prefetch and R+2 for n prefetch, wrapped incrementally
+  int rq = wrap_index(R0 + 1, g.ny);
+  int rn = wrap_index(R0 + 2, g.ny);
+  const int iters = ((seg_h + 8) + 3) & ~3;
+  for (int i = 0; i < iters; i += 4) {
+#define QLA_ITER(S)                                                                            \
+  {                                                                                            \
+    row_iteration<C, VEC, WIDE, MODE, POT, S>(p, g, xk, ok, i + S, seg_h, y0, rq * nx64,       \
+                                              rn * nx64);                                      \
+    rq = (rq + 1 == g.ny) ? 0 : rq + 1;                                                        \
+    rn = (rn + 1 == g.ny) ? 0 : rn + 1;                                                        \
+  }
+    QLA_ITER(0)
+    QLA_ITER(1)
+    QLA_ITER(2)
+    QLA_ITER(3)
+#undef QLA_ITER
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Validation scan of n at init: smallest n, largest applied potential angle,
+// and a flag for any n <= 0 or not finite. One partial per block.
+// ---------------------------------------------------------------------------
+struct ScanPartial {
+  double nmin;
+  double bmax;
+  double bad;
+  double pad;
+};
+
+__device__ __forceinline__ double wave_min(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+__global__ void __launch_bounds__(256) qla_scan_kernel(const float* __restrict__ n, int nx, int ny,
+                                                       double kb, ScanPartial* __restrict__ out) {
+  const int64_t plane = static_cast<int64_t>(nx) * ny;
+  double nmin = INFINITY, bmax = 0.0, bad = 0.0;
+  for (int64_t s = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; s < plane;
+       s += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int y = static_cast<int>(s / nx);
+    const int x = static_cast<int>(s - static_cast<int64_t>(y) * nx);
+    const int xp = x + 1 == nx ? 0 : x + 1, xm = x == 0 ? nx - 1 : x - 1;
+    const int yp = y + 1 == ny ? 0 : y + 1, ym = y == 0 ? ny - 1 : y - 1;
+    double v[3];
+    for (int c = 0; c < 3; ++c) {
+      v[c] = n[c * plane + s];
+      if (!(v[c] > 0.0) || !isfinite(v[c])) bad = 1.0;
+      nmin = fmin(nmin, v[c]);
+    }
+    if (bad == 0.0) {
+      const double d0 = n[1 * plane + static_cast<int64_t>(y) * nx + xp] - n[1 * plane + static_cast<int64_t>(y) * nx + xm];
+      const double d1 = n[0 * plane + static_cast<int64_t>(yp) * nx + x] - n[0 * plane + static_cast<int64_t>(ym) * nx + x];
+      const double d2 = n[2 * plane + static_cast<int64_t>(y) * nx + xp] - n[2 * plane + static_cast<int64_t>(y) * nx + xm];
+      const double d3 = n[2 * plane + static_cast<int64_t>(yp) * nx + x] - n[2 * plane + static_cast<int64_t>(ym) * nx + x];
+      bmax = fmax(bmax, fabs(kb * d0 / (v[1] * v[1])));
+      bmax = fmax(bmax, fabs(kb * d1 / (v[0] * v[0])));
+      bmax = fmax(bmax, fabs(kb * d2 / (v[2] * v[2])));
+      bmax = fmax(bmax, fabs(kb * d3 / (v[2] * v[2])));
+    }
+  }
+  __shared__ double sh[3][4];
+  nmin = wave_min(nmin);
+  bmax = wave_max(bmax);
+  bad = wave_max(bad);
+  const int w = threadIdx.x / kWave;
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    sh[0][w] = nmin;
+    sh[1][w] = bmax;
+    sh[2][w] = bad;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nw = blockDim.x / kWave;
+    for (int k = 1; k < nw; ++k) {
+      nmin = fmin(nmin, sh[0][k]);
+      bmax = fmax(bmax, sh[1][k]);
+      bad = fmax(bad, sh[2][k]);
+    }
+    out[blockIdx.x] = ScanPartial{nmin, bmax, bad, 0.0};
+  }
+}
+
+__global__ void qla_scan_final(ScanPartial* __restrict__ parts, int count) {
+  double nmin = INFINITY, bmax = 0.0, bad = 0.0;
+  for (int k = threadIdx.x; k < count; k += blockDim.x) {
+    nmin = fmin(nmin, parts[k].nmin);
+    bmax = fmax(bmax, parts[k].bmax);
+    bad = fmax(bad, parts[k].bad);
+  }
+  nmin = wave_min(nmin);
+  bmax = wave_max(bmax);
+  bad = wave_max(bad);
+  if (threadIdx.x == 0) parts[count] = ScanPartial{nmin, bmax, bad, 0.0};
+}
+
+// ---------------------------------------------------------------------------
+// Diagnostics (Eq. (27), div B, div D): per-block FP64 partials, then one
+// block folds them.
+// ---------------------------------------------------------------------------
+constexpr int kDiagVals = 8;   // energy, sum divB^2, max|divB|, max|B|^2, sum|B|^2,
+                               // sum divD^2, max|divD|, max|D|^2
+constexpr int kDiagBlocks = 1024;
+
+__global__ void __launch_bounds__(256) qla_diag_kernel(const float* __restrict__ q,
+                                                       const float* __restrict__ n, int nx, int ny,
+                                                       double* __restrict__ out) {
+  const int64_t plane = static_cast<int64_t>(nx) * ny;
+  double e = 0, sdb = 0, mdb = 0, mb = 0, sb = 0, sdd = 0, mdd = 0, md = 0;
+  for (int64_t s = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; s < plane;
+       s += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int y = static_cast<int>(s / nx);
+    const int x = static_cast<int>(s - static_cast<int64_t>(y) * nx);
+    const int64_t row = static_cast<int64_t>(y) * nx;
+    const int64_t sxp = row + (x + 1 == nx ? 0 : x + 1);
+    const int64_t sxm = row + (x == 0 ? nx - 1 : x - 1);
+    const int64_t syp = static_cast<int64_t>(y + 1 == ny ? 0 : y + 1) * nx + x;
+    const int64_t sym = static_cast<int64_t>(y == 0 ? ny - 1 : y - 1) * nx + x;
+    double qq[6];
+    for (int c = 0; c < 6; ++c) {
+      qq[c] = q[c * plane + s];
+      e += qq[c] * qq[c];
+    }
+    const double divb = 0.5 * (static_cast<double>(q[3 * plane + sxp]) - q[3 * plane + sxm]) +
+                        0.5 * (static_cast<double>(q[4 * plane + syp]) - q[4 * plane + sym]);
+    const double divd =
+        0.5 * (static_cast<double>(n[0 * plane + sxp]) * q[0 * plane + sxp] -
+               static_cast<double>(n[0 * plane + sxm]) * q[0 * plane + sxm]) +
+        0.5 * (static_cast<double>(n[1 * plane + syp]) * q[1 * plane + syp] -
+               static_cast<double>(n[1 * plane + sym]) * q[1 * plane + sym]);
+    const double b2 = qq[3] * qq[3] + qq[4] * qq[4] + qq[5] * qq[5];
+    const double dx = n[0 * plane + s] * qq[0], dy = n[1 * plane + s] * qq[1],
+                 dz = n[2 * plane + s] * qq[2];
+    const double d2 = dx * dx + dy * dy + dz * dz;
+    sdb += divb * divb;
+    mdb = fmax(mdb, fabs(divb));
+    mb = fmax(mb, b2);
+    sb += b2;
+    sdd += divd * divd;
+    mdd = fmax(mdd, fabs(divd));
+    md = fmax(md, d2);
+  }
+  e = wave_sum(e); sdb = wave_sum(sdb); sb = wave_sum(sb); sdd = wave_sum(sdd);
+  mdb = wave_max(mdb); mb = wave_max(mb); mdd = wave_max(mdd); md = wave_max(md);
+  __shared__ double sh[kDiagVals][4];
+  const int w = threadIdx.x / kWave;
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    sh[0][w] = e; sh[1][w] = sdb; sh[2][w] = mdb; sh[3][w] = mb;
+    sh[4][w] = sb; sh[5][w] = sdd; sh[6][w] = mdd; sh[7][w] = md;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nw = blockDim.x / kWave;
+    for (int k = 1; k < nw; ++k) {
+      e += sh[0][k]; sdb += sh[1][k]; mdb = fmax(mdb, sh[2][k]); mb = fmax(mb, sh[3][k]);
+      sb += sh[4][k]; sdd += sh[5][k]; mdd = fmax(mdd, sh[6][k]); md = fmax(md, sh[7][k]);
+    }
+    double* o = out + static_cast<int64_t>(blockIdx.x) * kDiagVals;
+    o[0] = e; o[1] = sdb; o[2] = mdb; o[3] = mb; o[4] = sb; o[5] = sdd; o[6] = mdd; o[7] = md;
+  }
+}
+
+__global__ void qla_diag_final(double* __restrict__ parts, int count) {
+  // one wave; parts[count * kDiagVals ..] receives the folded values
+  double v[kDiagVals];
+  for (int j = 0; j < kDiagVals; ++j) v[j] = 0.0;   // sums and maxima of non-negative values
+  for (int k = threadIdx.x; k < count; k += blockDim.x) {
+    const double* o = parts + static_cast<int64_t>(k) * kDiagVals;
+    v[0] += o[0]; v[1] += o[1]; v[2] = fmax(v[2], o[2]); v[3] = fmax(v[3], o[3]);
+    v[4] += o[4]; v[5] += o[5]; v[6] = fmax(v[6], o[6]); v[7] = fmax(v[7], o[7]);
+  }
+  v[0] = wave_sum(v[0]); v[1] = wave_sum(v[1]); v[4] = wave_sum(v[4]); v[5] = wave_sum(v[5]);
+  v[2] = wave_max(v[2]); v[3] = wave_max(v[3]); v[6] = wave_max(v[6]); v[7] = wave_max(v[7]);
+  if (threadIdx.x == 0)
+    for (int j = 0; j < kDiagVals; ++j) parts[static_cast<int64_t>(count) * kDiagVals + j] = v[j];
+}
+
+// E_c = q_c / n_c for c < 3, B copied: (E, B) planes of Eq. (15).
+__global__ void __launch_bounds__(256) qla_fields_kernel(const float* __restrict__ q,
+                                                         const float* __restrict__ n, int64_t plane,
+                                                         float* __restrict__ out) {
+  for (int64_t s = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; s < plane;
+       s += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    for (int c = 0; c < 3; ++c) out[c * plane + s] = q[c * plane + s] / n[c * plane + s];
+    for (int c = 3; c < 6; ++c) out[c * plane + s] = q[c * plane + s];
+  }
+}
+
+}  // namespace
+
+// ===========================================================================
+// Host side: context, launch selection, C ABI.
+// ===========================================================================
+
+namespace {
+
+thread_local char g_last_error[512] = "";
+
+qla_status fail(qla_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+qla_status fail(qla_status st, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
+  va_end(ap);
+  return st;
+}
+
+constexpr uint64_t kMagic = 0x514c41435458ull;   // "QLACTX"
+
+using StepFn = void (*)(const StepArgs&, dim3, dim3, hipStream_t);
+
+template <int C, bool VEC, bool WIDE, int MODE, bool POT>
+void launch_step(const StepArgs& a, dim3 grid, dim3 block, hipStream_t st) {
+  hipLaunchKernelGGL((qla_step_kernel<C, VEC, WIDE, MODE, POT>), grid, block, 0, st, a);
+}
+
+template <int C, bool VEC>
+StepFn pick_step(bool wide, int mode, bool pot) {
+  if (wide) {
+    if (mode == QLA_POT_EQ28)
+      return pot ? launch_step<C, VEC, true, 1, true> : launch_step<C, VEC, true, 1, false>;
+    return pot ? launch_step<C, VEC, true, 0, true> : launch_step<C, VEC, true, 0, false>;
+  }
+  if (mode == QLA_POT_EQ28)
+    return pot ? launch_step<C, VEC, false, 1, true> : launch_step<C, VEC, false, 1, false>;
+  return pot ? launch_step<C, VEC, false, 0, true> : launch_step<C, VEC, false, 0, false>;
+}
+
+}  // namespace
+
+struct qla_ctx {
+  uint64_t magic;
+  qla_params p;
+  const float* n;
+  float* buf[2];
+  int cur;                 // index of the buffer holding the current state
+  void* work;
+  hipStream_t stream;
+  int64_t steps;
+  bool wide;
+  bool poisoned;
+  int cols;                // columns per lane of the step kernel
+  StepArgs args;
+  dim3 grid, block;
+  StepFn step;
+  double nmin, bmax;
+};
+
+namespace {
+
+size_t work_bytes() {
+  // diagnostics partials (+ one folded row) and scan partials
+  return static_cast<size_t>(kDiagBlocks + 1) * kDiagVals * sizeof(double) +
+         static_cast<size_t>(kDiagBlocks + 1) * sizeof(ScanPartial);
+}
+
+qla_status check_params(const qla_params* p) {
+  if (!p) return fail(QLA_EINVAL, "qla: null params");
+  if (p->nx < 1 || p->ny < 1) return fail(QLA_EINVAL, "qla: lattice %d x %d must be at least 1 x 1", p->nx, p->ny);
+  if (static_cast<int64_t>(p->nx) * p->ny > (int64_t{1} << 40))
+    return fail(QLA_EINVAL, "qla: lattice too large");
+  if (!(p->delta > 0.0) || !std::isfinite(p->delta)) return fail(QLA_EINVAL, "qla: delta must be finite and > 0");
+  if (p->pot_mode != QLA_POT_EQ23 && p->pot_mode != QLA_POT_EQ28)
+    return fail(QLA_EINVAL, "qla: pot_mode %d is not QLA_POT_EQ23 or QLA_POT_EQ28", p->pot_mode);
+  if (p->beta_scale < QLA_BETA_PHYS || p->beta_scale > QLA_BETA_OFF)
+    return fail(QLA_EINVAL, "qla: beta_scale %d unknown", p->beta_scale);
+  return QLA_OK;
+}
+
+qla_status hip_fail(qla_ctx* ctx, hipError_t e, const char* what) {
+  if (ctx) ctx->poisoned = true;
+  return fail(QLA_EDEVICE, "qla: %s: %s", what, hipGetErrorString(e));
+}
+
+qla_status check_ctx(qla_ctx* ctx) {
+  if (!ctx || ctx->magic != kMagic) return fail(QLA_ESTATE, "qla: invalid context");
+  if (ctx->poisoned) return fail(QLA_ESTATE, "qla: context unusable after an earlier device error");
+  return QLA_OK;
+}
+
+double kappa_of(const qla_params& p) {
+  if (p.beta_scale == QLA_BETA_PHYS) return p.delta;
+  if (p.beta_scale == QLA_BETA_LATTICE) return p.delta * p.delta;
+  return 0.0;
+}
+
+// Launch geometry of the step kernel: C = 2 columns per lane, segments sized
+// so that the grid holds a few waves per SIMD of the 256-CU part.
+void plan_step(qla_ctx* c) {
+  const int C = 2;
+  using K = Cols<2>;
+  const int nx = c->p.nx, ny = c->p.ny;
+  const int nstrips = (nx + K::kOut - 1) / K::kOut;
+  const int target_waves = 256 * 4 * 3;
+  int segs_wanted = (target_waves + nstrips - 1) / nstrips;
+  int seg_rows = (ny + segs_wanted - 1) / segs_wanted;
+  if (seg_rows < 16) seg_rows = 16;
+  seg_rows = (seg_rows + 3) & ~3;
+  const int nsegs = (ny + seg_rows - 1) / seg_rows;
+  const int wpb = 4;
+  const int nblocks = nstrips * ((nsegs + wpb - 1) / wpb);
+  c->cols = C;
+  c->args.plane = static_cast<int64_t>(nx) * ny;
+  c->args.nx = nx;
+  c->args.ny = ny;
+  c->args.seg_rows = seg_rows;
+  c->args.nstrips = nstrips;
+  c->args.nsegs = nsegs;
+  c->args.waves_per_block = wpb;
+  c->args.a4 = static_cast<float>(c->p.delta / 4.0);
+  const double frac = c->p.pot_mode == QLA_POT_EQ28 ? 0.5 : 1.0;
+  c->args.kb = static_cast<float>(kappa_of(c->p) * frac * 0.5);
+  c->grid = dim3(nblocks);
+  c->block = dim3(kWave * wpb);
+  const bool vec = (nx % C) == 0;
+  const bool pot = c->p.beta_scale != QLA_BETA_OFF;
+  c->step = vec ? pick_step<2, true>(c->wide, c->p.pot_mode, pot)
+                : pick_step<2, false>(c->wide, c->p.pot_mode, pot);
+}
+
+}  // namespace
+
+extern "C" {
+
+qla_status qla_workspace_size(const qla_params* p, size_t* bytes) {
+  qla_status st = check_params(p);
+  if (st != QLA_OK) return st;
+  if (!bytes) return fail(QLA_EINVAL, "qla: null bytes pointer");
+  *bytes = work_bytes();
+  return QLA_OK;
+}
+
+qla_status qla_init(const qla_params* p, const float* d_n, float* d_q, float* d_q_pong,
+                    void* d_work, void* hip_stream, qla_ctx** out) {
+  if (!out) return fail(QLA_EINVAL, "qla: null output pointer");
+  *out = nullptr;
+  qla_status st = check_params(p);
+  if (st != QLA_OK) return st;
+  if (!d_n || !d_q || !d_q_pong || !d_work)
+    return fail(QLA_EINVAL, "qla: null device buffer");
+  if (d_q == d_q_pong) return fail(QLA_EINVAL, "qla: the two state buffers must differ");
+  if ((reinterpret_cast<uintptr_t>(d_work) & 255) != 0)
+    return fail(QLA_EINVAL, "qla: workspace must be 256-byte aligned");
+  qla_ctx* c = new (std::nothrow) qla_ctx();
+  if (!c) return fail(QLA_ENOMEM, "qla: host allocation failed");
+  c->magic = kMagic;
+  c->p = *p;
+  c->n = d_n;
+  c->buf[0] = d_q;
+  c->buf[1] = d_q_pong;
+  c->cur = 0;
+  c->work = d_work;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  c->steps = 0;
+  c->poisoned = false;
+
+  // validate n and size the coefficient series
+  const double frac = p->pot_mode == QLA_POT_EQ28 ? 0.5 : 1.0;
+  const double kb = kappa_of(*p) * frac * 0.5;
+  const int64_t plane = static_cast<int64_t>(p->nx) * p->ny;
+  int blocks = static_cast<int>((plane + 255) / 256);
+  if (blocks > kDiagBlocks) blocks = kDiagBlocks;
+  ScanPartial* parts = reinterpret_cast<ScanPartial*>(
+      static_cast<char*>(d_work) + static_cast<size_t>(kDiagBlocks + 1) * kDiagVals * sizeof(double));
+  hipLaunchKernelGGL(qla_scan_kernel, dim3(blocks), dim3(256), 0, c->stream, d_n, p->nx, p->ny, kb, parts);
+  hipLaunchKernelGGL(qla_scan_final, dim3(1), dim3(kWave), 0, c->stream, parts, blocks);
+  ScanPartial res{};
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(&res, parts + blocks, sizeof(res), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    st = hip_fail(nullptr, e, "validating n");
+    delete c;
+    return st;
+  }
+  if (res.bad != 0.0) {
+    delete c;
+    return fail(QLA_EINVAL, "qla: every refractive index must be finite and > 0");
+  }
+  c->nmin = res.nmin;
+  c->bmax = res.bmax;
+  const double theta_max = p->delta / (4.0 * res.nmin);
+  c->wide = !(theta_max <= kNarrowAngle && res.bmax <= kNarrowAngle);
+  plan_step(c);
+  *out = c;
+  return QLA_OK;
+}
+
+qla_status qla_step(qla_ctx* ctx, int64_t nsteps) {
+  qla_status st = check_ctx(ctx);
+  if (st != QLA_OK) return st;
+  if (nsteps < 0) return fail(QLA_EINVAL, "qla: negative step count");
+  for (int64_t s = 0; s < nsteps; ++s) {
+    StepArgs a = ctx->args;
+    a.qin = ctx->buf[ctx->cur];
+    a.qout = ctx->buf[ctx->cur ^ 1];
+    a.n = ctx->n;
+    ctx->step(a, ctx->grid, ctx->block, ctx->stream);
+    ctx->cur ^= 1;
+    ++ctx->steps;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(ctx, e, "launching the step kernel");
+  return QLA_OK;
+}
+
+qla_status qla_energy(qla_ctx* ctx, qla_diag* out) {
+  qla_status st = check_ctx(ctx);
+  if (st != QLA_OK) return st;
+  if (!out) return fail(QLA_EINVAL, "qla: null diag pointer");
+  const int64_t plane = static_cast<int64_t>(ctx->p.nx) * ctx->p.ny;
+  int blocks = static_cast<int>((plane + 255) / 256);
+  if (blocks > kDiagBlocks) blocks = kDiagBlocks;
+  double* parts = static_cast<double*>(ctx->work);
+  hipLaunchKernelGGL(qla_diag_kernel, dim3(blocks), dim3(256), 0, ctx->stream, ctx->buf[ctx->cur],
+                     ctx->n, ctx->p.nx, ctx->p.ny, parts);
+  hipLaunchKernelGGL(qla_diag_final, dim3(1), dim3(kWave), 0, ctx->stream, parts, blocks);
+  double v[kDiagVals];
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(v, parts + static_cast<int64_t>(blocks) * kDiagVals, sizeof(v),
+                       hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "computing diagnostics");
+  out->step = ctx->steps;
+  out->energy = v[0] / static_cast<double>(plane);
+  out->divB_l2 = std::sqrt(v[1]);
+  out->divB_max = v[2];
+  out->B_max = std::sqrt(v[3]);
+  out->B_l2 = std::sqrt(v[4]);
+  out->divD_l2 = std::sqrt(v[5]);
+  out->divD_max = v[6];
+  out->D_max = std::sqrt(v[7]);
+  return QLA_OK;
+}
+
+qla_status qla_fields(qla_ctx* ctx, float* dst, int32_t what, int32_t dst_is_host) {
+  qla_status st = check_ctx(ctx);
+  if (st != QLA_OK) return st;
+  if (!dst) return fail(QLA_EINVAL, "qla: null destination");
+  if (what != 0 && what != 1) return fail(QLA_EINVAL, "qla: what must be 0 (Q) or 1 (E, B)");
+  const int64_t plane = static_cast<int64_t>(ctx->p.nx) * ctx->p.ny;
+  const size_t bytes = static_cast<size_t>(plane) * 6 * sizeof(float);
+  const float* src = ctx->buf[ctx->cur];
+  hipError_t e = hipSuccess;
+  if (what == 1) {
+    // (E, B) is written into the idle state buffer, then copied out
+    float* tmp = ctx->buf[ctx->cur ^ 1];
+    int blocks = static_cast<int>((plane + 255) / 256);
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(qla_fields_kernel, dim3(blocks), dim3(256), 0, ctx->stream, src, ctx->n, plane, tmp);
+    e = hipGetLastError();
+    src = tmp;
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dst, src, bytes, dst_is_host ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,
+                       ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "exporting fields");
+  return QLA_OK;
+}
+
+qla_status qla_state(qla_ctx* ctx, float** d_current) {
+  qla_status st = check_ctx(ctx);
+  if (st != QLA_OK) return st;
+  if (!d_current) return fail(QLA_EINVAL, "qla: null output pointer");
+  *d_current = ctx->buf[ctx->cur];
+  return QLA_OK;
+}
+
+void qla_free(qla_ctx* ctx) {
+  if (!ctx || ctx->magic != kMagic) return;
+  ctx->magic = 0;
+  delete ctx;
+}
+
+const char* qla_last_error(void) { return g_last_error; }
+
+}  // extern "C"

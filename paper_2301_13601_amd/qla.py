@@ -1,0 +1,191 @@
+"""Python binding of libqla (C ABI in include/qla.h).
+
+The functions here carry the C names and only marshal arguments: every
+step of the method runs in the HIP kernels of ``libqla.so``. PyTorch
+provides device memory and streams. If the library has not been built
+the import fails loudly; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqla.so")
+
+QLA_OK, QLA_EINVAL, QLA_ENOMEM, QLA_EDEVICE, QLA_ESTATE = 0, -1, -2, -3, -4
+POT_MODES = {"eq23": 0, "eq28": 1}
+BETA_SCALES = {"phys": 0, "lattice": 1, "off": 2}
+_STATUS = {0: "QLA_OK", -1: "QLA_EINVAL", -2: "QLA_ENOMEM", -3: "QLA_EDEVICE", -4: "QLA_ESTATE"}
+
+
+class QlaError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("delta", ctypes.c_double),
+                ("pot_mode", ctypes.c_int32), ("beta_scale", ctypes.c_int32)]
+
+
+class Diag(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_int64), ("energy", ctypes.c_double),
+                ("divB_max", ctypes.c_double), ("divB_l2", ctypes.c_double),
+                ("B_max", ctypes.c_double), ("B_l2", ctypes.c_double),
+                ("divD_max", ctypes.c_double), ("divD_l2", ctypes.c_double),
+                ("D_max", ctypes.c_double)]
+
+    def as_dict(self) -> Dict[str, float]:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+_lib = None
+
+# name -> (argtypes, restype); the exported surface of include/qla.h
+_SIGNATURES = {
+    "qla_workspace_size": ([ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "qla_init": ([ctypes.POINTER(Params), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                  ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
+    "qla_step": ([ctypes.c_void_p, ctypes.c_int64], ctypes.c_int),
+    "qla_energy": ([ctypes.c_void_p, ctypes.POINTER(Diag)], ctypes.c_int),
+    "qla_fields": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
+    "qla_state": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
+    "qla_free": ([ctypes.c_void_p], None),
+    "qla_last_error": ([], ctypes.c_char_p),
+}
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded libqla.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                              "or python -m paper_2301_13601_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (argtypes, restype) in _SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.argtypes = argtypes
+            fn.restype = restype
+        _lib = L
+    return _lib
+
+
+def _check(status: int) -> None:
+    if status != QLA_OK:
+        raise QlaError(status, qla_last_error())
+
+
+def make_params(nx: int, ny: int, delta: float, pot_mode: str = "eq28",
+                beta_scale: str = "phys") -> Params:
+    return Params(int(nx), int(ny), float(delta), POT_MODES[pot_mode], BETA_SCALES[beta_scale])
+
+
+# ---------------------------------------------------------------------------
+# The C entry points, one to one.
+# ---------------------------------------------------------------------------
+
+def qla_last_error() -> str:
+    msg = lib().qla_last_error()
+    return msg.decode() if msg else ""
+
+
+def qla_workspace_size(params: Params) -> int:
+    out = ctypes.c_size_t(0)
+    _check(lib().qla_workspace_size(ctypes.byref(params), ctypes.byref(out)))
+    return int(out.value)
+
+
+def qla_init(params: Params, d_n: int, d_q: int, d_q_pong: int, d_work: int,
+             stream: int) -> ctypes.c_void_p:
+    ctx = ctypes.c_void_p()
+    _check(lib().qla_init(ctypes.byref(params), ctypes.c_void_p(d_n), ctypes.c_void_p(d_q),
+                          ctypes.c_void_p(d_q_pong), ctypes.c_void_p(d_work),
+                          ctypes.c_void_p(stream), ctypes.byref(ctx)))
+    return ctx
+
+
+def qla_step(ctx, nsteps: int) -> None:
+    _check(lib().qla_step(ctx, int(nsteps)))
+
+
+def qla_energy(ctx) -> Dict[str, float]:
+    d = Diag()
+    _check(lib().qla_energy(ctx, ctypes.byref(d)))
+    return d.as_dict()
+
+
+def qla_fields(ctx, dst: int, what: int, dst_is_host: bool) -> None:
+    _check(lib().qla_fields(ctx, ctypes.c_void_p(dst), int(what), int(bool(dst_is_host))))
+
+
+def qla_state(ctx) -> int:
+    p = ctypes.c_void_p()
+    _check(lib().qla_state(ctx, ctypes.byref(p)))
+    return int(p.value)
+
+
+def qla_free(ctx) -> None:
+    lib().qla_free(ctx)
+
+
+# ---------------------------------------------------------------------------
+# Convenience owner of the device buffers (torch) around one context.
+# ---------------------------------------------------------------------------
+
+class Simulation:
+    """One lattice on one GPU: n, two state buffers and the workspace as torch
+    tensors, and the libqla context bound to them."""
+
+    def __init__(self, n, q0, delta: float, pot_mode: str = "eq28", beta_scale: str = "phys",
+                 device: str = "cuda:0", stream=None):
+        import torch
+
+        self._torch = torch
+        n_t = torch.as_tensor(np.ascontiguousarray(n, dtype=np.float32)) if isinstance(n, np.ndarray) else n
+        q_t = torch.as_tensor(np.ascontiguousarray(q0, dtype=np.float32)) if isinstance(q0, np.ndarray) else q0
+        if n_t.dim() != 3 or n_t.shape[0] != 3 or tuple(q_t.shape) != (6,) + tuple(n_t.shape[1:]):
+            raise ValueError("expected n of shape (3, ny, nx) and q0 of shape (6, ny, nx)")
+        self.ny, self.nx = int(n_t.shape[1]), int(n_t.shape[2])
+        self.device = torch.device(device)
+        self.n = n_t.to(self.device, torch.float32).contiguous()
+        self.q = q_t.to(self.device, torch.float32).contiguous().clone()
+        self.q_pong = torch.empty_like(self.q)
+        self.params = make_params(self.nx, self.ny, delta, pot_mode, beta_scale)
+        nbytes = qla_workspace_size(self.params)
+        self.work = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.ctx = qla_init(self.params, self.n.data_ptr(), self.q.data_ptr(), self.q_pong.data_ptr(),
+                            self.work.data_ptr(), self.stream.cuda_stream)
+
+    def step(self, nsteps: int) -> None:
+        qla_step(self.ctx, nsteps)
+
+    def diagnostics(self) -> Dict[str, float]:
+        return qla_energy(self.ctx)
+
+    def fields(self, what: str = "Q") -> np.ndarray:
+        out = np.empty((6, self.ny, self.nx), dtype=np.float32)
+        qla_fields(self.ctx, out.ctypes.data, {"Q": 0, "EB": 1}[what], True)
+        return out
+
+    def state_tensor(self):
+        """The device tensor that holds the current state (no copy)."""
+        ptr = qla_state(self.ctx)
+        return self.q if ptr == self.q.data_ptr() else self.q_pong
+
+    def close(self) -> None:
+        if self.ctx is not None:
+            qla_free(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

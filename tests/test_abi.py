@@ -1,0 +1,82 @@
+"""CPU-side checks of the C ABI: the library loads, exports every entry
+point include/qla.h declares, and rejects bad arguments before touching a
+device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "qla.h")
+
+
+@pytest.fixture(scope="module")
+def qla():
+    from paper_2301_13601_amd import qla as q
+    if not os.path.exists(q.LIB_PATH):
+        from paper_2301_13601_amd import build
+        build.build()
+    return q
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(qla_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_four_verbs():
+    names = declared_functions()
+    for verb in ("qla_init", "qla_step", "qla_energy", "qla_fields"):
+        assert verb in names
+
+
+def test_library_exports_every_declared_function(qla):
+    L = ctypes.CDLL(qla.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(L, name), name
+    # and the binding wraps each of them under the same name
+    for name in declared_functions():
+        assert hasattr(qla, name), name
+
+
+def test_rejects_bad_parameters_without_a_device(qla):
+    for args in [(0, 5, 0.3, "eq28"), (5, 0, 0.3, "eq28"), (4, 4, 0.0, "eq28"),
+                 (4, 4, float("nan"), "eq28"), (4, 4, -1.0, "eq23")]:
+        with pytest.raises(qla.QlaError) as ei:
+            qla.qla_workspace_size(qla.make_params(*args))
+        assert ei.value.status == qla.QLA_EINVAL
+        assert qla.qla_last_error()
+    bad_mode = qla.Params(4, 4, 0.3, 7, 0)
+    with pytest.raises(qla.QlaError):
+        qla.qla_workspace_size(bad_mode)
+    bad_scale = qla.Params(4, 4, 0.3, 1, 9)
+    with pytest.raises(qla.QlaError):
+        qla.qla_workspace_size(bad_scale)
+
+
+def test_workspace_size_is_positive(qla):
+    assert qla.qla_workspace_size(qla.make_params(256, 256, 0.3)) > 0
+
+
+def test_init_rejects_null_buffers(qla):
+    p = qla.make_params(8, 8, 0.3)
+    with pytest.raises(qla.QlaError) as ei:
+        qla.qla_init(p, 0, 0, 0, 0, 0)
+    assert ei.value.status == qla.QLA_EINVAL
+    with pytest.raises(qla.QlaError) as ei:
+        qla.qla_init(p, 256, 512, 512, 1024, 0)   # same state buffer twice
+    assert ei.value.status == qla.QLA_EINVAL
+    with pytest.raises(qla.QlaError) as ei:
+        qla.qla_init(p, 256, 512, 768, 1025, 0)   # misaligned workspace
+    assert ei.value.status == qla.QLA_EINVAL
+
+
+def test_calls_on_a_null_context_report_state_errors(qla):
+    L = qla.lib()
+    assert L.qla_step(None, 1) == qla.QLA_ESTATE
+    d = qla.Diag()
+    assert L.qla_energy(None, ctypes.byref(d)) == qla.QLA_ESTATE
+    assert L.qla_fields(None, None, 0, 1) == qla.QLA_ESTATE
+    L.qla_free(None)   # safe

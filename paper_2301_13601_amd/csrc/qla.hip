@@ -43,11 +43,12 @@ constexpr int kWave = 64;
 // Cross-lane moves (DPP whole-wave shifts by one lane; the lane with no
 // source receives 0, which only ever lands in halo lanes).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ float from_next_lane(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
+// bound_ctrl set: the lane without a source reads 0 (no old value needed)
+__device__ __forceinline__ float from_next_lane(float v) {   // wave_shl:1
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x130, 0xf, 0xf, true));
 }
-__device__ __forceinline__ float from_prev_lane(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+__device__ __forceinline__ float from_prev_lane(float v) {   // wave_shr:1
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x138, 0xf, 0xf, true));
 }
 
 // Streaming along x in pull form: S^{+x} sets v(x) = v(x + 1).
@@ -150,34 +151,57 @@ __device__ __forceinline__ int wrap_index(int64_t i, int n) {
   return static_cast<int>(r < 0 ? r + n : r);
 }
 
+// Loads and stores of one row of one plane go through a buffer resource
+// whose base is the row (wave-uniform, scalar registers) and whose extent is
+// the row's nx floats; the lane supplies a fixed byte offset. A lane that
+// must not store uses an offset past the extent, which the hardware drops.
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+constexpr int kRsrcWord3 = 0x00020000;        // raw 32-bit buffer, gfx9 family
+constexpr uint32_t kNoStore = 0x80000000u;    // beyond any row extent
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const float* row, int nx) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(row), 0, nx * 4, kRsrcWord3);
+}
+
 template <int C, bool VEC>
-__device__ __forceinline__ void load_row(const float* __restrict__ base, const int (&xk)[C],
+__device__ __forceinline__ void load_row(const float* row, int nx, const uint32_t (&xb)[C],
                                          float (&out)[C]) {
+  const __amdgpu_buffer_rsrc_t r = row_rsrc(row, nx);
   if constexpr (VEC && C == 4) {
-    const float4 v = *reinterpret_cast<const float4*>(base + xk[0]);
-    out[0] = v.x; out[1] = v.y; out[2] = v.z; out[3] = v.w;
+    const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, xb[0], 0, 0);
+    out[0] = __uint_as_float(v.x); out[1] = __uint_as_float(v.y);
+    out[2] = __uint_as_float(v.z); out[3] = __uint_as_float(v.w);
   } else if constexpr (VEC && C == 2) {
-    const float2 v = *reinterpret_cast<const float2*>(base + xk[0]);
-    out[0] = v.x; out[1] = v.y;
+    const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, xb[0], 0, 0);
+    out[0] = __uint_as_float(v.x); out[1] = __uint_as_float(v.y);
   } else {
 #pragma unroll
-    for (int k = 0; k < C; ++k) out[k] = base[xk[k]];
+    for (int k = 0; k < C; ++k) out[k] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, xb[k], 0, 0));
   }
 }
 
 template <int C, bool VEC>
-__device__ __forceinline__ void store_row(float* __restrict__ base, const int (&xk)[C],
-                                          const float (&v)[C], const bool (&ok)[C]) {
+__device__ __forceinline__ void store_row(float* row, int nx, const uint32_t (&sb)[C],
+                                          const float (&v)[C]) {
+  const __amdgpu_buffer_rsrc_t r = row_rsrc(row, nx);
   if constexpr (VEC && C == 4) {
-    if (ok[0]) *reinterpret_cast<float4*>(base + xk[0]) = make_float4(v[0], v[1], v[2], v[3]);
+    u32x4 w;
+    w.x = __float_as_uint(v[0]); w.y = __float_as_uint(v[1]);
+    w.z = __float_as_uint(v[2]); w.w = __float_as_uint(v[3]);
+    __builtin_amdgcn_raw_buffer_store_b128(w, r, sb[0], 0, 0);
   } else if constexpr (VEC && C == 2) {
-    if (ok[0]) *reinterpret_cast<float2*>(base + xk[0]) = make_float2(v[0], v[1]);
+    u32x2 w;
+    w.x = __float_as_uint(v[0]); w.y = __float_as_uint(v[1]);
+    __builtin_amdgcn_raw_buffer_store_b64(w, r, sb[0], 0, 0);
   } else {
 #pragma unroll
-    for (int k = 0; k < C; ++k)
-      if (ok[k]) base[xk[k]] = v[k];
+    for (int k = 0; k < C; ++k) __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v[k]), r, sb[k], 0, 0);
   }
 }
+
+// true on every lane if any lane's flag is set (a wave-uniform branch)
+__device__ __forceinline__ bool wave_any(bool v) { return __any(v) != 0; }
 
 // Everything a wave carries from one row iteration to the next.
 template <int C>
@@ -188,31 +212,43 @@ struct Pipe {
   // collision coefficients (tan(theta_0/2), sin theta_0, tan(theta_2/2),
   // sin theta_2) of the last four rows, slot = row mod 4
   float th[4][4][C];
-  // V_Y coefficients (sin b1, 1-cos b1, sin b3, 1-cos b3) per row slot
+  // V_Y coefficients (sin b1, 1-cos b1, sin b3, 1-cos b3) per row slot, and
+  // whether the row has any nonzero y-difference of n_x or n_z (when it
+  // has none, beta_1 = beta_3 = 0 and V_Y is exactly the identity)
   float vy[4][4][C];
-  // Eq. (23) only: V_X coefficients and the (q1, q4) pair per row slot,
-  // both applied after U_Y
+  bool fy[4];
+  // Eq. (23) only: V_X coefficients, their flag and the (q1, q4) pair per row
+  // slot, all applied after U_Y
   float vx[4][4][C];
+  bool fx[4];
   float q14[4][2][C];
-  // the ingested row R: Q, and n for rows R-1 (x, z), R, R+1
+  // the ingested row R and the rows in flight: Q of R and R+1, n of R-1
+  // (x and z components), R, R+1 and R+2
   float q[6][C];
+  float q1[6][C];
   float nprev[2][C];
   float ncur[3][C];
   float nnext[3][C];
+  float nn2[3][C];
+};
+
+struct RowBases {
+  const float* qld;    // Q row R+2 (plane 0)
+  const float* nld;    // n row R+3 (plane 0)
 };
 
 // MODE: 0 = Eq. (23), 1 = Eq. (28). POT: potentials present (kappa != 0).
 template <int C, bool VEC, bool WIDE, int MODE, bool POT, int SLOT>
-__device__ __forceinline__ void row_iteration(Pipe<C>& p, const StepArgs& g, const int (&xk)[C],
-                                              const bool (&lane_out)[C], int i, int seg_h,
-                                              int y0, int64_t off_q_next, int64_t off_n_next2) {
-  // ---- prefetch Q of row R+1 and n of row R+2 -----------------------------
-  float qn[6][C];
-  float nn2[3][C];
+__device__ __forceinline__ void row_iteration(Pipe<C>& p, const StepArgs& g, const uint32_t (&xo)[C],
+                                              const uint32_t (&so)[C], bool edge_lane, int i,
+                                              int seg_h, int y0, const RowBases& rb) {
+  // ---- prefetch Q of row R+2 and n of row R+3 ------------------------------
+  float qld[6][C];
+  float nld[3][C];
 #pragma unroll
-  for (int c = 0; c < 6; ++c) load_row<C, VEC>(g.qin + c * g.plane + off_q_next, xk, qn[c]);
+  for (int c = 0; c < 6; ++c) load_row<C, VEC>(rb.qld + c * g.plane, g.nx, xo, qld[c]);
 #pragma unroll
-  for (int c = 0; c < 3; ++c) load_row<C, VEC>(g.n + c * g.plane + off_n_next2, xk, nn2[c]);
+  for (int c = 0; c < 3; ++c) load_row<C, VEC>(rb.nld + c * g.plane, g.nx, xo, nld[c]);
 
   // ---- coefficients of row R (Eq. (24), (25)) -----------------------------
   float u[3][C];
@@ -232,23 +268,42 @@ __device__ __forceinline__ void row_iteration(Pipe<C>& p, const StepArgs& g, con
     p.th[SLOT][2][k] = tc[2][k];
     p.th[SLOT][3][k] = sc[2][k];
   }
-  // V_X coefficients from the x-differences of n_y (beta_0) and n_z (beta_2)
+  // V_X coefficients from the x-differences of n_y (beta_0) and n_z (beta_2).
+  // Lanes 0 and 63 see a zero from the DPP shift at the wave edge; their
+  // values only reach halo columns, so they do not vote.
   float vxs0[C], vxh0[C], vxs2[C], vxh2[C];
+  bool fx = false;
   if constexpr (POT) {
-    float nyr[C], nyl[C], nzr[C], nzl[C];
+    float dny[C], dnz[C];
+    {
+      float r1[C], l1[C], r2[C], l2[C];
 #pragma unroll
-    for (int k = 0; k < C; ++k) {
-      nyr[k] = p.ncur[1][k]; nyl[k] = p.ncur[1][k];
-      nzr[k] = p.ncur[2][k]; nzl[k] = p.ncur[2][k];
+      for (int k = 0; k < C; ++k) {
+        r1[k] = l1[k] = p.ncur[1][k];
+        r2[k] = l2[k] = p.ncur[2][k];
+      }
+      pull_from_right<C>(r1); pull_from_left<C>(l1);
+      pull_from_right<C>(r2); pull_from_left<C>(l2);
+      bool nz = false;
+#pragma unroll
+      for (int k = 0; k < C; ++k) {
+        dny[k] = r1[k] - l1[k];
+        dnz[k] = r2[k] - l2[k];
+        nz = nz || dny[k] != 0.0f || dnz[k] != 0.0f;
+      }
+      fx = wave_any(nz && !edge_lane);
     }
-    pull_from_right<C>(nyr); pull_from_left<C>(nyl);
-    pull_from_right<C>(nzr); pull_from_left<C>(nzl);
+    if (fx) {
 #pragma unroll
-    for (int k = 0; k < C; ++k) {
-      const float b0 = g.kb * (nyr[k] - nyl[k]) * (u[1][k] * u[1][k]);
-      const float b2 = g.kb * (nzr[k] - nzl[k]) * (u[2][k] * u[2][k]);
-      pot_coef<WIDE>(b0, vxs0[k], vxh0[k]);
-      pot_coef<WIDE>(b2, vxs2[k], vxh2[k]);
+      for (int k = 0; k < C; ++k) {
+        const float b0 = g.kb * dny[k] * (u[1][k] * u[1][k]);
+        const float b2 = g.kb * dnz[k] * (u[2][k] * u[2][k]);
+        pot_coef<WIDE>(b0, vxs0[k], vxh0[k]);
+        pot_coef<WIDE>(b2, vxs2[k], vxh2[k]);
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < C; ++k) vxs0[k] = vxh0[k] = vxs2[k] = vxh2[k] = 0.0f;
     }
   }
 
@@ -269,10 +324,12 @@ __device__ __forceinline__ void row_iteration(Pipe<C>& p, const StepArgs& g, con
   using P_ = std::integral_constant<int, 1>;
   using M_ = std::integral_constant<int, -1>;
   auto vx_apply = [&]() {
+    if (fx) {
 #pragma unroll
-    for (int k = 0; k < C; ++k) {
-      q[4][k] = pot_row(q[4][k], -q[2][k], vxs2[k], vxh2[k]);
-      q[5][k] = pot_row(q[5][k], q[1][k], vxs0[k], vxh0[k]);
+      for (int k = 0; k < C; ++k) {
+        q[4][k] = pot_row(q[4][k], -q[2][k], vxs2[k], vxh2[k]);
+        q[5][k] = pot_row(q[5][k], q[1][k], vxs0[k], vxh0[k]);
+      }
     }
   };
   cx(M_{}); pull_from_left<C>(q[1]);  pull_from_left<C>(q[4]);
@@ -291,9 +348,9 @@ __device__ __forceinline__ void row_iteration(Pipe<C>& p, const StepArgs& g, con
   if constexpr (MODE == 1) {
     // q1 and q4 are final once U_X and V_X' are done: U_Y and V_Y leave them
     if (R_rel >= 0 && R_rel < seg_h) {
-      const int64_t off = static_cast<int64_t>(y0 + R_rel) * g.nx;
-      store_row<C, VEC>(g.qout + 1 * g.plane + off, xk, q[1], lane_out);
-      store_row<C, VEC>(g.qout + 4 * g.plane + off, xk, q[4], lane_out);
+      float* row = g.qout + static_cast<int64_t>(y0 + R_rel) * g.nx;
+      store_row<C, VEC>(row + 1 * g.plane, g.nx, so, q[1]);
+      store_row<C, VEC>(row + 4 * g.plane, g.nx, so, q[4]);
     }
   }
 
@@ -323,10 +380,12 @@ __device__ __forceinline__ void row_iteration(Pipe<C>& p, const StepArgs& g, con
   };
   auto vy_apply = [&](auto lag) {
     constexpr int sl = (SLOT - decltype(lag)::value) & 3;
+    if (p.fy[sl]) {
 #pragma unroll
-    for (int k = 0; k < C; ++k) {
-      b3[k] = pot_row(b3[k], b2[k], p.vy[sl][2][k], p.vy[sl][3][k]);
-      a5[k] = pot_row(a5[k], -a0[k], p.vy[sl][0][k], p.vy[sl][1][k]);
+      for (int k = 0; k < C; ++k) {
+        b3[k] = pot_row(b3[k], b2[k], p.vy[sl][2][k], p.vy[sl][3][k]);
+        a5[k] = pot_row(a5[k], -a0[k], p.vy[sl][0][k], p.vy[sl][1][k]);
+      }
     }
   };
   using L0 = std::integral_constant<int, 0>;
@@ -365,34 +424,42 @@ __device__ __forceinline__ void row_iteration(Pipe<C>& p, const StepArgs& g, con
     for (int k = 0; k < C; ++k) {
       o1[k] = p.q14[sl][0][k];
       o4[k] = p.q14[sl][1][k];
-      if constexpr (POT) {
-        o4[k] = pot_row(o4[k], -b2[k], p.vx[sl][2][k], p.vx[sl][3][k]);
-        a5[k] = pot_row(a5[k], o1[k], p.vx[sl][0][k], p.vx[sl][1][k]);
-      }
     }
-    if constexpr (POT) vy_apply(L4{});
+    if constexpr (POT) {
+      if (p.fx[sl]) {
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
+          o4[k] = pot_row(o4[k], -b2[k], p.vx[sl][2][k], p.vx[sl][3][k]);
+          a5[k] = pot_row(a5[k], o1[k], p.vx[sl][0][k], p.vx[sl][1][k]);
+        }
+      }
+      vy_apply(L4{});
+    }
   }
   if (O_rel >= 0 && O_rel < seg_h) {
-    const int64_t off = static_cast<int64_t>(y0 + O_rel) * g.nx;
-    store_row<C, VEC>(g.qout + 0 * g.plane + off, xk, a0, lane_out);
-    store_row<C, VEC>(g.qout + 2 * g.plane + off, xk, b2, lane_out);
-    store_row<C, VEC>(g.qout + 3 * g.plane + off, xk, b3, lane_out);
-    store_row<C, VEC>(g.qout + 5 * g.plane + off, xk, a5, lane_out);
+    float* row = g.qout + static_cast<int64_t>(y0 + O_rel) * g.nx;
+    store_row<C, VEC>(row + 0 * g.plane, g.nx, so, a0);
+    store_row<C, VEC>(row + 2 * g.plane, g.nx, so, b2);
+    store_row<C, VEC>(row + 3 * g.plane, g.nx, so, b3);
+    store_row<C, VEC>(row + 5 * g.plane, g.nx, so, a5);
     if constexpr (MODE == 0) {
-      store_row<C, VEC>(g.qout + 1 * g.plane + off, xk, o1, lane_out);
-      store_row<C, VEC>(g.qout + 4 * g.plane + off, xk, o4, lane_out);
+      store_row<C, VEC>(row + 1 * g.plane, g.nx, so, o1);
+      store_row<C, VEC>(row + 4 * g.plane, g.nx, so, o4);
     }
   }
 
-  // ---- per-row data kept for later rows --------------------------------
+  // ---- per-row data kept for later rows (slot R mod 4 was last read above,
+  // as row R-4) --------------------------------------------------------------
   if constexpr (MODE == 0) {
 #pragma unroll
     for (int k = 0; k < C; ++k) {
-      // q1, q4 of row R after U_X (the pipeline above consumed slot R-4)
-      // are written back into the same slot; see the note on slot reuse.
       p.q14[SLOT][0][k] = p.q[1][k];
       p.q14[SLOT][1][k] = p.q[4][k];
-      if constexpr (POT) {
+    }
+    if constexpr (POT) {
+      p.fx[SLOT] = fx;
+#pragma unroll
+      for (int k = 0; k < C; ++k) {
         p.vx[SLOT][0][k] = vxs0[k];
         p.vx[SLOT][1][k] = vxh0[k];
         p.vx[SLOT][2][k] = vxs2[k];
@@ -402,13 +469,25 @@ __device__ __forceinline__ void row_iteration(Pipe<C>& p, const StepArgs& g, con
   }
   if constexpr (POT) {
     // V_Y coefficients of row R from the y-differences of n_x (beta_1) and
-    // n_z (beta_3); slot R mod 4 was last read above (as row R-4)
+    // n_z (beta_3)
+    float d1[C], d3[C];
+    bool nz = false;
 #pragma unroll
     for (int k = 0; k < C; ++k) {
-      const float b1 = g.kb * (p.nnext[0][k] - p.nprev[0][k]) * (u[0][k] * u[0][k]);
-      const float b3c = g.kb * (p.nnext[2][k] - p.nprev[1][k]) * (u[2][k] * u[2][k]);
-      pot_coef<WIDE>(b1, p.vy[SLOT][0][k], p.vy[SLOT][1][k]);
-      pot_coef<WIDE>(b3c, p.vy[SLOT][2][k], p.vy[SLOT][3][k]);
+      d1[k] = p.nnext[0][k] - p.nprev[0][k];
+      d3[k] = p.nnext[2][k] - p.nprev[1][k];
+      nz = nz || d1[k] != 0.0f || d3[k] != 0.0f;
+    }
+    const bool fy = wave_any(nz);
+    p.fy[SLOT] = fy;
+    if (fy) {
+#pragma unroll
+      for (int k = 0; k < C; ++k) {
+        const float b1 = g.kb * d1[k] * (u[0][k] * u[0][k]);
+        const float b3c = g.kb * d3[k] * (u[2][k] * u[2][k]);
+        pot_coef<WIDE>(b1, p.vy[SLOT][0][k], p.vy[SLOT][1][k]);
+        pot_coef<WIDE>(b3c, p.vy[SLOT][2][k], p.vy[SLOT][3][k]);
+      }
     }
   }
   // advance the row window
@@ -419,17 +498,22 @@ __device__ __forceinline__ void row_iteration(Pipe<C>& p, const StepArgs& g, con
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       p.ncur[c][k] = p.nnext[c][k];
-      p.nnext[c][k] = nn2[c][k];
+      p.nnext[c][k] = p.nn2[c][k];
+      p.nn2[c][k] = nld[c][k];
     }
 #pragma unroll
-    for (int c = 0; c < 6; ++c) p.q[c][k] = qn[c][k];
+    for (int c = 0; c < 6; ++c) {
+      p.q[c][k] = p.q1[c][k];
+      p.q1[c][k] = qld[c][k];
+    }
   }
 }
 
 template <int C, bool VEC, bool WIDE, int MODE, bool POT>
 __global__ void __launch_bounds__(256) qla_step_kernel(StepArgs g) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int wave = threadIdx.x / kWave;
+  // wave index within the block, as a wave-uniform (scalar) value
+  const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x / kWave));
   // blocks are dealt round-robin to the 8 XCDs; regroup them so that each
   // XCD gets a contiguous band of the lattice (neighbouring strips share
   // halo columns through that XCD's L2)
@@ -448,13 +532,20 @@ __global__ void __launch_bounds__(256) qla_step_kernel(StepArgs g) {
   const int seg_h = min(g.seg_rows, g.ny - y0);
   const int x0 = strip * Cols<C>::kOut;
   const int64_t col0 = static_cast<int64_t>(x0) - Cols<C>::kHaloLanes * C + lane * C;
-  int xk[C];
-  bool ok[C];
+  // byte offsets of the lane's columns within a row: loads wrap
+  // periodically, stores only for output columns of this strip
+  uint32_t xo[C], so[C];
   const bool lane_in = lane >= Cols<C>::kHaloLanes && lane < kWave - Cols<C>::kHaloLanes;
+  const bool edge_lane = lane == 0 || lane == kWave - 1;
 #pragma unroll
   for (int k = 0; k < C; ++k) {
-    xk[k] = wrap_index(col0 + k, g.nx);
-    ok[k] = lane_in && (col0 + k < g.nx);
+    xo[k] = 4u * static_cast<uint32_t>(wrap_index(col0 + k, g.nx));
+    so[k] = (lane_in && col0 + k < g.nx) ? xo[k] : kNoStore;
+  }
+  if constexpr (VEC) {
+    // the lane's C columns are stored together or not at all
+#pragma unroll
+    for (int k = 1; k < C; ++k) so[k] = so[0];
   }
 
   Pipe<C> p;
@@ -465,7 +556,9 @@ __global__ void __launch_bounds__(256) qla_step_kernel(StepArgs g) {
 #pragma unroll
       for (int k = 0; k < C; ++k) p.d[s][c][k] = 0.0f;
 #pragma unroll
-  for (int s = 0; s < 4; ++s)
+  for (int s = 0; s < 4; ++s) {
+    p.fy[s] = false;
+    p.fx[s] = false;
 #pragma unroll
     for (int c = 0; c < 4; ++c)
 #pragma unroll
@@ -475,36 +568,42 @@ __global__ void __launch_bounds__(256) qla_step_kernel(StepArgs g) {
         p.vx[s][c][k] = 0.0f;
       }
 #pragma unroll
-  for (int s = 0; s < 4; ++s)
-#pragma unroll
     for (int k = 0; k < C; ++k) p.q14[s][0][k] = p.q14[s][1][k] = 0.0f;
+  }
 
-  // prologue: Q of row y0-4, n of rows y0-5 .. y0-3
+  // prologue: Q of rows y0-4, y0-3 and n of rows y0-5 .. y0-2
   const int64_t R0 = static_cast<int64_t>(y0) - 4;
   const int64_t nx64 = g.nx;
   {
-    const int64_t oq = wrap_index(R0, g.ny) * nx64;
-    const int64_t om = wrap_index(R0 - 1, g.ny) * nx64;
-    const int64_t on = wrap_index(R0 + 1, g.ny) * nx64;
+    const float* q0r = g.qin + wrap_index(R0, g.ny) * nx64;
+    const float* q1r = g.qin + wrap_index(R0 + 1, g.ny) * nx64;
+    const float* nm = g.n + wrap_index(R0 - 1, g.ny) * nx64;
+    const float* n0 = g.n + wrap_index(R0, g.ny) * nx64;
+    const float* n1 = g.n + wrap_index(R0 + 1, g.ny) * nx64;
+    const float* n2 = g.n + wrap_index(R0 + 2, g.ny) * nx64;
 #pragma unroll
-    for (int c = 0; c < 6; ++c) load_row<C, VEC>(g.qin + c * g.plane + oq, xk, p.q[c]);
+    for (int c = 0; c < 6; ++c) {
+      load_row<C, VEC>(q0r + c * g.plane, g.nx, xo, p.q[c]);
+      load_row<C, VEC>(q1r + c * g.plane, g.nx, xo, p.q1[c]);
+    }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      load_row<C, VEC>(g.n + c * g.plane + oq, xk, p.ncur[c]);
-      load_row<C, VEC>(g.n + c * g.plane + on, xk, p.nnext[c]);
+      load_row<C, VEC>(n0 + c * g.plane, g.nx, xo, p.ncur[c]);
+      load_row<C, VEC>(n1 + c * g.plane, g.nx, xo, p.nnext[c]);
+      load_row<C, VEC>(n2 + c * g.plane, g.nx, xo, p.nn2[c]);
     }
-    load_row<C, VEC>(g.n + 0 * g.plane + om, xk, p.nprev[0]);
-    load_row<C, VEC>(g.n + 2 * g.plane + om, xk, p.nprev[1]);
+    load_row<C, VEC>(nm + 0 * g.plane, g.nx, xo, p.nprev[0]);
+    load_row<C, VEC>(nm + 2 * g.plane, g.nx, xo, p.nprev[1]);
   }
-  // row R+1 for Q prefetch and R+2 for n prefetch, wrapped incrementally
-  int rq = wrap_index(R0 + 1, g.ny);
-  int rn = wrap_index(R0 + 2, g.ny);
+  // rows in flight: Q of R+2, n of R+3 (wrapped incrementally)
+  int rq = wrap_index(R0 + 2, g.ny);
+  int rn = wrap_index(R0 + 3, g.ny);
   const int iters = ((seg_h + 8) + 3) & ~3;
   for (int i = 0; i < iters; i += 4) {
 #define QLA_ITER(S)                                                                            \
   {                                                                                            \
-    row_iteration<C, VEC, WIDE, MODE, POT, S>(p, g, xk, ok, i + S, seg_h, y0, rq * nx64,       \
-                                              rn * nx64);                                      \
+    const RowBases rb{g.qin + rq * nx64, g.n + rn * nx64};                                     \
+    row_iteration<C, VEC, WIDE, MODE, POT, S>(p, g, xo, so, edge_lane, i + S, seg_h, y0, rb);  \
     rq = (rq + 1 == g.ny) ? 0 : rq + 1;                                                        \
     rn = (rn + 1 == g.ny) ? 0 : rn + 1;                                                        \
   }
@@ -792,20 +891,22 @@ double kappa_of(const qla_params& p) {
   return 0.0;
 }
 
-// Launch geometry of the step kernel: C = 2 columns per lane, segments sized
-// so that the grid holds a few waves per SIMD of the 256-CU part.
-void plan_step(qla_ctx* c) {
+// Launch geometry of the step kernel: C = 2 columns per lane; the lattice is
+// cut into strips (x) and segments (y) so that the whole grid is resident at
+// once (two waves per SIMD: one round, no tail), with segments as tall as
+// that allows (each segment re-reads 8 halo rows).
+void plan_step(qla_ctx* c, int cus, int waves_per_simd, int wpb) {
   const int C = 2;
   using K = Cols<2>;
   const int nx = c->p.nx, ny = c->p.ny;
   const int nstrips = (nx + K::kOut - 1) / K::kOut;
-  const int target_waves = 256 * 4 * 3;
-  int segs_wanted = (target_waves + nstrips - 1) / nstrips;
-  int seg_rows = (ny + segs_wanted - 1) / segs_wanted;
-  if (seg_rows < 16) seg_rows = 16;
+  const int slots = cus * 4 * waves_per_simd;            // resident waves
+  int block_rows = (slots / wpb) / nstrips;
+  if (block_rows < 1) block_rows = 1;
+  int seg_rows = (ny + block_rows * wpb - 1) / (block_rows * wpb);
+  if (seg_rows < 8) seg_rows = 8;
   seg_rows = (seg_rows + 3) & ~3;
   const int nsegs = (ny + seg_rows - 1) / seg_rows;
-  const int wpb = 4;
   const int nblocks = nstrips * ((nsegs + wpb - 1) / wpb);
   c->cols = C;
   c->args.plane = static_cast<int64_t>(nx) * ny;
@@ -889,7 +990,14 @@ qla_status qla_init(const qla_params* p, const float* d_n, float* d_q, float* d_
   c->bmax = res.bmax;
   const double theta_max = p->delta / (4.0 * res.nmin);
   c->wide = !(theta_max <= kNarrowAngle && res.bmax <= kNarrowAngle);
-  plan_step(c);
+  int dev = 0, cus = 0;
+  e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess || cus < 1) {
+    delete c;
+    return hip_fail(nullptr, e == hipSuccess ? hipErrorInvalidDevice : e, "querying the device");
+  }
+  plan_step(c, cus, 2, 1);
   *out = c;
   return QLA_OK;
 }

@@ -53,6 +53,36 @@ def measured_traffic():
     return rec.get("bytes_per_launch")
 
 
+def summarize_counters(fetch_csv: str, write_csv: str, copy_mib: int, out_path: str) -> dict:
+    """Turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per
+    dispatch) of this script into HBM bytes per step-kernel launch, scaled by
+    what the same counters read for the plain device copy of copy_mib MiB the
+    runs include (--calib-copy-mib)."""
+    import csv
+
+    def rows(path):
+        with open(path) as f:
+            return list(csv.DictReader(f))
+
+    copy_bytes = copy_mib * (1 << 20)
+    out = {"kernel_source_sha256_16": kernel_source_hash(), "copy_bytes": copy_bytes}
+    for tag, path in (("fetch", fetch_csv), ("write", write_csv)):
+        rs = rows(path)
+        step = [float(r["Counter_Value"]) for r in rs if "qla_step_kernel" in r["Kernel_Name"]]
+        # the calibration copy is the largest copy dispatch of the run
+        copies = [float(r["Counter_Value"]) for r in rs if "copyBuffer" in r["Kernel_Name"]
+                  or "copy" in r["Kernel_Name"].lower()]
+        cal = max(copies) * 1024.0
+        factor = copy_bytes / cal
+        out[tag] = {"kib_per_launch_raw": sum(step) / len(step), "launches": len(step),
+                    "copy_kib_raw": cal / 1024.0, "scale": factor,
+                    "bytes_per_launch": sum(step) / len(step) * 1024.0 * factor}
+    out["bytes_per_launch"] = out["fetch"]["bytes_per_launch"] + out["write"]["bytes_per_launch"]
+    with open(out_path, "w") as f:
+        json.dump(out, f, indent=1)
+    return out
+
+
 def make_workload(name: str, steps: int):
     from paper_2301_13601_amd import scenes
     if name == "cylinder_4096":
@@ -102,7 +132,14 @@ def main():
     ap.add_argument("--cpu-sample-n", type=int, default=4096)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one device copy of this many MiB (counter calibration)")
+    ap.add_argument("--counters", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_MIB"),
+                    help="summarise rocprofv3 counter CSVs into the committed traffic record and exit")
     args = ap.parse_args()
+
+    if args.counters:
+        rec = summarize_counters(args.counters[0], args.counters[1], int(args.counters[2]), TRAFFIC_FILE)
+        print(json.dumps(rec))
+        return
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "

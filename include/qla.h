@@ -84,6 +84,18 @@ typedef struct {
 
 typedef struct qla_ctx qla_ctx;   /* opaque */
 
+/* Launch geometry of the fused step kernel (a tuning knob, not part of the
+ * method). A wave owns 64*cols lattice columns and a segment of seg_rows rows.
+ * A field set to 0 asks for the library's default.
+ *   seg_rows         rows per wave segment, rounded up to a multiple of 4
+ *   waves_per_block  1..4 waves (vertically adjacent segments) per block
+ *   cols             lattice columns per lane: 2 or 4 */
+typedef struct {
+    int32_t seg_rows;
+    int32_t waves_per_block;
+    int32_t cols;
+} qla_launch;
+
 /* Bytes of device workspace qla_init needs for these parameters. */
 qla_status qla_workspace_size(const qla_params *p, size_t *bytes);
 
@@ -112,6 +124,14 @@ qla_status qla_energy(qla_ctx *ctx, qla_diag *out);
  *   dst_is_host = 1: dst is host memory; 0: device memory
  * Synchronises the stream. */
 qla_status qla_fields(qla_ctx *ctx, float *dst, int32_t what, int32_t dst_is_host);
+
+/* The launch geometry in use (never 0 fields). */
+qla_status qla_get_launch(qla_ctx *ctx, qla_launch *out);
+
+/* Request a launch geometry for later qla_step calls (0 fields: default).
+ * QLA_EINVAL if a field is out of range, in which case the previous geometry
+ * stays. Results are bitwise identical for every geometry. */
+qla_status qla_set_launch(qla_ctx *ctx, const qla_launch *req);
 
 /* Device pointer of the buffer holding the current state (d_q or d_q_pong). */
 qla_status qla_state(qla_ctx *ctx, float **d_current);

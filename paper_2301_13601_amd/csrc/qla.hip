@@ -203,14 +203,17 @@ __device__ __forceinline__ void store_row(float* row, int nx, const uint32_t (&s
 // true on every lane if any lane's flag is set (a wave-uniform branch)
 __device__ __forceinline__ bool wave_any(bool v) { return __any(v) != 0; }
 
-// Everything a wave carries from one row iteration to the next.
+// Everything a wave carries from one row iteration to the next. The wave
+// marches through its segment in direction DIR (+1: increasing y, -1:
+// decreasing y); "row R" is the row ingested this iteration and "lag k" the
+// row ingested k iterations ago (R - k*DIR).
 template <int C>
 struct Pipe {
-  // y-sweep stream stages (ops 2,4,6,8,10,12,14,16 of Eq. (20) in the
-  // order they act): one-row delay registers for two components each
+  // y-sweep stream stages (the 8 S^{+-y} of Eq. (20) in the order they act):
+  // one-row delay registers for two components each
   float d[8][2][C];
   // collision coefficients (tan(theta_0/2), sin theta_0, tan(theta_2/2),
-  // sin theta_2) of the last four rows, slot = row mod 4
+  // sin theta_2) of rows lag 1..4, slot = iteration mod 4
   float th[4][4][C];
   // V_Y coefficients (sin b1, 1-cos b1, sin b3, 1-cos b3) per row slot, and
   // whether the row has any nonzero y-difference of n_x or n_z (when it
@@ -222,8 +225,8 @@ struct Pipe {
   float vx[4][4][C];
   bool fx[4];
   float q14[4][2][C];
-  // the ingested row R and the rows in flight: Q of R and R+1, n of R-1
-  // (x and z components), R, R+1 and R+2
+  // the ingested row R and the rows in flight: Q of R and R+DIR, n of R-DIR
+  // (x and z components), R, R+DIR and R+2*DIR
   float q[6][C];
   float q1[6][C];
   float nprev[2][C];
@@ -233,16 +236,31 @@ struct Pipe {
 };
 
 struct RowBases {
-  const float* qld;    // Q row R+2 (plane 0)
-  const float* nld;    // n row R+3 (plane 0)
+  const float* qld;    // Q row R+2*DIR (plane 0)
+  const float* nld;    // n row R+3*DIR (plane 0)
+};
+
+// Lag (in rows) of the y-pipeline after each of its 8 stream stages. A stage
+// that pulls from the row ahead in marching order (S^{+y} when marching in
+// +y, S^{-y} when marching in -y) has to wait one more row.
+template <int DIR>
+struct YLags {
+  // stream stages in acting order: S-03 S+03 S+25 S-25 S+03 S-03 S-25 S+25
+  static constexpr int sgn[8] = {-1, +1, +1, -1, +1, -1, -1, +1};
+  static constexpr int after(int k) {
+    int l = 0;
+    for (int j = 0; j <= k; ++j) l += (sgn[j] == DIR) ? 1 : 0;
+    return l;
+  }
+  static constexpr int before(int k) { return k == 0 ? 0 : after(k - 1); }
 };
 
 // MODE: 0 = Eq. (23), 1 = Eq. (28). POT: potentials present (kappa != 0).
-template <int C, bool VEC, bool WIDE, int MODE, bool POT, int SLOT>
+template <int C, bool VEC, bool WIDE, int MODE, bool POT, int DIR, int SLOT>
 __device__ __forceinline__ void row_iteration(Pipe<C>& p, const StepArgs& g, const uint32_t (&xo)[C],
                                               const uint32_t (&so)[C], bool edge_lane, int i,
                                               int seg_h, int y0, const RowBases& rb) {
-  // ---- prefetch Q of row R+2 and n of row R+3 ------------------------------
+  // ---- prefetch Q of row R+2*DIR and n of row R+3*DIR ---------------------
   float qld[6][C];
   float nld[3][C];
 #pragma unroll
@@ -260,13 +278,6 @@ __device__ __forceinline__ void row_iteration(Pipe<C>& p, const StepArgs& g, con
       u[c][k] = __builtin_amdgcn_rcpf(p.ncur[c][k]);
       rot_coef<WIDE>(g.a4 * u[c][k], tc[c][k], sc[c][k]);
     }
-  }
-#pragma unroll
-  for (int k = 0; k < C; ++k) {
-    p.th[SLOT][0][k] = tc[0][k];
-    p.th[SLOT][1][k] = sc[0][k];
-    p.th[SLOT][2][k] = tc[2][k];
-    p.th[SLOT][3][k] = sc[2][k];
   }
   // V_X coefficients from the x-differences of n_y (beta_0) and n_z (beta_2).
   // Lanes 0 and 63 see a zero from the DPP shift at the wave edge; their
@@ -343,11 +354,15 @@ __device__ __forceinline__ void row_iteration(Pipe<C>& p, const StepArgs& g, con
   cx(M_{}); pull_from_right<C>(q[2]); pull_from_right<C>(q[5]);
   if constexpr (MODE == 1 && POT) vx_apply();
 
-  const int R_rel = i - 4;     // row R relative to y0
-  const int O_rel = i - 8;     // row R-4 relative to y0
+  // rows of this iteration relative to y0: R, and R - 4*DIR which leaves
+  // the pipeline; both lie in the segment for the same range of i
+  const int R_rel = DIR > 0 ? i - 4 : seg_h + 3 - i;
+  const int O_rel = DIR > 0 ? i - 8 : seg_h + 7 - i;
+  const bool R_out = i >= 4 && i < seg_h + 4;
+  const bool O_out = i >= 8 && i < seg_h + 8;
   if constexpr (MODE == 1) {
     // q1 and q4 are final once U_X and V_X' are done: U_Y and V_Y leave them
-    if (R_rel >= 0 && R_rel < seg_h) {
+    if (R_out) {
       float* row = g.qout + static_cast<int64_t>(y0 + R_rel) * g.nx;
       store_row<C, VEC>(row + 1 * g.plane, g.nx, so, q[1]);
       store_row<C, VEC>(row + 4 * g.plane, g.nx, so, q[4]);
@@ -361,13 +376,25 @@ __device__ __forceinline__ void row_iteration(Pipe<C>& p, const StepArgs& g, con
   float (&a5)[C] = q[5];
   float (&b2)[C] = q[2];
   float (&b3)[C] = q[3];
-  auto cy = [&](auto sgn, auto lag) {
+  using Lg = YLags<DIR>;
+  // collision k (0..7) acts on the row at lag Lg::before(k); lag 0 is the
+  // row just computed above, older rows come from the ring
+  auto cy = [&](auto sgn, auto kk) {
     constexpr int S = decltype(sgn)::value;
-    constexpr int sl = (SLOT - decltype(lag)::value) & 3;
+    constexpr int lag = Lg::before(decltype(kk)::value);
+    if constexpr (lag == 0) {
 #pragma unroll
-    for (int k = 0; k < C; ++k) {
-      rot<-S>(a0[k], a5[k], p.th[sl][0][k], p.th[sl][1][k]);
-      rot<-S>(b2[k], b3[k], p.th[sl][2][k], p.th[sl][3][k]);
+      for (int k = 0; k < C; ++k) {
+        rot<-S>(a0[k], a5[k], tc[0][k], sc[0][k]);
+        rot<-S>(b2[k], b3[k], tc[2][k], sc[2][k]);
+      }
+    } else {
+      constexpr int sl = (SLOT - lag) & 3;
+#pragma unroll
+      for (int k = 0; k < C; ++k) {
+        rot<-S>(a0[k], a5[k], p.th[sl][0][k], p.th[sl][1][k]);
+        rot<-S>(b2[k], b3[k], p.th[sl][2][k], p.th[sl][3][k]);
+      }
     }
   };
   auto swap_in = [&](float (&cur)[C], float (&dly)[C]) {
@@ -376,6 +403,19 @@ __device__ __forceinline__ void row_iteration(Pipe<C>& p, const StepArgs& g, con
       const float t = cur[k];
       cur[k] = dly[k];
       dly[k] = t;
+    }
+  };
+  // stream stage k shifting (sa, sb) and leaving (ka, kb) of the active four
+  auto sy = [&](auto kk, float (&sa)[C], float (&sb)[C], float (&ka)[C], float (&kb)[C]) {
+    constexpr int k = decltype(kk)::value;
+    if constexpr (Lg::sgn[k] == DIR) {
+      // pulls from the row ahead: the other two wait one row
+      swap_in(ka, p.d[k][0]);
+      swap_in(kb, p.d[k][1]);
+    } else {
+      // pulls from the row behind: the shifted two come from the delay line
+      swap_in(sa, p.d[k][0]);
+      swap_in(sb, p.d[k][1]);
     }
   };
   auto vy_apply = [&](auto lag) {
@@ -388,37 +428,31 @@ __device__ __forceinline__ void row_iteration(Pipe<C>& p, const StepArgs& g, con
       }
     }
   };
-  using L0 = std::integral_constant<int, 0>;
-  using L1 = std::integral_constant<int, 1>;
-  using L2 = std::integral_constant<int, 2>;
-  using L3 = std::integral_constant<int, 3>;
-  using L4 = std::integral_constant<int, 4>;
-  // Operators in the order they act; a stage streaming from y-1 swaps its
-  // two shifted components with the delay line, a stage streaming from y+1
-  // swaps the two it leaves in place (and adds one row of lag).
-  cy(M_{}, L0{});                                   // C_Y^dagger
-  swap_in(a0, p.d[0][0]); swap_in(b3, p.d[0][1]);   // S^{-y}_{03}
-  cy(P_{}, L0{});                                   // C_Y
-  swap_in(a5, p.d[1][0]); swap_in(b2, p.d[1][1]);   // S^{+y}_{03}
-  cy(M_{}, L1{});                                   // C_Y^dagger
-  swap_in(a0, p.d[2][0]); swap_in(b3, p.d[2][1]);   // S^{+y}_{25}
-  cy(P_{}, L2{});                                   // C_Y
-  swap_in(b2, p.d[3][0]); swap_in(a5, p.d[3][1]);   // S^{-y}_{25}
-  if constexpr (MODE == 1 && POT) vy_apply(L2{});   // V_Y' (Eq. (28))
-  cy(P_{}, L2{});                                   // C_Y
-  swap_in(a5, p.d[4][0]); swap_in(b2, p.d[4][1]);   // S^{+y}_{03}
-  cy(M_{}, L3{});                                   // C_Y^dagger
-  swap_in(a0, p.d[5][0]); swap_in(b3, p.d[5][1]);   // S^{-y}_{03}
-  cy(P_{}, L3{});                                   // C_Y
-  swap_in(b2, p.d[6][0]); swap_in(a5, p.d[6][1]);   // S^{-y}_{25}
-  cy(M_{}, L3{});                                   // C_Y^dagger
-  swap_in(a0, p.d[7][0]); swap_in(b3, p.d[7][1]);   // S^{+y}_{25}
-  // the pipeline now holds row R-4
+  using K0 = std::integral_constant<int, 0>;
+  using K1 = std::integral_constant<int, 1>;
+  using K2 = std::integral_constant<int, 2>;
+  using K3 = std::integral_constant<int, 3>;
+  using K4 = std::integral_constant<int, 4>;
+  using K5 = std::integral_constant<int, 5>;
+  using K6 = std::integral_constant<int, 6>;
+  using K7 = std::integral_constant<int, 7>;
+  static_assert(Lg::after(3) == 2 && Lg::after(7) == 4, "V_Y' acts at lags 2 and 4");
+  // Eq. (20), right to left
+  cy(M_{}, K0{});  sy(K0{}, a0, b3, a5, b2);      // C_Y^dagger, S^{-y}_{03}
+  cy(P_{}, K1{});  sy(K1{}, a0, b3, a5, b2);      // C_Y,        S^{+y}_{03}
+  cy(M_{}, K2{});  sy(K2{}, b2, a5, a0, b3);      // C_Y^dagger, S^{+y}_{25}
+  cy(P_{}, K3{});  sy(K3{}, b2, a5, a0, b3);      // C_Y,        S^{-y}_{25}
+  if constexpr (MODE == 1 && POT) vy_apply(std::integral_constant<int, 2>{});   // V_Y' (Eq. (28))
+  cy(P_{}, K4{});  sy(K4{}, a0, b3, a5, b2);      // C_Y,        S^{+y}_{03}
+  cy(M_{}, K5{});  sy(K5{}, a0, b3, a5, b2);      // C_Y^dagger, S^{-y}_{03}
+  cy(P_{}, K6{});  sy(K6{}, b2, a5, a0, b3);      // C_Y,        S^{-y}_{25}
+  cy(M_{}, K7{});  sy(K7{}, b2, a5, a0, b3);      // C_Y^dagger, S^{+y}_{25}
+  // the pipeline now holds the row at lag 4
   float o1[C], o4[C];
   if constexpr (MODE == 1) {
-    if constexpr (POT) vy_apply(L4{});              // V_Y' (Eq. (28))
+    if constexpr (POT) vy_apply(std::integral_constant<int, 4>{});   // V_Y' (Eq. (28))
   } else {
-    // Eq. (23): V_X then V_Y after U_Y, on row R-4
+    // Eq. (23): V_X then V_Y after U_Y, on the row at lag 4
     constexpr int sl = (SLOT - 4) & 3;
 #pragma unroll
     for (int k = 0; k < C; ++k) {
@@ -433,10 +467,10 @@ __device__ __forceinline__ void row_iteration(Pipe<C>& p, const StepArgs& g, con
           a5[k] = pot_row(a5[k], o1[k], p.vx[sl][0][k], p.vx[sl][1][k]);
         }
       }
-      vy_apply(L4{});
+      vy_apply(std::integral_constant<int, 4>{});
     }
   }
-  if (O_rel >= 0 && O_rel < seg_h) {
+  if (O_out) {
     float* row = g.qout + static_cast<int64_t>(y0 + O_rel) * g.nx;
     store_row<C, VEC>(row + 0 * g.plane, g.nx, so, a0);
     store_row<C, VEC>(row + 2 * g.plane, g.nx, so, b2);
@@ -448,8 +482,15 @@ __device__ __forceinline__ void row_iteration(Pipe<C>& p, const StepArgs& g, con
     }
   }
 
-  // ---- per-row data kept for later rows (slot R mod 4 was last read above,
-  // as row R-4) --------------------------------------------------------------
+  // ---- per-row data kept for later rows (slot SLOT held the row at lag 4,
+  // consumed above) ------------------------------------------------------------
+#pragma unroll
+  for (int k = 0; k < C; ++k) {
+    p.th[SLOT][0][k] = tc[0][k];
+    p.th[SLOT][1][k] = sc[0][k];
+    p.th[SLOT][2][k] = tc[2][k];
+    p.th[SLOT][3][k] = sc[2][k];
+  }
   if constexpr (MODE == 0) {
 #pragma unroll
     for (int k = 0; k < C; ++k) {
@@ -468,14 +509,19 @@ __device__ __forceinline__ void row_iteration(Pipe<C>& p, const StepArgs& g, con
     }
   }
   if constexpr (POT) {
-    // V_Y coefficients of row R from the y-differences of n_x (beta_1) and
-    // n_z (beta_3)
+    // V_Y coefficients of row R from the y-differences n(R+1) - n(R-1) of
+    // n_x (beta_1) and n_z (beta_3)
     float d1[C], d3[C];
     bool nz = false;
 #pragma unroll
     for (int k = 0; k < C; ++k) {
-      d1[k] = p.nnext[0][k] - p.nprev[0][k];
-      d3[k] = p.nnext[2][k] - p.nprev[1][k];
+      if constexpr (DIR > 0) {
+        d1[k] = p.nnext[0][k] - p.nprev[0][k];
+        d3[k] = p.nnext[2][k] - p.nprev[1][k];
+      } else {
+        d1[k] = p.nprev[0][k] - p.nnext[0][k];
+        d3[k] = p.nprev[1][k] - p.nnext[2][k];
+      }
       nz = nz || d1[k] != 0.0f || d3[k] != 0.0f;
     }
     const bool fy = wave_any(nz);
@@ -509,14 +555,91 @@ __device__ __forceinline__ void row_iteration(Pipe<C>& p, const StepArgs& g, con
   }
 }
 
+// One wave's march over its segment in direction DIR.
+template <int C, bool VEC, bool WIDE, int MODE, bool POT, int DIR>
+__device__ __forceinline__ void march(const StepArgs& g, const uint32_t (&xo)[C],
+                                      const uint32_t (&so)[C], bool edge_lane, int y0, int seg_h) {
+  Pipe<C> p;
+#pragma unroll
+  for (int s = 0; s < 8; ++s)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int k = 0; k < C; ++k) p.d[s][c][k] = 0.0f;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    p.fy[s] = false;
+    p.fx[s] = false;
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int k = 0; k < C; ++k) {
+        p.th[s][c][k] = 0.0f;
+        p.vy[s][c][k] = 0.0f;
+        p.vx[s][c][k] = 0.0f;
+      }
+#pragma unroll
+    for (int k = 0; k < C; ++k) p.q14[s][0][k] = p.q14[s][1][k] = 0.0f;
+  }
+
+  // first ingested row: 4 rows before the segment in marching order
+  const int64_t R0 = DIR > 0 ? static_cast<int64_t>(y0) - 4 : static_cast<int64_t>(y0) + seg_h + 3;
+  const int64_t nx64 = g.nx;
+  {
+    const float* q0r = g.qin + wrap_index(R0, g.ny) * nx64;
+    const float* q1r = g.qin + wrap_index(R0 + DIR, g.ny) * nx64;
+    const float* nm = g.n + wrap_index(R0 - DIR, g.ny) * nx64;
+    const float* n0 = g.n + wrap_index(R0, g.ny) * nx64;
+    const float* n1 = g.n + wrap_index(R0 + DIR, g.ny) * nx64;
+    const float* n2 = g.n + wrap_index(R0 + 2 * DIR, g.ny) * nx64;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      load_row<C, VEC>(q0r + c * g.plane, g.nx, xo, p.q[c]);
+      load_row<C, VEC>(q1r + c * g.plane, g.nx, xo, p.q1[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      load_row<C, VEC>(n0 + c * g.plane, g.nx, xo, p.ncur[c]);
+      load_row<C, VEC>(n1 + c * g.plane, g.nx, xo, p.nnext[c]);
+      load_row<C, VEC>(n2 + c * g.plane, g.nx, xo, p.nn2[c]);
+    }
+    load_row<C, VEC>(nm + 0 * g.plane, g.nx, xo, p.nprev[0]);
+    load_row<C, VEC>(nm + 2 * g.plane, g.nx, xo, p.nprev[1]);
+  }
+  // rows in flight: Q of R+2*DIR, n of R+3*DIR (wrapped incrementally)
+  int rq = wrap_index(R0 + 2 * DIR, g.ny);
+  int rn = wrap_index(R0 + 3 * DIR, g.ny);
+  const int iters = ((seg_h + 8) + 3) & ~3;
+  for (int i = 0; i < iters; i += 4) {
+#define QLA_ITER(S)                                                                            \
+  {                                                                                            \
+    const RowBases rb{g.qin + rq * nx64, g.n + rn * nx64};                                     \
+    row_iteration<C, VEC, WIDE, MODE, POT, DIR, S>(p, g, xo, so, edge_lane, i + S, seg_h, y0,  \
+                                                   rb);                                        \
+    if constexpr (DIR > 0) {                                                                   \
+      rq = (rq + 1 == g.ny) ? 0 : rq + 1;                                                      \
+      rn = (rn + 1 == g.ny) ? 0 : rn + 1;                                                      \
+    } else {                                                                                   \
+      rq = (rq == 0) ? g.ny - 1 : rq - 1;                                                      \
+      rn = (rn == 0) ? g.ny - 1 : rn - 1;                                                      \
+    }                                                                                          \
+  }
+    QLA_ITER(0)
+    QLA_ITER(1)
+    QLA_ITER(2)
+    QLA_ITER(3)
+#undef QLA_ITER
+  }
+}
+
 template <int C, bool VEC, bool WIDE, int MODE, bool POT>
 __global__ void __launch_bounds__(256) qla_step_kernel(StepArgs g) {
   const int lane = threadIdx.x & (kWave - 1);
   // wave index within the block, as a wave-uniform (scalar) value
   const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x / kWave));
   // blocks are dealt round-robin to the 8 XCDs; regroup them so that each
-  // XCD gets a contiguous band of the lattice (neighbouring strips share
-  // halo columns through that XCD's L2)
+  // XCD gets a contiguous band of the lattice (neighbouring strips and
+  // segments share halo data through that XCD's L2)
   const int nblk = gridDim.x;
   const int b = blockIdx.x;
   const int per = nblk / 8;
@@ -547,72 +670,14 @@ __global__ void __launch_bounds__(256) qla_step_kernel(StepArgs g) {
 #pragma unroll
     for (int k = 1; k < C; ++k) so[k] = so[0];
   }
-
-  Pipe<C> p;
-#pragma unroll
-  for (int s = 0; s < 8; ++s)
-#pragma unroll
-    for (int c = 0; c < 2; ++c)
-#pragma unroll
-      for (int k = 0; k < C; ++k) p.d[s][c][k] = 0.0f;
-#pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    p.fy[s] = false;
-    p.fx[s] = false;
-#pragma unroll
-    for (int c = 0; c < 4; ++c)
-#pragma unroll
-      for (int k = 0; k < C; ++k) {
-        p.th[s][c][k] = 0.0f;
-        p.vy[s][c][k] = 0.0f;
-        p.vx[s][c][k] = 0.0f;
-      }
-#pragma unroll
-    for (int k = 0; k < C; ++k) p.q14[s][0][k] = p.q14[s][1][k] = 0.0f;
-  }
-
-  // prologue: Q of rows y0-4, y0-3 and n of rows y0-5 .. y0-2
-  const int64_t R0 = static_cast<int64_t>(y0) - 4;
-  const int64_t nx64 = g.nx;
-  {
-    const float* q0r = g.qin + wrap_index(R0, g.ny) * nx64;
-    const float* q1r = g.qin + wrap_index(R0 + 1, g.ny) * nx64;
-    const float* nm = g.n + wrap_index(R0 - 1, g.ny) * nx64;
-    const float* n0 = g.n + wrap_index(R0, g.ny) * nx64;
-    const float* n1 = g.n + wrap_index(R0 + 1, g.ny) * nx64;
-    const float* n2 = g.n + wrap_index(R0 + 2, g.ny) * nx64;
-#pragma unroll
-    for (int c = 0; c < 6; ++c) {
-      load_row<C, VEC>(q0r + c * g.plane, g.nx, xo, p.q[c]);
-      load_row<C, VEC>(q1r + c * g.plane, g.nx, xo, p.q1[c]);
-    }
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      load_row<C, VEC>(n0 + c * g.plane, g.nx, xo, p.ncur[c]);
-      load_row<C, VEC>(n1 + c * g.plane, g.nx, xo, p.nnext[c]);
-      load_row<C, VEC>(n2 + c * g.plane, g.nx, xo, p.nn2[c]);
-    }
-    load_row<C, VEC>(nm + 0 * g.plane, g.nx, xo, p.nprev[0]);
-    load_row<C, VEC>(nm + 2 * g.plane, g.nx, xo, p.nprev[1]);
-  }
-  // rows in flight: Q of R+2, n of R+3 (wrapped incrementally)
-  int rq = wrap_index(R0 + 2, g.ny);
-  int rn = wrap_index(R0 + 3, g.ny);
-  const int iters = ((seg_h + 8) + 3) & ~3;
-  for (int i = 0; i < iters; i += 4) {
-#define QLA_ITER(S)                                                                            \
-  {                                                                                            \
-    const RowBases rb{g.qin + rq * nx64, g.n + rn * nx64};                                     \
-    row_iteration<C, VEC, WIDE, MODE, POT, S>(p, g, xo, so, edge_lane, i + S, seg_h, y0, rb);  \
-    rq = (rq + 1 == g.ny) ? 0 : rq + 1;                                                        \
-    rn = (rn + 1 == g.ny) ? 0 : rn + 1;                                                        \
-  }
-    QLA_ITER(0)
-    QLA_ITER(1)
-    QLA_ITER(2)
-    QLA_ITER(3)
-#undef QLA_ITER
-  }
+  // Neighbouring segments march in opposite directions, so that the 8 halo
+  // rows two segments share are read by both at about the same time (at
+  // the start of both marches or at the end of both) and come from L2 for
+  // the second reader.
+  if (seg & 1)
+    march<C, VEC, WIDE, MODE, POT, +1>(g, xo, so, edge_lane, y0, seg_h);
+  else
+    march<C, VEC, WIDE, MODE, POT, -1>(g, xo, so, edge_lane, y0, seg_h);
 }
 
 // ---------------------------------------------------------------------------
@@ -814,23 +879,44 @@ qla_status fail(qla_status st, const char* fmt, ...) {
 
 constexpr uint64_t kMagic = 0x514c41435458ull;   // "QLACTX"
 
-using StepFn = void (*)(const StepArgs&, dim3, dim3, hipStream_t);
+// One compiled instance of the step kernel: how to launch it and how many
+// of its blocks fit on a CU.
+struct StepImpl {
+  void (*launch)(const StepArgs&, dim3, dim3, hipStream_t);
+  hipError_t (*blocks_per_cu)(int* nb, int threads);
+  int cols;
+};
 
 template <int C, bool VEC, bool WIDE, int MODE, bool POT>
 void launch_step(const StepArgs& a, dim3 grid, dim3 block, hipStream_t st) {
   hipLaunchKernelGGL((qla_step_kernel<C, VEC, WIDE, MODE, POT>), grid, block, 0, st, a);
 }
 
+template <int C, bool VEC, bool WIDE, int MODE, bool POT>
+hipError_t step_blocks_per_cu(int* nb, int threads) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, qla_step_kernel<C, VEC, WIDE, MODE, POT>,
+                                                      threads, 0);
+}
+
+template <int C, bool VEC, bool WIDE, int MODE, bool POT>
+StepImpl impl() {
+  return StepImpl{launch_step<C, VEC, WIDE, MODE, POT>, step_blocks_per_cu<C, VEC, WIDE, MODE, POT>, C};
+}
+
 template <int C, bool VEC>
-StepFn pick_step(bool wide, int mode, bool pot) {
+StepImpl pick_step_c(bool wide, int mode, bool pot) {
   if (wide) {
-    if (mode == QLA_POT_EQ28)
-      return pot ? launch_step<C, VEC, true, 1, true> : launch_step<C, VEC, true, 1, false>;
-    return pot ? launch_step<C, VEC, true, 0, true> : launch_step<C, VEC, true, 0, false>;
+    if (mode == QLA_POT_EQ28) return pot ? impl<C, VEC, true, 1, true>() : impl<C, VEC, true, 1, false>();
+    return pot ? impl<C, VEC, true, 0, true>() : impl<C, VEC, true, 0, false>();
   }
-  if (mode == QLA_POT_EQ28)
-    return pot ? launch_step<C, VEC, false, 1, true> : launch_step<C, VEC, false, 1, false>;
-  return pot ? launch_step<C, VEC, false, 0, true> : launch_step<C, VEC, false, 0, false>;
+  if (mode == QLA_POT_EQ28) return pot ? impl<C, VEC, false, 1, true>() : impl<C, VEC, false, 1, false>();
+  return pot ? impl<C, VEC, false, 0, true>() : impl<C, VEC, false, 0, false>();
+}
+
+StepImpl pick_step(int cols, bool vec, bool wide, int mode, bool pot) {
+  if (cols == 4)
+    return vec ? pick_step_c<4, true>(wide, mode, pot) : pick_step_c<4, false>(wide, mode, pot);
+  return vec ? pick_step_c<2, true>(wide, mode, pot) : pick_step_c<2, false>(wide, mode, pot);
 }
 
 }  // namespace
@@ -846,10 +932,12 @@ struct qla_ctx {
   int64_t steps;
   bool wide;
   bool poisoned;
-  int cols;                // columns per lane of the step kernel
+  int cus;                 // compute units of the device
+  qla_launch launch;       // requested geometry (0 fields: library default)
+  qla_launch planned;      // geometry in use
   StepArgs args;
   dim3 grid, block;
-  StepFn step;
+  StepImpl step;
   double nmin, bmax;
 };
 
@@ -891,24 +979,39 @@ double kappa_of(const qla_params& p) {
   return 0.0;
 }
 
-// Launch geometry of the step kernel: C = 2 columns per lane; the lattice is
-// cut into strips (x) and segments (y) so that the whole grid is resident at
-// once (two waves per SIMD: one round, no tail), with segments as tall as
-// that allows (each segment re-reads 8 halo rows).
-void plan_step(qla_ctx* c, int cus, int waves_per_simd, int wpb) {
-  const int C = 2;
-  using K = Cols<2>;
+// Launch geometry of the step kernel. A wave covers 64*C columns (C = 2 by
+// default) of which (64 - 2*ceil(4/C))*C are output; the lattice is cut into
+// strips (x) and segments (y) so that the whole grid is resident at once
+// (one round, no tail), with segments as tall as that allows (each segment
+// re-reads 8 halo rows). Requested fields of ctx->launch override the
+// defaults.
+qla_status plan_step(qla_ctx* c) {
   const int nx = c->p.nx, ny = c->p.ny;
-  const int nstrips = (nx + K::kOut - 1) / K::kOut;
-  const int slots = cus * 4 * waves_per_simd;            // resident waves
-  int block_rows = (slots / wpb) / nstrips;
-  if (block_rows < 1) block_rows = 1;
-  int seg_rows = (ny + block_rows * wpb - 1) / (block_rows * wpb);
-  if (seg_rows < 8) seg_rows = 8;
+  int C = c->launch.cols > 0 ? c->launch.cols : 2;
+  if (C != 2 && C != 4) return fail(QLA_EINVAL, "qla: cols must be 2 or 4");
+  const int wpb = c->launch.waves_per_block > 0 ? c->launch.waves_per_block : 1;
+  if (wpb > 4) return fail(QLA_EINVAL, "qla: waves_per_block must be 1..4");
+  const bool vec = (nx % C) == 0;
+  const bool pot = c->p.beta_scale != QLA_BETA_OFF;
+  c->step = pick_step(C, vec, c->wide, c->p.pot_mode, pot);
+  const int halo = (4 + C - 1) / C;
+  const int out_cols = (kWave - 2 * halo) * C;
+  const int nstrips = (nx + out_cols - 1) / out_cols;
+  int seg_rows = c->launch.seg_rows;
+  if (seg_rows <= 0) {
+    int bpc = 0;
+    hipError_t e = c->step.blocks_per_cu(&bpc, kWave * wpb);
+    if (e != hipSuccess || bpc < 1) bpc = 1;
+    const int slots = c->cus * bpc;                      // resident blocks
+    int block_rows = slots / nstrips;
+    if (block_rows < 1) block_rows = 1;
+    seg_rows = (ny + block_rows * wpb - 1) / (block_rows * wpb);
+    if (seg_rows < 8) seg_rows = 8;
+  }
   seg_rows = (seg_rows + 3) & ~3;
   const int nsegs = (ny + seg_rows - 1) / seg_rows;
-  const int nblocks = nstrips * ((nsegs + wpb - 1) / wpb);
-  c->cols = C;
+  const int64_t nblocks64 = static_cast<int64_t>(nstrips) * ((nsegs + wpb - 1) / wpb);
+  if (nblocks64 > (int64_t{1} << 30)) return fail(QLA_EINVAL, "qla: launch geometry too large");
   c->args.plane = static_cast<int64_t>(nx) * ny;
   c->args.nx = nx;
   c->args.ny = ny;
@@ -919,12 +1022,10 @@ void plan_step(qla_ctx* c, int cus, int waves_per_simd, int wpb) {
   c->args.a4 = static_cast<float>(c->p.delta / 4.0);
   const double frac = c->p.pot_mode == QLA_POT_EQ28 ? 0.5 : 1.0;
   c->args.kb = static_cast<float>(kappa_of(c->p) * frac * 0.5);
-  c->grid = dim3(nblocks);
+  c->grid = dim3(static_cast<unsigned>(nblocks64));
   c->block = dim3(kWave * wpb);
-  const bool vec = (nx % C) == 0;
-  const bool pot = c->p.beta_scale != QLA_BETA_OFF;
-  c->step = vec ? pick_step<2, true>(c->wide, c->p.pot_mode, pot)
-                : pick_step<2, false>(c->wide, c->p.pot_mode, pot);
+  c->planned = qla_launch{seg_rows, wpb, C};
+  return QLA_OK;
 }
 
 }  // namespace
@@ -997,7 +1098,13 @@ qla_status qla_init(const qla_params* p, const float* d_n, float* d_q, float* d_
     delete c;
     return hip_fail(nullptr, e == hipSuccess ? hipErrorInvalidDevice : e, "querying the device");
   }
-  plan_step(c, cus, 2, 1);
+  c->cus = cus;
+  c->launch = qla_launch{0, 0, 0};
+  st = plan_step(c);
+  if (st != QLA_OK) {
+    delete c;
+    return st;
+  }
   *out = c;
   return QLA_OK;
 }
@@ -1011,7 +1118,7 @@ qla_status qla_step(qla_ctx* ctx, int64_t nsteps) {
     a.qin = ctx->buf[ctx->cur];
     a.qout = ctx->buf[ctx->cur ^ 1];
     a.n = ctx->n;
-    ctx->step(a, ctx->grid, ctx->block, ctx->stream);
+    ctx->step.launch(a, ctx->grid, ctx->block, ctx->stream);
     ctx->cur ^= 1;
     ++ctx->steps;
   }
@@ -1074,6 +1181,31 @@ qla_status qla_fields(qla_ctx* ctx, float* dst, int32_t what, int32_t dst_is_hos
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "exporting fields");
   return QLA_OK;
+}
+
+qla_status qla_get_launch(qla_ctx* ctx, qla_launch* out) {
+  qla_status st = check_ctx(ctx);
+  if (st != QLA_OK) return st;
+  if (!out) return fail(QLA_EINVAL, "qla: null launch pointer");
+  *out = ctx->planned;
+  return QLA_OK;
+}
+
+qla_status qla_set_launch(qla_ctx* ctx, const qla_launch* req) {
+  qla_status st = check_ctx(ctx);
+  if (st != QLA_OK) return st;
+  if (!req) return fail(QLA_EINVAL, "qla: null launch pointer");
+  if (req->seg_rows < 0 || req->waves_per_block < 0 || req->waves_per_block > 4 ||
+      (req->cols != 0 && req->cols != 2 && req->cols != 4))
+    return fail(QLA_EINVAL, "qla: launch fields out of range");
+  const qla_launch keep = ctx->launch;
+  ctx->launch = *req;
+  st = plan_step(ctx);
+  if (st != QLA_OK) {
+    ctx->launch = keep;
+    plan_step(ctx);
+  }
+  return st;
 }
 
 qla_status qla_state(qla_ctx* ctx, float** d_current) {

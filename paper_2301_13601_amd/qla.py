@@ -44,6 +44,14 @@ class Diag(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class Launch(ctypes.Structure):
+    _fields_ = [("seg_rows", ctypes.c_int32), ("waves_per_block", ctypes.c_int32),
+                ("cols", ctypes.c_int32)]
+
+    def as_dict(self) -> Dict[str, int]:
+        return {name: int(getattr(self, name)) for name, _ in self._fields_}
+
+
 _lib = None
 
 # name -> (argtypes, restype); the exported surface of include/qla.h
@@ -54,6 +62,8 @@ _SIGNATURES = {
     "qla_step": ([ctypes.c_void_p, ctypes.c_int64], ctypes.c_int),
     "qla_energy": ([ctypes.c_void_p, ctypes.POINTER(Diag)], ctypes.c_int),
     "qla_fields": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
+    "qla_get_launch": ([ctypes.c_void_p, ctypes.POINTER(Launch)], ctypes.c_int),
+    "qla_set_launch": ([ctypes.c_void_p, ctypes.POINTER(Launch)], ctypes.c_int),
     "qla_state": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
     "qla_free": ([ctypes.c_void_p], None),
     "qla_last_error": ([], ctypes.c_char_p),
@@ -124,6 +134,17 @@ def qla_fields(ctx, dst: int, what: int, dst_is_host: bool) -> None:
     _check(lib().qla_fields(ctx, ctypes.c_void_p(dst), int(what), int(bool(dst_is_host))))
 
 
+def qla_get_launch(ctx) -> Dict[str, int]:
+    out = Launch()
+    _check(lib().qla_get_launch(ctx, ctypes.byref(out)))
+    return out.as_dict()
+
+
+def qla_set_launch(ctx, seg_rows: int = 0, waves_per_block: int = 0, cols: int = 0) -> None:
+    req = Launch(int(seg_rows), int(waves_per_block), int(cols))
+    _check(lib().qla_set_launch(ctx, ctypes.byref(req)))
+
+
 def qla_state(ctx) -> int:
     p = ctypes.c_void_p()
     _check(lib().qla_state(ctx, ctypes.byref(p)))
@@ -173,6 +194,12 @@ class Simulation:
         out = np.empty((6, self.ny, self.nx), dtype=np.float32)
         qla_fields(self.ctx, out.ctypes.data, {"Q": 0, "EB": 1}[what], True)
         return out
+
+    def launch(self) -> Dict[str, int]:
+        return qla_get_launch(self.ctx)
+
+    def set_launch(self, seg_rows: int = 0, waves_per_block: int = 0, cols: int = 0) -> None:
+        qla_set_launch(self.ctx, seg_rows, waves_per_block, cols)
 
     def state_tensor(self):
         """The device tensor that holds the current state (no copy)."""

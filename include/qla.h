@@ -11,7 +11,8 @@
  * U_Y (Eq. (17)-(20)) and the refractive-index potentials V_X, V_Y
  * (Eq. (21), (22)), in the arrangement of Eq. (23) or Eq. (28), with the
  * angles of Eq. (24) and (25). One call to qla_step performs whole time
- * steps; every sub-operator of a step runs in one fused kernel pass.
+ * steps; every sub-operator of a step runs in one fused kernel pass, for
+ * one lattice or for a batch of lattices of uneven sizes.
  *
  * Conventions shared by every entry point:
  *  - Arrays are structure-of-arrays FP32 planes in device memory,
@@ -85,19 +86,37 @@ typedef struct {
 typedef struct qla_ctx qla_ctx;   /* opaque */
 
 /* Launch geometry of the fused step kernel (a tuning knob, not part of the
- * method). A wave owns 64*cols lattice columns and a segment of seg_rows rows.
+ * method; results are bitwise identical for every geometry). A wave owns 128
+ * lattice columns (120 of them output) and a segment of seg_rows rows.
  * A field set to 0 asks for the library's default.
  *   seg_rows         rows per wave segment, rounded up to a multiple of 4
+ *                    (default: the shortest for which the whole grid is
+ *                    resident at once)
  *   waves_per_block  1..4 waves (vertically adjacent segments) per block
- *   cols             lattice columns per lane: 2 or 4 */
+ *                    (default 1)
+ *   graph_steps      steps per replayed HIP graph (rounded up to even);
+ *                    1 launches every step on its own (default 32) */
 typedef struct {
     int32_t seg_rows;
     int32_t waves_per_block;
-    int32_t cols;
+    int32_t graph_steps;
 } qla_launch;
+
+/* One lattice of a batch: its parameters and caller-owned device buffers
+ * (layouts as for qla_init). Every lattice of a batch must use the same
+ * pot_mode and beta_scale; sizes and delta may differ. */
+typedef struct {
+    qla_params p;
+    const float *d_n;
+    float *d_q;
+    float *d_q_pong;
+} qla_instance;
 
 /* Bytes of device workspace qla_init needs for these parameters. */
 qla_status qla_workspace_size(const qla_params *p, size_t *bytes);
+
+/* Bytes of device workspace qla_init_batch needs for this batch. */
+qla_status qla_batch_workspace_size(int32_t count, const qla_instance *inst, size_t *bytes);
 
 /* Bind the caller's buffers and validate n.
  *   d_n        3*ny*nx FP32, n_x, n_y, n_z; read by every step, never written
@@ -112,15 +131,32 @@ qla_status qla_workspace_size(const qla_params *p, size_t *bytes);
 qla_status qla_init(const qla_params *p, const float *d_n, float *d_q, float *d_q_pong,
                     void *d_work, void *hip_stream, qla_ctx **out);
 
-/* Enqueue nsteps >= 0 whole time steps (Eq. (23) or Eq. (28)) on the
- * context's stream. Asynchronous; launch errors are reported. */
+/* A batch of count >= 1 independent lattices of uneven sizes (many
+ * scattering instances): every qla_step advances all of them, with one
+ * kernel launch per step covering the whole batch. inst is read during the
+ * call only; the buffers it names must outlive the context. d_work is
+ * qla_batch_workspace_size() bytes, 256-byte aligned. qla_init is the batch
+ * of one. */
+qla_status qla_init_batch(int32_t count, const qla_instance *inst, void *d_work, void *hip_stream,
+                          qla_ctx **out);
+
+/* Number of lattices the context steps. */
+qla_status qla_count(qla_ctx *ctx, int32_t *count);
+
+/* Enqueue nsteps >= 0 whole time steps (Eq. (23) or Eq. (28)) of every
+ * lattice on the context's stream. Runs of graph_steps steps are replayed
+ * from a HIP graph built on first use. Asynchronous; launch errors are
+ * reported. */
 qla_status qla_step(qla_ctx *ctx, int64_t nsteps);
 
-/* Compute qla_diag for the current state. Synchronises the stream. */
+/* Compute qla_diag for the current state of each lattice: out holds one
+ * entry per lattice, in batch order. Synchronises the stream. */
 qla_status qla_energy(qla_ctx *ctx, qla_diag *out);
 
-/* Copy the current state to dst (6*ny*nx FP32).
- *   what = 0: Q as stored;  what = 1: (E, B) with E_c = q_c / n_c (Eq. (15))
+/* Copy the current state of every lattice to dst, lattices back to back in
+ * batch order, 6*ny*nx FP32 each.
+ *   what = 0: Q as stored;  what = 1: (E, B) with E_c = q_c / n_c (Eq. (15));
+ *             (E, B) is staged in the idle state buffer
  *   dst_is_host = 1: dst is host memory; 0: device memory
  * Synchronises the stream. */
 qla_status qla_fields(qla_ctx *ctx, float *dst, int32_t what, int32_t dst_is_host);
@@ -133,8 +169,10 @@ qla_status qla_get_launch(qla_ctx *ctx, qla_launch *out);
  * stays. Results are bitwise identical for every geometry. */
 qla_status qla_set_launch(qla_ctx *ctx, const qla_launch *req);
 
-/* Device pointer of the buffer holding the current state (d_q or d_q_pong). */
+/* Device pointer of the buffer holding the current state (d_q or d_q_pong)
+ * of lattice 0, or of lattice index. */
 qla_status qla_state(qla_ctx *ctx, float **d_current);
+qla_status qla_state_at(qla_ctx *ctx, int32_t index, float **d_current);
 
 /* Release the context's host memory. Safe on NULL. Does not synchronise. */
 void qla_free(qla_ctx *ctx);

@@ -46,10 +46,15 @@ class Diag(ctypes.Structure):
 
 class Launch(ctypes.Structure):
     _fields_ = [("seg_rows", ctypes.c_int32), ("waves_per_block", ctypes.c_int32),
-                ("cols", ctypes.c_int32)]
+                ("graph_steps", ctypes.c_int32)]
 
     def as_dict(self) -> Dict[str, int]:
         return {name: int(getattr(self, name)) for name, _ in self._fields_}
+
+
+class Instance(ctypes.Structure):
+    _fields_ = [("p", Params), ("d_n", ctypes.c_void_p), ("d_q", ctypes.c_void_p),
+                ("d_q_pong", ctypes.c_void_p)]
 
 
 _lib = None
@@ -57,14 +62,20 @@ _lib = None
 # name -> (argtypes, restype); the exported surface of include/qla.h
 _SIGNATURES = {
     "qla_workspace_size": ([ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "qla_batch_workspace_size": ([ctypes.c_int32, ctypes.POINTER(Instance),
+                                  ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "qla_init": ([ctypes.POINTER(Params), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                   ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
+    "qla_init_batch": ([ctypes.c_int32, ctypes.POINTER(Instance), ctypes.c_void_p, ctypes.c_void_p,
+                        ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
+    "qla_count": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
     "qla_step": ([ctypes.c_void_p, ctypes.c_int64], ctypes.c_int),
     "qla_energy": ([ctypes.c_void_p, ctypes.POINTER(Diag)], ctypes.c_int),
     "qla_fields": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
     "qla_get_launch": ([ctypes.c_void_p, ctypes.POINTER(Launch)], ctypes.c_int),
     "qla_set_launch": ([ctypes.c_void_p, ctypes.POINTER(Launch)], ctypes.c_int),
     "qla_state": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
+    "qla_state_at": ([ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
     "qla_free": ([ctypes.c_void_p], None),
     "qla_last_error": ([], ctypes.c_char_p),
 }
@@ -111,6 +122,27 @@ def qla_workspace_size(params: Params) -> int:
     return int(out.value)
 
 
+def qla_batch_workspace_size(instances) -> int:
+    arr = (Instance * len(instances))(*instances)
+    out = ctypes.c_size_t(0)
+    _check(lib().qla_batch_workspace_size(len(instances), arr, ctypes.byref(out)))
+    return int(out.value)
+
+
+def qla_init_batch(instances, d_work: int, stream: int) -> ctypes.c_void_p:
+    arr = (Instance * len(instances))(*instances)
+    ctx = ctypes.c_void_p()
+    _check(lib().qla_init_batch(len(instances), arr, ctypes.c_void_p(d_work), ctypes.c_void_p(stream),
+                                ctypes.byref(ctx)))
+    return ctx
+
+
+def qla_count(ctx) -> int:
+    out = ctypes.c_int32(0)
+    _check(lib().qla_count(ctx, ctypes.byref(out)))
+    return int(out.value)
+
+
 def qla_init(params: Params, d_n: int, d_q: int, d_q_pong: int, d_work: int,
              stream: int) -> ctypes.c_void_p:
     ctx = ctypes.c_void_p()
@@ -124,10 +156,12 @@ def qla_step(ctx, nsteps: int) -> None:
     _check(lib().qla_step(ctx, int(nsteps)))
 
 
-def qla_energy(ctx) -> Dict[str, float]:
-    d = Diag()
-    _check(lib().qla_energy(ctx, ctypes.byref(d)))
-    return d.as_dict()
+def qla_energy(ctx, count: int = 1):
+    """One diagnostics dict per lattice (a single dict when count == 1)."""
+    d = (Diag * count)()
+    _check(lib().qla_energy(ctx, d))
+    out = [x.as_dict() for x in d]
+    return out[0] if count == 1 else out
 
 
 def qla_fields(ctx, dst: int, what: int, dst_is_host: bool) -> None:
@@ -140,14 +174,20 @@ def qla_get_launch(ctx) -> Dict[str, int]:
     return out.as_dict()
 
 
-def qla_set_launch(ctx, seg_rows: int = 0, waves_per_block: int = 0, cols: int = 0) -> None:
-    req = Launch(int(seg_rows), int(waves_per_block), int(cols))
+def qla_set_launch(ctx, seg_rows: int = 0, waves_per_block: int = 0, graph_steps: int = 0) -> None:
+    req = Launch(int(seg_rows), int(waves_per_block), int(graph_steps))
     _check(lib().qla_set_launch(ctx, ctypes.byref(req)))
 
 
 def qla_state(ctx) -> int:
     p = ctypes.c_void_p()
     _check(lib().qla_state(ctx, ctypes.byref(p)))
+    return int(p.value)
+
+
+def qla_state_at(ctx, index: int) -> int:
+    p = ctypes.c_void_p()
+    _check(lib().qla_state_at(ctx, int(index), ctypes.byref(p)))
     return int(p.value)
 
 
@@ -198,13 +238,84 @@ class Simulation:
     def launch(self) -> Dict[str, int]:
         return qla_get_launch(self.ctx)
 
-    def set_launch(self, seg_rows: int = 0, waves_per_block: int = 0, cols: int = 0) -> None:
-        qla_set_launch(self.ctx, seg_rows, waves_per_block, cols)
+    def set_launch(self, seg_rows: int = 0, waves_per_block: int = 0, graph_steps: int = 0) -> None:
+        qla_set_launch(self.ctx, seg_rows, waves_per_block, graph_steps)
 
     def state_tensor(self):
         """The device tensor that holds the current state (no copy)."""
         ptr = qla_state(self.ctx)
         return self.q if ptr == self.q.data_ptr() else self.q_pong
+
+    def close(self) -> None:
+        if self.ctx is not None:
+            qla_free(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many lattices of uneven sizes stepped together (one kernel launch per
+    step for the whole batch): per-lattice n, state buffers (torch) and one
+    shared workspace."""
+
+    def __init__(self, ns, q0s, deltas, pot_mode: str = "eq28", beta_scale: str = "phys",
+                 device: str = "cuda:0", stream=None):
+        import torch
+
+        if not (len(ns) == len(q0s) == len(deltas)) or len(ns) == 0:
+            raise ValueError("need one n, q0 and delta per lattice")
+        self.device = torch.device(device)
+        self.n, self.q, self.q_pong, self.shapes = [], [], [], []
+        insts = []
+        for n, q0, d in zip(ns, q0s, deltas):
+            n_t = torch.as_tensor(np.ascontiguousarray(n, dtype=np.float32)).to(self.device)
+            q_t = torch.as_tensor(np.ascontiguousarray(q0, dtype=np.float32)).to(self.device).clone()
+            if n_t.dim() != 3 or n_t.shape[0] != 3 or tuple(q_t.shape) != (6,) + tuple(n_t.shape[1:]):
+                raise ValueError("expected n of shape (3, ny, nx) and q0 of shape (6, ny, nx)")
+            ny, nx = int(n_t.shape[1]), int(n_t.shape[2])
+            qp = torch.empty_like(q_t)
+            self.n.append(n_t)
+            self.q.append(q_t)
+            self.q_pong.append(qp)
+            self.shapes.append((ny, nx))
+            insts.append(Instance(make_params(nx, ny, d, pot_mode, beta_scale), n_t.data_ptr(),
+                                  q_t.data_ptr(), qp.data_ptr()))
+        nbytes = qla_batch_workspace_size(insts)
+        self.work = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.ctx = qla_init_batch(insts, self.work.data_ptr(), self.stream.cuda_stream)
+        self.count = len(insts)
+
+    @property
+    def sites(self) -> int:
+        return sum(ny * nx for ny, nx in self.shapes)
+
+    def step(self, nsteps: int) -> None:
+        qla_step(self.ctx, nsteps)
+
+    def diagnostics(self):
+        return qla_energy(self.ctx, self.count) if self.count > 1 else [qla_energy(self.ctx, 1)]
+
+    def fields(self, what: str = "Q"):
+        total = sum(6 * ny * nx for ny, nx in self.shapes)
+        flat = np.empty(total, dtype=np.float32)
+        qla_fields(self.ctx, flat.ctypes.data, {"Q": 0, "EB": 1}[what], True)
+        out, o = [], 0
+        for ny, nx in self.shapes:
+            out.append(flat[o:o + 6 * ny * nx].reshape(6, ny, nx))
+            o += 6 * ny * nx
+        return out
+
+    def launch(self) -> Dict[str, int]:
+        return qla_get_launch(self.ctx)
+
+    def set_launch(self, seg_rows: int = 0, waves_per_block: int = 0, graph_steps: int = 0) -> None:
+        qla_set_launch(self.ctx, seg_rows, waves_per_block, graph_steps)
 
     def close(self) -> None:
         if self.ctx is not None:

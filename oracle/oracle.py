@@ -24,6 +24,7 @@ _LIB = os.path.join(_HERE, "libqla_oracle.so")
 
 POT_MODES = {"eq23": 0, "eq28": 1}
 BETA_SCALES = {"phys": 0, "lattice": 1, "off": 2}
+V_FORMS = {"printed": 0, "skew": 1}
 
 _lib = None
 
@@ -48,6 +49,13 @@ def _load():
         lib.qla_oracle_run.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                        ctypes.c_int, dp, dp, ctypes.c_int64, ctypes.c_int]
         lib.qla_oracle_run.restype = ctypes.c_int
+        lib.qla_oracle_run_form.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                            ctypes.c_int, ctypes.c_int, dp, dp, ctypes.c_int64,
+                                            ctypes.c_int]
+        lib.qla_oracle_run_form.restype = ctypes.c_int
+        lib.qla_oracle_potential.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                             ctypes.c_int, ctypes.c_int, ctypes.c_double, dp, dp]
+        lib.qla_oracle_potential.restype = ctypes.c_int
         lib.qla_oracle_angles.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                           dp, dp, dp]
         lib.qla_oracle_angles.restype = ctypes.c_int
@@ -67,17 +75,34 @@ def threads(nthreads: int = 0) -> int:
 
 
 def run(n: np.ndarray, q: np.ndarray, delta: float, steps: int, pot_mode: str = "eq28",
-        beta_scale: str = "phys", nthreads: int = 0) -> np.ndarray:
+        beta_scale: str = "phys", nthreads: int = 0, v_form: str = "printed") -> np.ndarray:
     """Return Q after ``steps`` full QLA steps (Eq. (23) or Eq. (28)),
-    computed in FP64. The inputs are not modified."""
+    computed in FP64, with the potentials of Eq. (21)/(22) as printed
+    (``v_form="printed"``) or their skew-symmetric variant (``"skew"``).
+    The inputs are not modified."""
     n64 = np.ascontiguousarray(n, dtype=np.float64)
     q64 = np.array(q, dtype=np.float64, order="C", copy=True)
     if n64.ndim != 3 or n64.shape[0] != 3 or q64.shape != (6,) + n64.shape[1:]:
         raise ValueError("expected n of shape (3, ny, nx) and q of shape (6, ny, nx)")
     ny, nx = n64.shape[1:]
-    rc = _load().qla_oracle_run(int(nx), int(ny), float(delta), POT_MODES[pot_mode],
-                                BETA_SCALES[beta_scale], _dptr(n64), _dptr(q64),
-                                int(steps), int(nthreads))
+    rc = _load().qla_oracle_run_form(int(nx), int(ny), float(delta), POT_MODES[pot_mode],
+                                     BETA_SCALES[beta_scale], V_FORMS[v_form], _dptr(n64),
+                                     _dptr(q64), int(steps), int(nthreads))
+    if rc != 0:
+        raise ValueError(f"oracle rejected its arguments (status {rc})")
+    return q64
+
+
+def potential(n: np.ndarray, q: np.ndarray, delta: float, axis: str, frac: float = 1.0,
+              beta_scale: str = "phys", v_form: str = "printed") -> np.ndarray:
+    """V_X (``axis="x"``, Eq. (21)) or V_Y (``"y"``, Eq. (22)) alone, with
+    the angles of Eq. (25) scaled by ``frac``, applied to a copy of q."""
+    n64 = np.ascontiguousarray(n, dtype=np.float64)
+    q64 = np.array(q, dtype=np.float64, order="C", copy=True)
+    ny, nx = n64.shape[1:]
+    rc = _load().qla_oracle_potential(int(nx), int(ny), float(delta), BETA_SCALES[beta_scale],
+                                      V_FORMS[v_form], {"x": 0, "y": 1}[axis], float(frac),
+                                      _dptr(n64), _dptr(q64))
     if rc != 0:
         raise ValueError(f"oracle rejected its arguments (status {rc})")
     return q64

@@ -38,6 +38,14 @@
  *  - Eq. (28): the interleaved potentials use half angles and act after the
  *    8th and after the 16th operator of each directional sequence; the
  *    x potentials act before U_Y.
+ *
+ * Besides the printed potentials the oracle holds one variant the paper
+ * names as future work but does not specify (a unitary potential): the
+ * skew-symmetric part of V_X, V_Y. The printed V at angle b differs from the
+ * identity, to first order in b, by b times a matrix G with a single entry
+ * per coupled pair; the variant replaces V by exp(b (G - G^T) / 2), which
+ * is a rotation by b/2 in the same pair and in the sense of the printed
+ * coupling. It is orthogonal, so with it every step conserves Eq. (27).
  */
 #include <math.h>
 #include <stdint.h>
@@ -49,6 +57,7 @@
 
 enum { POT_EQ23 = 0, POT_EQ28 = 1 };
 enum { BETA_PHYS = 0, BETA_LATTICE = 1, BETA_OFF = 2 };
+enum { V_PRINTED = 0, V_SKEW = 1 };
 
 typedef struct {
     int nx, ny;
@@ -56,6 +65,7 @@ typedef struct {
     double *theta;   /* theta[c][site], c = 0,1,2: Eq. (24)            */
     double *beta;    /* beta[k][site],  k = 0..3:  Eq. (25)            */
     double *tmp;     /* one plane of scratch for the streaming shifts  */
+    int v_form;      /* V_PRINTED or V_SKEW                             */
 } lattice;
 
 #define AT(plane, c, s, L) ((plane)[(int64_t)(c) * (L)->sites + (s)])
@@ -171,10 +181,18 @@ static void stream(lattice *L, double *q, int a, int b, int dx, int dy) {
  * ------------------------------------------------------------------------- */
 static void potential_x(lattice *L, double *q, double frac) {
     const int64_t N = L->sites;
+    const int skew = L->v_form == V_SKEW;
 #pragma omp parallel for schedule(static)
     for (int64_t s = 0; s < N; ++s) {
         const double b0 = frac * AT(L->beta, 0, s, L);
         const double b2 = frac * AT(L->beta, 2, s, L);
+        if (skew) {
+            /* row 4 couples -q2 into q4: rotate (q4, q2) by b2/2;
+             * row 5 couples +q1 into q5: rotate (q1, q5) by b0/2 */
+            rotate(&AT(q, 4, s, L), &AT(q, 2, s, L), 0.5 * b2);
+            rotate(&AT(q, 1, s, L), &AT(q, 5, s, L), 0.5 * b0);
+            continue;
+        }
         const double q1 = AT(q, 1, s, L), q2 = AT(q, 2, s, L);
         const double q4 = AT(q, 4, s, L), q5 = AT(q, 5, s, L);
         AT(q, 4, s, L) = -sin(b2) * q2 + cos(b2) * q4;
@@ -188,10 +206,18 @@ static void potential_x(lattice *L, double *q, double frac) {
  * ------------------------------------------------------------------------- */
 static void potential_y(lattice *L, double *q, double frac) {
     const int64_t N = L->sites;
+    const int skew = L->v_form == V_SKEW;
 #pragma omp parallel for schedule(static)
     for (int64_t s = 0; s < N; ++s) {
         const double b1 = frac * AT(L->beta, 1, s, L);
         const double b3 = frac * AT(L->beta, 3, s, L);
+        if (skew) {
+            /* row 3 couples +q2 into q3: rotate (q2, q3) by b3/2;
+             * row 5 couples -q0 into q5: rotate (q5, q0) by b1/2 */
+            rotate(&AT(q, 2, s, L), &AT(q, 3, s, L), 0.5 * b3);
+            rotate(&AT(q, 5, s, L), &AT(q, 0, s, L), 0.5 * b1);
+            continue;
+        }
         const double q0 = AT(q, 0, s, L), q2 = AT(q, 2, s, L);
         const double q3 = AT(q, 3, s, L), q5 = AT(q, 5, s, L);
         AT(q, 3, s, L) = sin(b3) * q2 + cos(b3) * q3;
@@ -291,6 +317,7 @@ static int lattice_init(lattice *L, int nx, int ny) {
     L->theta = (double *)malloc(sizeof(double) * 3 * (size_t)L->sites);
     L->beta = (double *)malloc(sizeof(double) * 4 * (size_t)L->sites);
     L->tmp = (double *)malloc(sizeof(double) * (size_t)L->sites);
+    L->v_form = V_PRINTED;
     return (L->theta && L->beta && L->tmp) ? 0 : -2;
 }
 
@@ -311,10 +338,12 @@ static int check_args(int nx, int ny, double delta, int pot_mode, int beta_scale
     return 0;
 }
 
-/* Advance q (6*ny*nx doubles, in place) by nsteps full steps. */
-int qla_oracle_run(int nx, int ny, double delta, int pot_mode, int beta_scale,
-                   const double *n, double *q, int64_t nsteps, int nthreads) {
+/* Advance q (6*ny*nx doubles, in place) by nsteps full steps, with the
+ * potentials in form v_form (V_PRINTED or V_SKEW). */
+int qla_oracle_run_form(int nx, int ny, double delta, int pot_mode, int beta_scale, int v_form,
+                        const double *n, double *q, int64_t nsteps, int nthreads) {
     if (!n || !q || nsteps < 0) return -1;
+    if (v_form != V_PRINTED && v_form != V_SKEW) return -1;
     int rc = check_args(nx, ny, delta, pot_mode, beta_scale, n);
     if (rc) return rc;
 #ifdef _OPENMP
@@ -325,8 +354,38 @@ int qla_oracle_run(int nx, int ny, double delta, int pot_mode, int beta_scale,
     lattice L;
     rc = lattice_init(&L, nx, ny);
     if (rc == 0) {
+        L.v_form = v_form;
         compute_angles(&L, n, delta, kappa_of(delta, beta_scale));
         for (int64_t t = 0; t < nsteps; ++t) full_step(&L, q, pot_mode);
+    }
+    lattice_free(&L);
+    return rc;
+}
+
+/* Advance q by nsteps full steps with the printed potentials. */
+int qla_oracle_run(int nx, int ny, double delta, int pot_mode, int beta_scale,
+                   const double *n, double *q, int64_t nsteps, int nthreads) {
+    return qla_oracle_run_form(nx, ny, delta, pot_mode, beta_scale, V_PRINTED, n, q, nsteps,
+                               nthreads);
+}
+
+/* One potential operator alone: V_X (axis 0) or V_Y (axis 1) with its
+ * angles scaled by frac, in form v_form, applied to q in place. */
+int qla_oracle_potential(int nx, int ny, double delta, int beta_scale, int v_form, int axis,
+                         double frac, const double *n, double *q) {
+    if (!n || !q || (axis != 0 && axis != 1)) return -1;
+    if (v_form != V_PRINTED && v_form != V_SKEW) return -1;
+    int rc = check_args(nx, ny, delta, POT_EQ28, beta_scale, n);
+    if (rc) return rc;
+    lattice L;
+    rc = lattice_init(&L, nx, ny);
+    if (rc == 0) {
+        L.v_form = v_form;
+        compute_angles(&L, n, delta, kappa_of(delta, beta_scale));
+        if (axis == 0)
+            potential_x(&L, q, frac);
+        else
+            potential_y(&L, q, frac);
     }
     lattice_free(&L);
     return rc;

@@ -161,6 +161,14 @@ qla_status qla_energy(qla_ctx *ctx, qla_diag *out);
  * Synchronises the stream. */
 qla_status qla_fields(qla_ctx *ctx, float *dst, int32_t what, int32_t dst_is_host);
 
+/* qla_fields for lattice index of the context only (6*ny*nx FP32). */
+qla_status qla_fields_at(qla_ctx *ctx, int32_t index, float *dst, int32_t what, int32_t dst_is_host);
+
+/* Overwrite the current state of lattice index with src (6*ny*nx FP32 Q,
+ * host memory if src_is_host, else device memory); the step count is
+ * unchanged. Synchronises the stream when src is host memory. */
+qla_status qla_load_at(qla_ctx *ctx, int32_t index, const float *src, int32_t src_is_host);
+
 /* The launch geometry in use (never 0 fields). */
 qla_status qla_get_launch(qla_ctx *ctx, qla_launch *out);
 

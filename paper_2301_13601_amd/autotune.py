@@ -1,0 +1,117 @@
+"""Launch-geometry autotuner for the fused QLA step.
+
+For a set of lattice shapes (one lattice or a batch) and the potential
+placement, time a small set of launch geometries (segment height, waves per
+block, steps per replayed graph) on the GPU and keep the fastest. Results
+are cached as JSON keyed by GPU architecture, placement and shapes, so a
+second call for the same key measures nothing.
+
+Every geometry gives bitwise-identical results (the per-site operation
+sequence does not depend on it), so tuning is free to pick any of them.
+Timing uses the real index profiles (the kernel skips the potentials on
+rows without index gradients, so speed depends on n) and a zero state.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+from typing import Dict, List, Optional, Sequence, Tuple
+
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "qla_autotune.json")
+
+
+def _key(arch: str, pot_mode: str, beta_scale: str, shapes: Sequence[Tuple[int, int]]) -> str:
+    h = hashlib.sha256(json.dumps(sorted(shapes)).encode()).hexdigest()[:16]
+    return f"{arch}|{pot_mode}|{beta_scale}|n{len(shapes)}|{h}"
+
+
+def candidates(default_seg: int, max_ny: int) -> List[Dict[str, int]]:
+    """Geometries to try around the library's default segment height."""
+    segs = {default_seg}
+    for f in (0.5, 0.75, 1.5, 2.0, 3.0):
+        s = int(round(default_seg * f / 4.0)) * 4
+        if 8 <= s <= max(8, max_ny + 3):
+            segs.add(s)
+    out = []
+    for s in sorted(segs):
+        for wpb in (1, 2):
+            out.append({"seg_rows": s, "waves_per_block": wpb, "graph_steps": 32})
+    out.append({"seg_rows": default_seg, "waves_per_block": 1, "graph_steps": 1})
+    return out
+
+
+def _load(path: str) -> Dict:
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(path: str, cache: Dict) -> None:
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def tune(ns: Sequence, deltas: Sequence[float], pot_mode: str = "eq28", beta_scale: str = "phys",
+         steps: int = 64, cache_path: Optional[str] = None, device: str = "cuda:0",
+         force: bool = False) -> Dict:
+    """Best launch geometry for lattices with index profiles ``ns`` (numpy
+    (3, ny, nx) arrays or device tensors). Returns {"launch": {...},
+    "us_per_step": t, "measured": [...], "cached": bool}."""
+    import numpy as np
+    import torch
+
+    from . import qla
+
+    cache_path = cache_path or os.environ.get("QLA_AUTOTUNE_CACHE", DEFAULT_CACHE)
+    shapes = [tuple(int(v) for v in n.shape[1:]) for n in ns]
+    arch = torch.cuda.get_device_properties(torch.device(device)).gcnArchName
+    key = _key(arch, pot_mode, beta_scale, shapes)
+    cache = _load(cache_path)
+    if not force and key in cache:
+        rec = dict(cache[key])
+        rec["cached"] = True
+        return rec
+
+    zeros = [np.zeros((6,) + s, dtype=np.float32) for s in shapes]
+    n32 = [n if isinstance(n, torch.Tensor) else np.ascontiguousarray(n, dtype=np.float32) for n in ns]
+    stream = torch.cuda.current_stream(torch.device(device))
+    batch = qla.Batch(n32, zeros, list(deltas), pot_mode, beta_scale, device=device, stream=stream)
+    try:
+        default = batch.launch()
+        max_ny = max(s[0] for s in shapes)
+        measured = []
+        for cfg in candidates(default["seg_rows"], max_ny):
+            batch.set_launch(**cfg)
+            batch.step(2 * max(cfg["graph_steps"], 1))          # builds and warms the graphs
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            batch.step(steps)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            us = e0.elapsed_time(e1) * 1e3 / steps
+            measured.append({"launch": batch.launch(), "us_per_step": us})
+        best = min(measured, key=lambda r: r["us_per_step"])
+    finally:
+        batch.close()
+    rec = {"launch": best["launch"], "us_per_step": best["us_per_step"], "measured": measured,
+           "default": default, "arch": arch, "shapes": shapes}
+    cache[key] = rec
+    _store(cache_path, cache)
+    out = dict(rec)
+    out["cached"] = False
+    return out
+
+
+def apply(obj, ns, deltas, pot_mode="eq28", beta_scale="phys", **kw) -> Dict:
+    """Tune for ``ns`` and set the winning geometry on a Simulation or Batch."""
+    rec = tune(ns, deltas, pot_mode, beta_scale, **kw)
+    obj.set_launch(**rec["launch"])
+    return rec

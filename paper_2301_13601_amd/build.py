@@ -13,7 +13,7 @@ import tempfile
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["qla.hip", "qla_step_eq23.hip", "qla_step_eq28.hip"]
+SOURCES = ["qla.hip", "qla_step_eq23.hip", "qla_step_eq28.hip", "qnn.hip"]
 LIB = os.path.join(HERE, "libqla.so")
 INCLUDE = os.path.join(ROOT, "include")
 

@@ -238,6 +238,16 @@ size_t work_bytes(int count) { return diag_bytes() + scan_bytes() + align256(siz
 
 }  // namespace
 
+// error reporting shared with the surrogate kernels (qnn.hip)
+namespace qnn {
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
+  va_end(ap);
+}
+}  // namespace qnn
+
 struct qla_ctx {
   uint64_t magic;
   int count;
@@ -622,14 +632,16 @@ qla_status qla_energy(qla_ctx* ctx, qla_diag* out) {
   return QLA_OK;
 }
 
-qla_status qla_fields(qla_ctx* ctx, float* dst, int32_t what, int32_t dst_is_host) {
-  qla_status st = check_ctx(ctx);
-  if (st != QLA_OK) return st;
+namespace {
+
+// export lattice i (or every lattice when i < 0) to dst
+qla_status fields_impl(qla_ctx* ctx, int i_only, float* dst, int32_t what, int32_t dst_is_host) {
   if (!dst) return fail(QLA_EINVAL, "qla: null destination");
   if (what != 0 && what != 1) return fail(QLA_EINVAL, "qla: what must be 0 (Q) or 1 (E, B)");
   hipError_t e = hipSuccess;
   float* o = dst;
   for (int i = 0; i < ctx->count && e == hipSuccess; ++i) {
+    if (i_only >= 0 && i != i_only) continue;
     const qla_params& p = ctx->p[i];
     const int64_t plane = static_cast<int64_t>(p.nx) * p.ny;
     const size_t bytes = static_cast<size_t>(plane) * 6 * sizeof(float);
@@ -650,6 +662,35 @@ qla_status qla_fields(qla_ctx* ctx, float* dst, int32_t what, int32_t dst_is_hos
   }
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "exporting fields");
+  return QLA_OK;
+}
+
+}  // namespace
+
+qla_status qla_fields(qla_ctx* ctx, float* dst, int32_t what, int32_t dst_is_host) {
+  qla_status st = check_ctx(ctx);
+  if (st != QLA_OK) return st;
+  return fields_impl(ctx, -1, dst, what, dst_is_host);
+}
+
+qla_status qla_fields_at(qla_ctx* ctx, int32_t index, float* dst, int32_t what, int32_t dst_is_host) {
+  qla_status st = check_ctx(ctx);
+  if (st != QLA_OK) return st;
+  if (index < 0 || index >= ctx->count) return fail(QLA_EINVAL, "qla: lattice index %d out of range", index);
+  return fields_impl(ctx, index, dst, what, dst_is_host);
+}
+
+qla_status qla_load_at(qla_ctx* ctx, int32_t index, const float* src, int32_t src_is_host) {
+  qla_status st = check_ctx(ctx);
+  if (st != QLA_OK) return st;
+  if (!src) return fail(QLA_EINVAL, "qla: null source");
+  if (index < 0 || index >= ctx->count) return fail(QLA_EINVAL, "qla: lattice index %d out of range", index);
+  const qla_params& p = ctx->p[index];
+  const size_t bytes = static_cast<size_t>(p.nx) * p.ny * 6 * sizeof(float);
+  hipError_t e = hipMemcpyAsync(ctx->buf[ctx->cur][index], src, bytes,
+                                src_is_host ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, ctx->stream);
+  if (e == hipSuccess && src_is_host) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "loading a state");
   return QLA_OK;
 }
 

@@ -1,0 +1,712 @@
+// Kernels of the convolutional surrogate (C ABI in include/qla_nn.h): BF16
+// implicit-GEMM 3x3 circular convolutions on the gfx950 matrix cores
+// (v_mfma_f32_32x32x16_bf16, FP32 accumulation), their weight gradients, and
+// the elementwise pieces of a U-net step (pooling, upsampling, activation,
+// input packing, relative-L2 loss, Adam).
+//
+// MFMA 32x32x16 operand layout (lane l of the wave): A supplies row l % 32
+// and the eight K values 8*(l / 32) .. +7; B supplies column l % 32 and the
+// same eight K values; the 16 FP32 results of lane l are column l % 32,
+// rows 8*(r / 4) + 4*(l / 32) + r % 4 for r = 0..15.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+
+#include "qla_nn.h"
+
+extern "C" const char* qla_last_error(void);
+
+namespace qnn {
+
+// the library's per-thread error message (defined with the step ABI)
+void set_error(const char* fmt, ...) __attribute__((format(printf, 1, 2)));
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr float kLeakySlope = 0.125f;
+
+__host__ __device__ inline float bf2f(uint16_t v) { return __uint_as_float(static_cast<uint32_t>(v) << 16); }
+
+// round to nearest even; NaN stays NaN
+__host__ __device__ inline uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return static_cast<uint16_t>((u >> 16) | 0x40);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return static_cast<uint16_t>(u >> 16);
+}
+
+__device__ inline int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+// ---------------------------------------------------------------------------
+// Forward 3x3 circular convolution as an implicit GEMM. A wave computes 32
+// pixels x 32*NT output channels; a block is 4 waves along the pixels.
+// ---------------------------------------------------------------------------
+template <int NT, bool OUT_FP32>
+__global__ void __launch_bounds__(256) conv_fwd_kernel(int P, int H, int W, const uint16_t* __restrict__ x,
+                                                       int cin, const uint16_t* __restrict__ w,
+                                                       const float* __restrict__ bias, int act,
+                                                       void* __restrict__ y, int y_ld, int c_store) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int m0 = (blockIdx.x * 4 + wave) * 32;
+  if (m0 >= P) return;
+  const int n0 = blockIdx.y * 32 * NT;
+  const int HW = H * W;
+  const int p = m0 + (lane & 31);
+  const int pc = p < P ? p : P - 1;
+  const int b = pc / HW;
+  const int rem = pc - b * HW;
+  const int yy = rem / W;
+  const int xx = rem - yy * W;
+  int nb[9];
+#pragma unroll
+  for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+    for (int dx = -1; dx <= 1; ++dx)
+      nb[(dy + 1) * 3 + (dx + 1)] = b * HW + wrapi(yy + dy, H) * W + wrapi(xx + dx, W);
+  const int kg = (lane >> 5) * 8;
+  const int K = 9 * cin;
+  f32x16 acc[NT];
+#pragma unroll
+  for (int j = 0; j < NT; ++j)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[j][r] = 0.0f;
+  const uint16_t* wl[NT];
+#pragma unroll
+  for (int j = 0; j < NT; ++j) wl[j] = w + static_cast<int64_t>(n0 + j * 32 + (lane & 31)) * K + kg;
+#pragma unroll 1
+  for (int t = 0; t < 9; ++t) {
+    const uint16_t* xr = x + static_cast<int64_t>(nb[t]) * cin + kg;
+#pragma unroll 2
+    for (int c0 = 0; c0 < cin; c0 += 16) {
+      const bf16x8 a = *reinterpret_cast<const bf16x8*>(xr + c0);
+#pragma unroll
+      for (int j = 0; j < NT; ++j) {
+        const bf16x8 bv = *reinterpret_cast<const bf16x8*>(wl[j] + t * cin + c0);
+        acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bv, acc[j], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < NT; ++j) {
+    const int col = n0 + j * 32 + (lane & 31);
+    if (col >= c_store) continue;
+    const float bsum = bias ? bias[col] : 0.0f;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = m0 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+      if (row >= P) continue;
+      float v = acc[j][r] + bsum;
+      if (act == QNN_ACT_LEAKY) v = v > 0.0f ? v : kLeakySlope * v;
+      if constexpr (OUT_FP32)
+        static_cast<float*>(y)[static_cast<int64_t>(row) * y_ld + col] = v;
+      else
+        static_cast<uint16_t*>(y)[static_cast<int64_t>(row) * y_ld + col] = f2bf(v);
+    }
+  }
+}
+
+__global__ void flip_kernel(const uint16_t* __restrict__ w, int cout, int cin, uint16_t* __restrict__ wt) {
+  const int64_t n = static_cast<int64_t>(cout) * 9 * cin;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int ci = static_cast<int>(i % cin);
+    const int t = static_cast<int>((i / cin) % 9);
+    const int co = static_cast<int>(i / (9 * static_cast<int64_t>(cin)));
+    wt[(static_cast<int64_t>(ci) * 9 + (8 - t)) * cout + co] = w[i];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Weight gradient: dW[co][k] = sum_p dy[p][co] * x[nbr(p, t)][ci], k = t*cin+ci,
+// an MFMA GEMM (M = c_out, N = 9*c_in, K = pixels). A block (4 waves) owns a
+// 32x32 tile of dW and a range of pixels; waves take interleaved 16-pixel
+// chunks (each within one image row, W % 16 == 0), then fold through LDS.
+// ---------------------------------------------------------------------------
+constexpr int kWgradPixelsPerBlock = 4096;
+
+// ROWS: W % 16 == 0, so a 16-pixel chunk lies in one image row and its
+// neighbours are found once per chunk; otherwise every pixel is decoded
+// (and bounds-checked) on its own.
+template <bool ROWS>
+__global__ void __launch_bounds__(256) wgrad_kernel(int P, int H, int W, const uint16_t* __restrict__ x,
+                                                    int cin, const uint16_t* __restrict__ dy,
+                                                    int cout, float* __restrict__ part,
+                                                    float* __restrict__ bpart) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int co0 = blockIdx.x * 32;
+  const int k0 = blockIdx.y * 32;
+  const int split = blockIdx.z;
+  const int K = 9 * cin;
+  const int HW = H * W;
+  // columns past 9*c_in (when it is not a multiple of 32) compute zeros and
+  // are not stored
+  const bool kvalid = k0 + (lane & 31) < K;
+  const int kk = kvalid ? k0 + (lane & 31) : K - 1;
+  const int t = kk / cin;
+  const int ci = kk - t * cin;
+  const int tdy = t / 3 - 1, tdx = t % 3 - 1;
+  const int co = co0 + (lane & 31);
+  const int half = (lane >> 5) * 8;
+  f32x16 acc;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+  float bsum = 0.0f;
+  const int pbeg = split * kWgradPixelsPerBlock;
+  const int pend = min(P, pbeg + kWgradPixelsPerBlock);
+  for (int p0 = pbeg + wave * 16; p0 < pend; p0 += 64) {
+    bf16x8 a, bb;
+    if constexpr (ROWS) {
+      // the chunk's row: image b, row yy, columns xb .. xb+15
+      const int b = p0 / HW;
+      const int rem = p0 - b * HW;
+      const int yy = rem / W;
+      const int xb = rem - yy * W;
+      const int ysrc = wrapi(yy + tdy, H);
+      const int64_t rowbase = static_cast<int64_t>(b) * HW + static_cast<int64_t>(ysrc) * W;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const uint16_t dv = dy[static_cast<int64_t>(p0 + half + j) * cout + co];
+        bsum += bf2f(dv);
+        a[j] = __builtin_bit_cast(__bf16, dv);
+        const int xs = wrapi(xb + half + j + tdx, W);
+        const uint16_t xv = x[(rowbase + xs) * cin + ci];
+        bb[j] = __builtin_bit_cast(__bf16, kvalid ? xv : static_cast<uint16_t>(0));
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int pp = p0 + half + j;
+        uint16_t dv = 0, xv = 0;
+        if (pp < pend) {
+          dv = dy[static_cast<int64_t>(pp) * cout + co];
+          const int b = pp / HW;
+          const int rem = pp - b * HW;
+          const int yy = rem / W;
+          const int xx = rem - yy * W;
+          const int64_t src = static_cast<int64_t>(b) * HW + static_cast<int64_t>(wrapi(yy + tdy, H)) * W +
+                              wrapi(xx + tdx, W);
+          if (kvalid) xv = x[src * cin + ci];
+        }
+        bsum += bf2f(dv);
+        a[j] = __builtin_bit_cast(__bf16, dv);
+        bb[j] = __builtin_bit_cast(__bf16, xv);
+      }
+    }
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bb, acc, 0, 0, 0);
+  }
+  // fold the four waves
+  __shared__ float sh[4][16][64];
+  __shared__ float shb[4][64];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) sh[wave][r][lane] = acc[r];
+  shb[wave][lane] = bsum;
+  __syncthreads();
+  if (wave == 0) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const float v = sh[0][r][lane] + sh[1][r][lane] + sh[2][r][lane] + sh[3][r][lane];
+      const int row = (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);     // co within the tile
+      if (kvalid) part[(static_cast<int64_t>(split) * cout + co0 + row) * K + k0 + (lane & 31)] = v;
+    }
+    if (bpart && blockIdx.y == 0 && lane < 32) {
+      const float v = shb[0][lane] + shb[1][lane] + shb[2][lane] + shb[3][lane] +
+                      shb[0][lane + 32] + shb[1][lane + 32] + shb[2][lane + 32] + shb[3][lane + 32];
+      bpart[static_cast<int64_t>(split) * cout + co0 + lane] = v;
+    }
+  }
+}
+
+__global__ void wgrad_reduce_kernel(const float* __restrict__ part, int nsplit, int64_t n,
+                                    float* __restrict__ out) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    float s = 0.0f;
+    for (int k = 0; k < nsplit; ++k) s += part[static_cast<int64_t>(k) * n + i];
+    out[i] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Elementwise pieces.
+// ---------------------------------------------------------------------------
+#define QNN_GRID_STRIDE(i, n)                                                                  \
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < (n);       \
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+
+__global__ void leaky_bwd_kernel(int64_t n, const uint16_t* __restrict__ y, const uint16_t* dy, uint16_t* dz) {
+  QNN_GRID_STRIDE(i, n) {
+    const float g = bf2f(dy[i]);
+    dz[i] = f2bf(bf2f(y[i]) > 0.0f ? g : kLeakySlope * g);
+  }
+}
+
+__global__ void add_kernel(int64_t n, const uint16_t* a, const uint16_t* b, uint16_t* y) {
+  QNN_GRID_STRIDE(i, n) { y[i] = f2bf(bf2f(a[i]) + bf2f(b[i])); }
+}
+
+__global__ void avgpool2_kernel(int B, int H, int W, int C, const uint16_t* __restrict__ x, uint16_t* __restrict__ y) {
+  const int h = H / 2, w = W / 2;
+  const int64_t n = static_cast<int64_t>(B) * h * w * C;
+  QNN_GRID_STRIDE(i, n) {
+    const int c = static_cast<int>(i % C);
+    int64_t q = i / C;
+    const int xo = static_cast<int>(q % w);
+    q /= w;
+    const int yo = static_cast<int>(q % h);
+    const int b = static_cast<int>(q / h);
+    const int64_t base = ((static_cast<int64_t>(b) * H + 2 * yo) * W + 2 * xo) * C + c;
+    const float s = bf2f(x[base]) + bf2f(x[base + C]) + bf2f(x[base + static_cast<int64_t>(W) * C]) +
+                    bf2f(x[base + static_cast<int64_t>(W) * C + C]);
+    y[i] = f2bf(0.25f * s);
+  }
+}
+
+__global__ void avgpool2_bwd_kernel(int B, int H, int W, int C, const uint16_t* __restrict__ dy,
+                                    uint16_t* __restrict__ dx, int accumulate) {
+  const int h = H / 2, w = W / 2;
+  const int64_t n = static_cast<int64_t>(B) * H * W * C;
+  QNN_GRID_STRIDE(i, n) {
+    const int c = static_cast<int>(i % C);
+    int64_t q = i / C;
+    const int xx = static_cast<int>(q % W);
+    q /= W;
+    const int yy = static_cast<int>(q % H);
+    const int b = static_cast<int>(q / H);
+    const float g = 0.25f * bf2f(dy[((static_cast<int64_t>(b) * h + yy / 2) * w + xx / 2) * C + c]);
+    dx[i] = f2bf(accumulate ? bf2f(dx[i]) + g : g);
+  }
+}
+
+__global__ void upsample2_kernel(int B, int h, int w, int C, const uint16_t* __restrict__ x, uint16_t* __restrict__ y) {
+  const int H = 2 * h, W = 2 * w;
+  const int64_t n = static_cast<int64_t>(B) * H * W * C;
+  QNN_GRID_STRIDE(i, n) {
+    const int c = static_cast<int>(i % C);
+    int64_t q = i / C;
+    const int xx = static_cast<int>(q % W);
+    q /= W;
+    const int yy = static_cast<int>(q % H);
+    const int b = static_cast<int>(q / H);
+    y[i] = x[((static_cast<int64_t>(b) * h + yy / 2) * w + xx / 2) * C + c];
+  }
+}
+
+__global__ void upsample2_bwd_kernel(int B, int h, int w, int C, const uint16_t* __restrict__ dy, uint16_t* __restrict__ dx) {
+  const int W = 2 * w;
+  const int64_t n = static_cast<int64_t>(B) * h * w * C;
+  QNN_GRID_STRIDE(i, n) {
+    const int c = static_cast<int>(i % C);
+    int64_t q = i / C;
+    const int xo = static_cast<int>(q % w);
+    q /= w;
+    const int yo = static_cast<int>(q % h);
+    const int b = static_cast<int>(q / h);
+    const int64_t base = ((static_cast<int64_t>(b) * 2 * h + 2 * yo) * W + 2 * xo) * C + c;
+    const float s = bf2f(dy[base]) + bf2f(dy[base + C]) + bf2f(dy[base + static_cast<int64_t>(W) * C]) +
+                    bf2f(dy[base + static_cast<int64_t>(W) * C + C]);
+    dx[i] = f2bf(s);
+  }
+}
+
+__global__ void absmax_kernel(int H, int W, const float* __restrict__ q, const int32_t* __restrict__ idx,
+                              float* __restrict__ scale) {
+  const int b = blockIdx.x;
+  const int64_t n = 6 * static_cast<int64_t>(H) * W;
+  const float* qs = q + (idx ? idx[b] : b) * n;
+  float m = 0.0f;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) m = fmaxf(m, fabsf(qs[i]));
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+  __shared__ float sh[4];
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    m = fmaxf(fmaxf(sh[0], sh[1]), fmaxf(sh[2], sh[3]));
+    scale[b] = m > 0.0f ? m : 1.0f;
+  }
+}
+
+constexpr int kInCh = 48;
+
+__global__ void pack_input_kernel(int B, int H, int W, const float* __restrict__ q, const int32_t* __restrict__ idx_q,
+                                  const float* __restrict__ n, const int32_t* __restrict__ idx_n,
+                                  const float* __restrict__ scale, float n_shift, float n_scale, int shift,
+                                  uint16_t* __restrict__ x) {
+  const int64_t HW = static_cast<int64_t>(H) * W;
+  const int64_t total = B * HW * kInCh;
+  QNN_GRID_STRIDE(i, total) {
+    const int c = static_cast<int>(i % kInCh);
+    const int64_t p = i / kInCh;
+    const int b = static_cast<int>(p / HW);
+    const int64_t s = p - b * HW;
+    const int yy = static_cast<int>(s / W);
+    const int xx = static_cast<int>(s - static_cast<int64_t>(yy) * W);
+    float v = 0.0f;
+    const int64_t qs = idx_q ? idx_q[b] : b;
+    if (c < 6) {
+      v = q[(qs * 6 + c) * HW + s] / scale[b];
+    } else if (c < 9) {
+      const int64_t ns = idx_n ? idx_n[b] : b;
+      v = (n[(ns * 3 + (c - 6)) * HW + s] - n_shift) / n_scale;
+    } else if (c < 33) {
+      const int blk = (c - 9) / 6, cc = (c - 9) % 6;
+      int sy = yy, sx = xx;
+      if (blk == 0) sx = xx - shift;
+      else if (blk == 1) sx = xx + shift;
+      else if (blk == 2) sy = yy - shift;
+      else sy = yy + shift;
+      sx %= W;
+      if (sx < 0) sx += W;
+      sy %= H;
+      if (sy < 0) sy += H;
+      v = q[(qs * 6 + cc) * HW + static_cast<int64_t>(sy) * W + sx] / scale[b];
+    }
+    x[i] = f2bf(v);
+  }
+}
+
+__global__ void unpack_output_kernel(int B, int H, int W, const float* __restrict__ y, int y_ld,
+                                     const float* __restrict__ scale, float* __restrict__ q) {
+  const int64_t HW = static_cast<int64_t>(H) * W;
+  const int64_t total = B * 6 * HW;
+  QNN_GRID_STRIDE(i, total) {
+    const int64_t s = i % HW;
+    const int c = static_cast<int>((i / HW) % 6);
+    const int b = static_cast<int>(i / (6 * HW));
+    q[i] = y[(b * HW + s) * y_ld + c] * scale[b];
+  }
+}
+
+// relative L2: per-sample partial sums of (pred-target)^2 and target^2, the
+// target being lattice sample idx_t[b] divided by scale[b]
+__global__ void __launch_bounds__(256) rel_l2_partial_kernel(int H, int W, const float* __restrict__ pred, int pred_ld,
+                                                             const float* __restrict__ target,
+                                                             const int32_t* __restrict__ idx_t,
+                                                             const float* __restrict__ scale,
+                                                             double* __restrict__ work) {
+  const int b = blockIdx.y;
+  const int64_t HW = static_cast<int64_t>(H) * W;
+  const float* tb = target + (idx_t ? idx_t[b] : b) * 6 * HW;
+  const double inv = 1.0 / static_cast<double>(scale ? scale[b] : 1.0f);
+  double num = 0.0, den = 0.0;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < 6 * HW;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int c = static_cast<int>(i / HW);
+    const int64_t s = i - c * HW;
+    const double t = static_cast<double>(tb[i]) * inv;
+    const double d = static_cast<double>(pred[(b * HW + s) * pred_ld + c]) - t;
+    num += d * d;
+    den += t * t;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    num += __shfl_xor(num, o);
+    den += __shfl_xor(den, o);
+  }
+  __shared__ double sh[2][4];
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sh[0][wv] = num;
+    sh[1][wv] = den;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nb = gridDim.x;
+    work[(static_cast<int64_t>(b) * nb + blockIdx.x) * 2 + 0] = sh[0][0] + sh[0][1] + sh[0][2] + sh[0][3];
+    work[(static_cast<int64_t>(b) * nb + blockIdx.x) * 2 + 1] = sh[1][0] + sh[1][1] + sh[1][2] + sh[1][3];
+  }
+}
+
+// one thread per sample folds its partials; thread 0 then forms the loss
+__global__ void rel_l2_final_kernel(int B, int nb, double* __restrict__ work, double* __restrict__ loss,
+                                    double* __restrict__ per_sample) {
+  __shared__ double rel2[1024];
+  for (int b = threadIdx.x; b < B; b += blockDim.x) {
+    double num = 0.0, den = 0.0;
+    for (int k = 0; k < nb; ++k) {
+      num += work[(static_cast<int64_t>(b) * nb + k) * 2 + 0];
+      den += work[(static_cast<int64_t>(b) * nb + k) * 2 + 1];
+    }
+    // folded (num, den) of sample b go to the front of the workspace
+    work[2 * static_cast<int64_t>(B) * nb + 2 * b + 0] = num;
+    work[2 * static_cast<int64_t>(B) * nb + 2 * b + 1] = den;
+    const double r = den > 0.0 ? num / den : 0.0;
+    if (b < 1024) rel2[b] = r;
+    if (per_sample) per_sample[b] = sqrt(r);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int b = 0; b < B && b < 1024; ++b) s += rel2[b];
+    *loss = s / B;
+  }
+}
+
+__global__ void rel_l2_grad_kernel(int B, int H, int W, int nb, const float* __restrict__ pred, int pred_ld,
+                                   const float* __restrict__ target, const int32_t* __restrict__ idx_t,
+                                   const float* __restrict__ scale, const double* __restrict__ work,
+                                   uint16_t* __restrict__ dpred, int d_ld) {
+  const int64_t HW = static_cast<int64_t>(H) * W;
+  const int64_t total = B * HW * d_ld;
+  QNN_GRID_STRIDE(i, total) {
+    const int c = static_cast<int>(i % d_ld);
+    const int64_t p = i / d_ld;
+    const int b = static_cast<int>(p / HW);
+    const int64_t s = p - b * HW;
+    float g = 0.0f;
+    if (c < 6) {
+      const double den = work[2 * static_cast<int64_t>(B) * nb + 2 * b + 1];
+      const double inv = 1.0 / static_cast<double>(scale ? scale[b] : 1.0f);
+      const double t = static_cast<double>(target[((idx_t ? idx_t[b] : b) * 6 + c) * HW + s]) * inv;
+      const double d = static_cast<double>(pred[p * pred_ld + c]) - t;
+      g = den > 0.0 ? static_cast<float>(2.0 * d / (den * B)) : 0.0f;
+    }
+    dpred[i] = f2bf(g);
+  }
+}
+
+__global__ void adam_kernel(int64_t n, float* __restrict__ p, float* __restrict__ m, float* __restrict__ v,
+                            const float* __restrict__ g, uint16_t* __restrict__ pb, float lr, float b1,
+                            float b2, float eps, float c1, float c2) {
+  QNN_GRID_STRIDE(i, n) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float pi = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    p[i] = pi;
+    if (pb) pb[i] = f2bf(pi);
+  }
+}
+
+__global__ void __launch_bounds__(256) compare_kernel(int64_t m, const float* __restrict__ a, const float* __restrict__ r,
+                                                      double* __restrict__ rel, double* __restrict__ en) {
+  const int b = blockIdx.x;
+  const float* ab = a + b * m;
+  const float* rb = r + b * m;
+  double dd = 0.0, aa = 0.0, rr = 0.0;
+  for (int64_t i = threadIdx.x; i < m; i += blockDim.x) {
+    const double x = ab[i], y = rb[i];
+    dd += (x - y) * (x - y);
+    aa += x * x;
+    rr += y * y;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    dd += __shfl_xor(dd, o);
+    aa += __shfl_xor(aa, o);
+    rr += __shfl_xor(rr, o);
+  }
+  __shared__ double sh[3][4];
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sh[0][wv] = dd;
+    sh[1][wv] = aa;
+    sh[2][wv] = rr;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    dd = sh[0][0] + sh[0][1] + sh[0][2] + sh[0][3];
+    aa = sh[1][0] + sh[1][1] + sh[1][2] + sh[1][3];
+    rr = sh[2][0] + sh[2][1] + sh[2][2] + sh[2][3];
+    rel[b] = rr > 0.0 ? sqrt(dd / rr) : sqrt(dd);
+    en[b] = rr > 0.0 ? fabs(aa - rr) / rr : aa;
+  }
+}
+
+__global__ void to_bf16_kernel(int64_t n, const float* __restrict__ x, uint16_t* __restrict__ y) {
+  QNN_GRID_STRIDE(i, n) { y[i] = f2bf(x[i]); }
+}
+
+int grid_for(int64_t n) {
+  int64_t g = (n + 255) / 256;
+  if (g > 16384) g = 16384;
+  return static_cast<int>(g < 1 ? 1 : g);
+}
+
+int launched(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    set_error("qnn: %s: %s", what, hipGetErrorString(e));
+    return QNN_EDEVICE;
+  }
+  return QNN_OK;
+}
+
+int bad(const char* what) {
+  set_error("qnn: %s", what);
+  return QNN_EINVAL;
+}
+
+}  // namespace qnn
+
+using namespace qnn;
+
+extern "C" {
+
+int qnn_conv3x3_fwd(int32_t B, int32_t H, int32_t W, const uint16_t* x, int32_t c_in, const uint16_t* w,
+                    const float* bias, int32_t c_out, int32_t act, void* y, int32_t y_fp32, int32_t y_ld,
+                    int32_t c_store, void* hip_stream) {
+  if (B < 1 || H < 1 || W < 1 || !x || !w || !y) return bad("conv3x3_fwd: bad size or null pointer");
+  if (c_in < 16 || c_in % 16 || c_out < 32 || c_out % 32) return bad("conv3x3_fwd: c_in % 16, c_out % 32");
+  if (c_store < 1 || c_store > c_out || y_ld < c_store) return bad("conv3x3_fwd: bad c_store / y_ld");
+  if (act != QNN_ACT_NONE && act != QNN_ACT_LEAKY) return bad("conv3x3_fwd: unknown activation");
+  const int64_t P64 = static_cast<int64_t>(B) * H * W;
+  if (P64 * (c_in > y_ld ? c_in : y_ld) >= (int64_t{1} << 31)) return bad("conv3x3_fwd: tensor too large");
+  const int P = static_cast<int>(P64);
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const int nt = (c_out % 64 == 0) ? 2 : 1;
+  dim3 grid((P + 127) / 128, c_out / (32 * nt));
+  if (nt == 2) {
+    if (y_fp32) hipLaunchKernelGGL((conv_fwd_kernel<2, true>), grid, dim3(256), 0, st, P, H, W, x, c_in, w, bias, act, y, y_ld, c_store);
+    else hipLaunchKernelGGL((conv_fwd_kernel<2, false>), grid, dim3(256), 0, st, P, H, W, x, c_in, w, bias, act, y, y_ld, c_store);
+  } else {
+    if (y_fp32) hipLaunchKernelGGL((conv_fwd_kernel<1, true>), grid, dim3(256), 0, st, P, H, W, x, c_in, w, bias, act, y, y_ld, c_store);
+    else hipLaunchKernelGGL((conv_fwd_kernel<1, false>), grid, dim3(256), 0, st, P, H, W, x, c_in, w, bias, act, y, y_ld, c_store);
+  }
+  return launched("conv3x3_fwd");
+}
+
+int qnn_conv3x3_flip(const uint16_t* w, int32_t c_out, int32_t c_in, uint16_t* wt, void* hip_stream) {
+  if (!w || !wt || c_out < 1 || c_in < 1) return bad("conv3x3_flip: bad size or null pointer");
+  const int64_t n = static_cast<int64_t>(c_out) * 9 * c_in;
+  hipLaunchKernelGGL(flip_kernel, dim3(grid_for(n)), dim3(256), 0, static_cast<hipStream_t>(hip_stream), w, c_out, c_in, wt);
+  return launched("conv3x3_flip");
+}
+
+int64_t qnn_wgrad_work_floats(int32_t B, int32_t H, int32_t W, int32_t c_in, int32_t c_out) {
+  const int64_t P = static_cast<int64_t>(B) * H * W;
+  const int64_t nsplit = (P + kWgradPixelsPerBlock - 1) / kWgradPixelsPerBlock;
+  return nsplit * c_out * (9 * static_cast<int64_t>(c_in) + 1);
+}
+
+int qnn_conv3x3_wgrad(int32_t B, int32_t H, int32_t W, const uint16_t* x, int32_t c_in, const uint16_t* dy,
+                      int32_t c_out, float* dw, float* dbias, float* work, void* hip_stream) {
+  if (B < 1 || H < 1 || W < 1 || !x || !dy || !dw || !work) return bad("conv3x3_wgrad: bad size or null pointer");
+  if (c_in < 16 || c_in % 16 || c_out < 32 || c_out % 32) return bad("conv3x3_wgrad: c_in % 16, c_out % 32");
+  const int64_t P64 = static_cast<int64_t>(B) * H * W;
+  if (P64 * (c_in > c_out ? c_in : c_out) >= (int64_t{1} << 31)) return bad("conv3x3_wgrad: tensor too large");
+  const int P = static_cast<int>(P64);
+  const int nsplit = (P + kWgradPixelsPerBlock - 1) / kWgradPixelsPerBlock;
+  const int K = 9 * c_in;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  float* part = work;
+  float* bpart = work + static_cast<int64_t>(nsplit) * c_out * K;
+  dim3 grid(c_out / 32, (K + 31) / 32, nsplit);
+  if (W % 16 == 0)
+    hipLaunchKernelGGL((wgrad_kernel<true>), grid, dim3(256), 0, st, P, H, W, x, c_in, dy, c_out, part, dbias ? bpart : nullptr);
+  else
+    hipLaunchKernelGGL((wgrad_kernel<false>), grid, dim3(256), 0, st, P, H, W, x, c_in, dy, c_out, part, dbias ? bpart : nullptr);
+  const int64_t n = static_cast<int64_t>(c_out) * K;
+  hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(grid_for(n)), dim3(256), 0, st, part, nsplit, n, dw);
+  if (dbias) hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(grid_for(c_out)), dim3(256), 0, st, bpart, nsplit, static_cast<int64_t>(c_out), dbias);
+  return launched("conv3x3_wgrad");
+}
+
+int qnn_leaky_bwd(int64_t n, const uint16_t* y, const uint16_t* dy, uint16_t* dz, void* hip_stream) {
+  if (n < 0 || !y || !dy || !dz) return bad("leaky_bwd: bad size or null pointer");
+  hipLaunchKernelGGL(leaky_bwd_kernel, dim3(grid_for(n)), dim3(256), 0, static_cast<hipStream_t>(hip_stream), n, y, dy, dz);
+  return launched("leaky_bwd");
+}
+
+int qnn_add(int64_t n, const uint16_t* a, const uint16_t* b, uint16_t* y, void* hip_stream) {
+  if (n < 0 || !a || !b || !y) return bad("add: bad size or null pointer");
+  hipLaunchKernelGGL(add_kernel, dim3(grid_for(n)), dim3(256), 0, static_cast<hipStream_t>(hip_stream), n, a, b, y);
+  return launched("add");
+}
+
+int qnn_avgpool2(int32_t B, int32_t H, int32_t W, int32_t C, const uint16_t* x, uint16_t* y, void* hip_stream) {
+  if (B < 1 || H < 2 || W < 2 || (H | W) & 1 || C < 1 || !x || !y) return bad("avgpool2: bad size or null pointer");
+  const int64_t n = static_cast<int64_t>(B) * (H / 2) * (W / 2) * C;
+  hipLaunchKernelGGL(avgpool2_kernel, dim3(grid_for(n)), dim3(256), 0, static_cast<hipStream_t>(hip_stream), B, H, W, C, x, y);
+  return launched("avgpool2");
+}
+
+int qnn_avgpool2_bwd(int32_t B, int32_t H, int32_t W, int32_t C, const uint16_t* dy, uint16_t* dx, int32_t accumulate,
+                     void* hip_stream) {
+  if (B < 1 || H < 2 || W < 2 || (H | W) & 1 || C < 1 || !dy || !dx) return bad("avgpool2_bwd: bad size or null pointer");
+  const int64_t n = static_cast<int64_t>(B) * H * W * C;
+  hipLaunchKernelGGL(avgpool2_bwd_kernel, dim3(grid_for(n)), dim3(256), 0, static_cast<hipStream_t>(hip_stream), B, H, W, C, dy, dx, accumulate);
+  return launched("avgpool2_bwd");
+}
+
+int qnn_upsample2(int32_t B, int32_t h, int32_t w, int32_t C, const uint16_t* x, uint16_t* y, void* hip_stream) {
+  if (B < 1 || h < 1 || w < 1 || C < 1 || !x || !y) return bad("upsample2: bad size or null pointer");
+  const int64_t n = static_cast<int64_t>(B) * 4 * h * w * C;
+  hipLaunchKernelGGL(upsample2_kernel, dim3(grid_for(n)), dim3(256), 0, static_cast<hipStream_t>(hip_stream), B, h, w, C, x, y);
+  return launched("upsample2");
+}
+
+int qnn_upsample2_bwd(int32_t B, int32_t h, int32_t w, int32_t C, const uint16_t* dy, uint16_t* dx, void* hip_stream) {
+  if (B < 1 || h < 1 || w < 1 || C < 1 || !dy || !dx) return bad("upsample2_bwd: bad size or null pointer");
+  const int64_t n = static_cast<int64_t>(B) * h * w * C;
+  hipLaunchKernelGGL(upsample2_bwd_kernel, dim3(grid_for(n)), dim3(256), 0, static_cast<hipStream_t>(hip_stream), B, h, w, C, dy, dx);
+  return launched("upsample2_bwd");
+}
+
+int qnn_absmax(int32_t B, int32_t H, int32_t W, const float* q, const int32_t* idx, float* scale, void* hip_stream) {
+  if (B < 1 || H < 1 || W < 1 || !q || !scale) return bad("absmax: bad argument");
+  hipLaunchKernelGGL(absmax_kernel, dim3(B), dim3(256), 0, static_cast<hipStream_t>(hip_stream), H, W, q, idx, scale);
+  return launched("absmax");
+}
+
+int qnn_pack_input(int32_t B, int32_t H, int32_t W, const float* q, const int32_t* idx_q, const float* n,
+                   const int32_t* idx_n, const float* scale, float n_shift, float n_scale, int32_t shift,
+                   uint16_t* x, void* hip_stream) {
+  if (B < 1 || H < 1 || W < 1 || !q || !n || !scale || !x || !(n_scale != 0.0f)) return bad("pack_input: bad argument");
+  const int64_t total = static_cast<int64_t>(B) * H * W * kInCh;
+  hipLaunchKernelGGL(pack_input_kernel, dim3(grid_for(total)), dim3(256), 0, static_cast<hipStream_t>(hip_stream), B, H, W, q, idx_q, n, idx_n, scale, n_shift, n_scale, shift, x);
+  return launched("pack_input");
+}
+
+int qnn_unpack_output(int32_t B, int32_t H, int32_t W, const float* y, int32_t y_ld, const float* scale, float* q,
+                      void* hip_stream) {
+  if (B < 1 || H < 1 || W < 1 || !y || !scale || !q || y_ld < 6) return bad("unpack_output: bad argument");
+  const int64_t total = static_cast<int64_t>(B) * 6 * H * W;
+  hipLaunchKernelGGL(unpack_output_kernel, dim3(grid_for(total)), dim3(256), 0, static_cast<hipStream_t>(hip_stream), B, H, W, y, y_ld, scale, q);
+  return launched("unpack_output");
+}
+
+int qnn_rel_l2(int32_t B, int32_t H, int32_t W, const float* pred, int32_t pred_ld, const float* target,
+               const int32_t* idx_t, const float* scale, uint16_t* dpred, int32_t d_ld, double* loss_out,
+               double* per_sample, double* work, void* hip_stream) {
+  if (B < 1 || B > 1024 || H < 1 || W < 1 || !pred || !target || !loss_out || !work || pred_ld < 6)
+    return bad("rel_l2: bad argument");
+  if (dpred && d_ld < 6) return bad("rel_l2: d_ld < 6");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const int nb = 31;   // partial blocks per sample: 2*B*nb + 2*B <= 64*B doubles of work
+  hipLaunchKernelGGL(rel_l2_partial_kernel, dim3(nb, B), dim3(256), 0, st, H, W, pred, pred_ld, target, idx_t, scale, work);
+  hipLaunchKernelGGL(rel_l2_final_kernel, dim3(1), dim3(256), 0, st, B, nb, work, loss_out, per_sample);
+  if (dpred) {
+    const int64_t total = static_cast<int64_t>(B) * H * W * d_ld;
+    hipLaunchKernelGGL(rel_l2_grad_kernel, dim3(grid_for(total)), dim3(256), 0, st, B, H, W, nb, pred, pred_ld, target, idx_t, scale, work, dpred, d_ld);
+  }
+  return launched("rel_l2");
+}
+
+int qnn_adam(int64_t n, float* p, float* m, float* v, const float* g, uint16_t* p_bf16, float lr, float b1, float b2,
+             float eps, int32_t t, void* hip_stream) {
+  if (n < 0 || !p || !m || !v || !g || t < 1) return bad("adam: bad argument");
+  const float c1 = 1.0f - powf(b1, static_cast<float>(t));
+  const float c2 = 1.0f - powf(b2, static_cast<float>(t));
+  hipLaunchKernelGGL(adam_kernel, dim3(grid_for(n)), dim3(256), 0, static_cast<hipStream_t>(hip_stream), n, p, m, v, g, p_bf16, lr, b1, b2, eps, c1, c2);
+  return launched("adam");
+}
+
+int qnn_compare(int32_t B, int64_t m, const float* a, const float* r, double* rel, double* en, void* hip_stream) {
+  if (B < 1 || m < 1 || !a || !r || !rel || !en) return bad("compare: bad argument");
+  hipLaunchKernelGGL(compare_kernel, dim3(B), dim3(256), 0, static_cast<hipStream_t>(hip_stream), m, a, r, rel, en);
+  return launched("compare");
+}
+
+int qnn_to_bf16(int64_t n, const float* x, uint16_t* y, void* hip_stream) {
+  if (n < 0 || !x || !y) return bad("to_bf16: bad argument");
+  hipLaunchKernelGGL(to_bf16_kernel, dim3(grid_for(n)), dim3(256), 0, static_cast<hipStream_t>(hip_stream), n, x, y);
+  return launched("to_bf16");
+}
+
+}  // extern "C"

@@ -72,6 +72,9 @@ _SIGNATURES = {
     "qla_step": ([ctypes.c_void_p, ctypes.c_int64], ctypes.c_int),
     "qla_energy": ([ctypes.c_void_p, ctypes.POINTER(Diag)], ctypes.c_int),
     "qla_fields": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
+    "qla_fields_at": ([ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32],
+                      ctypes.c_int),
+    "qla_load_at": ([ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32], ctypes.c_int),
     "qla_get_launch": ([ctypes.c_void_p, ctypes.POINTER(Launch)], ctypes.c_int),
     "qla_set_launch": ([ctypes.c_void_p, ctypes.POINTER(Launch)], ctypes.c_int),
     "qla_state": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
@@ -166,6 +169,14 @@ def qla_energy(ctx, count: int = 1):
 
 def qla_fields(ctx, dst: int, what: int, dst_is_host: bool) -> None:
     _check(lib().qla_fields(ctx, ctypes.c_void_p(dst), int(what), int(bool(dst_is_host))))
+
+
+def qla_fields_at(ctx, index: int, dst: int, what: int, dst_is_host: bool) -> None:
+    _check(lib().qla_fields_at(ctx, int(index), ctypes.c_void_p(dst), int(what), int(bool(dst_is_host))))
+
+
+def qla_load_at(ctx, index: int, src: int, src_is_host: bool) -> None:
+    _check(lib().qla_load_at(ctx, int(index), ctypes.c_void_p(src), int(bool(src_is_host))))
 
 
 def qla_get_launch(ctx) -> Dict[str, int]:
@@ -272,9 +283,14 @@ class Batch:
         self.device = torch.device(device)
         self.n, self.q, self.q_pong, self.shapes = [], [], [], []
         insts = []
+        def dev_tensor(a):
+            if isinstance(a, torch.Tensor):
+                return a.to(self.device, torch.float32).contiguous()
+            return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32)).to(self.device)
+
         for n, q0, d in zip(ns, q0s, deltas):
-            n_t = torch.as_tensor(np.ascontiguousarray(n, dtype=np.float32)).to(self.device)
-            q_t = torch.as_tensor(np.ascontiguousarray(q0, dtype=np.float32)).to(self.device).clone()
+            n_t = dev_tensor(n)
+            q_t = dev_tensor(q0).clone()
             if n_t.dim() != 3 or n_t.shape[0] != 3 or tuple(q_t.shape) != (6,) + tuple(n_t.shape[1:]):
                 raise ValueError("expected n of shape (3, ny, nx) and q0 of shape (6, ny, nx)")
             ny, nx = int(n_t.shape[1]), int(n_t.shape[2])

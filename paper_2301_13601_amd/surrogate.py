@@ -1,0 +1,509 @@
+"""Convolutional surrogate of K whole QLA steps, trained on the library's own
+runs, with plain QLA as its judge and fallback.
+
+The network maps (Q(t), n) -> Q(t + K) on a periodic lattice (K = 256 by
+default). QLA is linear in Q for fixed n, so each sample is divided by its
+largest |q| on the way in and multiplied back on the way out. Architecture:
+a four-level U-net with additive skips,
+
+  level l (l = 0..3, resolution /2^l): two 3x3 convs to C_l = 32, 64, 128, 128
+  bottleneck (resolution /16): four 3x3 convs at 128 channels
+  decoder level l: 2x upsample, 3x3 conv to C_l, add the level-l encoder
+                   output, 3x3 conv
+  output: 3x3 conv to 6 channels (FP32), no activation
+
+The input carries, besides Q(t) and n, four copies of Q(t) displaced by the
+distance a vacuum wave covers in one jump (delta*K cells) along +x, -x, +y
+and -y, so that the skip paths see detail where waves moving along an axis
+end up. Circular padding everywhere (the lattice is periodic), leaky ReLU
+(slope 1/8), BF16 activations and weights, FP32 accumulation, FP32 master
+weights and Adam. Its receptive field is about +-125 cells, beyond the
+~77 cells a vacuum pulse travels in 256 steps at delta = 0.3. Every
+arithmetic step runs in the HIP kernels of include/qla_nn.h; torch only
+holds device memory.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+import time
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+from . import qla, qnn, scenes
+
+LEVELS = (32, 64, 128, 128)
+BOTTLENECK = 4
+IN_CH = 48            # 6 field + 3 index + 4x6 displaced field channels, padded to 48
+LIVE_IN = 33          # channels that carry data
+OUT_CH = 32           # output conv width (6 stored)
+N_SHIFT, N_SCALE = 2.0, 1.0
+
+
+@dataclasses.dataclass
+class Conv:
+    name: str
+    c_in: int
+    c_out: int
+    act: int
+    level: int
+    w_off: int = 0    # offsets into the flat parameter buffer
+    b_off: int = 0
+
+    @property
+    def n_w(self) -> int:
+        return self.c_out * 9 * self.c_in
+
+
+def layer_specs() -> List[Conv]:
+    L = qnn.QNN_ACT_LEAKY
+    specs = [Conv("e0a", IN_CH, LEVELS[0], L, 0), Conv("e0", LEVELS[0], LEVELS[0], L, 0)]
+    for l in range(1, 4):
+        specs += [Conv(f"e{l}a", LEVELS[l - 1], LEVELS[l], L, l), Conv(f"e{l}", LEVELS[l], LEVELS[l], L, l)]
+    for k in range(BOTTLENECK):
+        specs.append(Conv(f"b{k}", LEVELS[3], LEVELS[3], L, 4))
+    up_in = LEVELS[3]
+    for l in (3, 2, 1, 0):
+        specs += [Conv(f"d{l}a", up_in, LEVELS[l], L, l), Conv(f"d{l}", LEVELS[l], LEVELS[l], L, l)]
+        up_in = LEVELS[l]
+    specs.append(Conv("out", LEVELS[0], OUT_CH, qnn.QNN_ACT_NONE, 0))
+    off = 0
+    for s in specs:
+        s.w_off = off
+        off += s.n_w
+        s.b_off = off
+        off += s.c_out
+    return specs
+
+
+def macs_per_pixel() -> float:
+    """Multiply-accumulates of one forward pass per full-resolution pixel."""
+    return sum(s.n_w / 4 ** s.level for s in layer_specs())
+
+
+class UNet:
+    """Parameters, Adam state and activation buffers of the surrogate."""
+
+    def __init__(self, device="cuda:0", seed: int = 0, stream=None, shift: int = 77):
+        import torch
+
+        # displacement of the shifted input copies: the distance (cells) a
+        # vacuum wave travels over one jump, delta * K (0.3 * 256 = 76.8)
+        self.shift = int(shift)
+        self.torch = torch
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.specs = layer_specs()
+        self.by_name = {s.name: s for s in self.specs}
+        self.n_params = self.specs[-1].b_off + self.specs[-1].c_out
+        rng = np.random.default_rng(seed)
+        p = np.zeros(self.n_params, dtype=np.float32)
+        for s in self.specs:
+            fan_in = 9 * (LIVE_IN if s.name == "e0a" else s.c_in)
+            std = math.sqrt(2.0 / fan_in) * (0.1 if s.name == "out" else 1.0)
+            w = rng.standard_normal((s.c_out, 9, s.c_in)).astype(np.float32) * std
+            if s.name == "e0a":
+                w[:, :, LIVE_IN:] = 0.0
+            p[s.w_off:s.w_off + s.n_w] = w.ravel()
+        f32 = dict(dtype=torch.float32, device=self.device)
+        self.p = torch.as_tensor(p).to(self.device)
+        self.m = torch.zeros(self.n_params, **f32)
+        self.v = torch.zeros(self.n_params, **f32)
+        self.g = torch.zeros(self.n_params, **f32)
+        self.pb = torch.empty(self.n_params, dtype=torch.bfloat16, device=self.device)
+        self.flipped = {s.name: torch.empty(s.n_w, dtype=torch.bfloat16, device=self.device)
+                        for s in self.specs}
+        qnn.qnn_to_bf16(self.n_params, self.p, self.pb, self.stream)
+        self.t = 0
+        self.geom = None
+        self.trainable = False
+
+    # -- parameter views ----------------------------------------------------
+    def w(self, s: Conv):
+        return self.pb[s.w_off:s.w_off + s.n_w]
+
+    def b(self, s: Conv):
+        return self.p[s.b_off:s.b_off + s.c_out]
+
+    def dw(self, s: Conv):
+        return self.g[s.w_off:s.w_off + s.n_w]
+
+    def db(self, s: Conv):
+        return self.g[s.b_off:s.b_off + s.c_out]
+
+    def state(self) -> Dict[str, np.ndarray]:
+        return {"p": self.p.cpu().numpy(), "m": self.m.cpu().numpy(), "v": self.v.cpu().numpy(),
+                "t": np.array(self.t)}
+
+    def load(self, st: Dict[str, np.ndarray]) -> None:
+        torch = self.torch
+        self.p.copy_(torch.as_tensor(st["p"]))
+        self.m.copy_(torch.as_tensor(st["m"]))
+        self.v.copy_(torch.as_tensor(st["v"]))
+        self.t = int(st["t"])
+        qnn.qnn_to_bf16(self.n_params, self.p, self.pb, self.stream)
+
+    # -- buffers ---------------------------------------------------------------
+    def _buffers(self, B: int, H: int, W: int, train: bool = False) -> None:
+        if self.geom == (B, H, W) and (self.trainable or not train):
+            return
+        self.trainable = train
+        if H % 16 or W % 16:
+            raise ValueError("lattice sides must be multiples of 16")
+        torch = self.torch
+        bf = dict(dtype=torch.bfloat16, device=self.device)
+        self.geom = (B, H, W)
+        self.act, self.grad = {}, {}
+
+        def px(level):
+            return B * (H >> level) * (W >> level)
+
+        self.act["x"] = torch.empty(px(0) * IN_CH, **bf)
+        for s in self.specs:
+            if s.name == "out":
+                self.act["out"] = torch.empty(px(0) * OUT_CH, dtype=torch.float32, device=self.device)
+            else:
+                self.act[s.name] = torch.empty(px(s.level) * s.c_out, **bf)
+        for l in range(1, 5):
+            self.act[f"p{l}"] = torch.empty(px(l) * LEVELS[l - 1], **bf)
+        up_c = LEVELS[3]
+        for l in (3, 2, 1, 0):
+            self.act[f"u{l}"] = torch.empty(px(l) * up_c, **bf)
+            self.act[f"h{l}"] = torch.empty(px(l) * LEVELS[l], **bf)
+            up_c = LEVELS[l]
+        if train:
+            # gradients of every activation, and the activation-gradient
+            # product of each leaky ReLU
+            for name, t in self.act.items():
+                if name not in ("x", "out"):
+                    self.grad[name] = torch.empty_like(t)
+            self.grad["out"] = torch.empty(px(0) * OUT_CH, **bf)
+            self.dz = {s.name: torch.empty(px(s.level) * s.c_out, **bf) for s in self.specs}
+            wk = max(qnn.qnn_wgrad_work_floats(B, H >> s.level, W >> s.level, s.c_in, s.c_out)
+                     for s in self.specs)
+            self.wwork = torch.empty(wk, dtype=torch.float32, device=self.device)
+        self.scale = torch.empty(B, dtype=torch.float32, device=self.device)
+        self.loss = torch.zeros(1, dtype=torch.float64, device=self.device)
+        self.per_sample = torch.zeros(B, dtype=torch.float64, device=self.device)
+        self.lwork = torch.zeros(64 * B, dtype=torch.float64, device=self.device)
+
+    # -- forward -----------------------------------------------------------------
+    def _conv(self, s: Conv, x, B, H, W, y=None, fp32=False):
+        h, w = H >> s.level, W >> s.level
+        y = self.act[s.name] if y is None else y
+        if fp32:
+            qnn.qnn_conv3x3_fwd(B, h, w, x, s.c_in, self.w(s), self.b(s), s.c_out, s.act, y, 1, OUT_CH, 6,
+                                self.stream)
+        else:
+            qnn.qnn_conv3x3_fwd(B, h, w, x, s.c_in, self.w(s), self.b(s), s.c_out, s.act, y, 0, s.c_out,
+                                s.c_out, self.stream)
+        return y
+
+    def forward_packed(self, B: int, H: int, W: int):
+        """Run the network on self.act["x"]; returns the FP32 output [P][32]."""
+        A, S = self.act, self.by_name
+        st = self.stream
+        x = A["x"]
+        for l in range(4):
+            if l > 0:
+                qnn.qnn_avgpool2(B, H >> (l - 1), W >> (l - 1), LEVELS[l - 1], x, A[f"p{l}"], st)
+                x = A[f"p{l}"]
+            x = self._conv(S[f"e{l}a"], x, B, H, W)
+            x = self._conv(S[f"e{l}"], x, B, H, W)
+        qnn.qnn_avgpool2(B, H >> 3, W >> 3, LEVELS[3], x, A["p4"], st)
+        x = A["p4"]
+        for k in range(BOTTLENECK):
+            x = self._conv(S[f"b{k}"], x, B, H, W)
+        up_c = LEVELS[3]
+        for l in (3, 2, 1, 0):
+            qnn.qnn_upsample2(B, H >> (l + 1), W >> (l + 1), up_c, x, A[f"u{l}"], st)
+            d = self._conv(S[f"d{l}a"], A[f"u{l}"], B, H, W)
+            n = B * (H >> l) * (W >> l) * LEVELS[l]
+            qnn.qnn_add(n, d, A[f"e{l}"], A[f"h{l}"], st)
+            x = self._conv(S[f"d{l}"], A[f"h{l}"], B, H, W)
+            up_c = LEVELS[l]
+        return self._conv(S["out"], x, B, H, W, fp32=True)
+
+    def pack(self, B, H, W, q, idx_q, n, idx_n, train=False):
+        """Input tensor from lattice fields (q [N][6][H][W], n [M][3][H][W],
+        int32 index tensors or None); sets the per-sample scales."""
+        self._buffers(B, H, W, train)
+        qnn.qnn_absmax(B, H, W, q, idx_q, self.scale, self.stream)
+        qnn.qnn_pack_input(B, H, W, q, idx_q, n, idx_n, self.scale, N_SHIFT, N_SCALE, self.shift,
+                           self.act["x"], self.stream)
+
+    def predict(self, q, n, out_q, chunk: int = 8):
+        """out_q[b] = network(q[b], n[b]) for lattices q [B][6][H][W] (FP32),
+        in chunks of at most ``chunk`` lattices."""
+        B, _, H, W = q.shape
+        for c0 in range(0, B, chunk):
+            c1 = min(B, c0 + chunk)
+            self.pack(c1 - c0, H, W, q[c0:c1], None, n[c0:c1], None)
+            y = self.forward_packed(c1 - c0, H, W)
+            qnn.qnn_unpack_output(c1 - c0, H, W, y, OUT_CH, self.scale, out_q[c0:c1], self.stream)
+
+    # -- backward ----------------------------------------------------------------
+    def _conv_bwd(self, s: Conv, x_in, dy, B, H, W, dx=None):
+        """Gradients of y = act(conv(x_in)) given dL/dy; returns dL/dx_in
+        (written to dx) unless dx is None."""
+        h, w = H >> s.level, W >> s.level
+        st = self.stream
+        if s.act == qnn.QNN_ACT_LEAKY:
+            dz = self.dz[s.name]
+            qnn.qnn_leaky_bwd(B * h * w * s.c_out, self.act[s.name], dy, dz, st)
+        else:
+            dz = dy
+        qnn.qnn_conv3x3_wgrad(B, h, w, x_in, s.c_in, dz, s.c_out, self.dw(s), self.db(s), self.wwork, st)
+        if dx is not None:
+            qnn.qnn_conv3x3_fwd(B, h, w, dz, s.c_out, self.flipped[s.name], None, s.c_in, qnn.QNN_ACT_NONE,
+                                dx, 0, s.c_in, s.c_in, st)
+        return dx
+
+    def backward(self, B: int, H: int, W: int, dout) -> None:
+        A, G, S = self.act, self.grad, self.by_name
+        st = self.stream
+        for s in self.specs:
+            qnn.qnn_conv3x3_flip(self.w(s), s.c_out, s.c_in, self.flipped[s.name], st)
+        # decoder, top down
+        g = self._conv_bwd(S["out"], A["d0"], dout, B, H, W, G["d0"])
+        for l in (0, 1, 2, 3):
+            # d_l = conv(h_l); h_l = d_la + e_l; d_la = conv(u_l); u_l = up(prev)
+            self._conv_bwd(S[f"d{l}"], A[f"h{l}"], g, B, H, W, G[f"h{l}"])
+            prev = "b3" if l == 3 else f"d{l + 1}"
+            up_c = LEVELS[3] if l == 3 else LEVELS[l + 1]
+            self._conv_bwd(S[f"d{l}a"], A[f"u{l}"], G[f"h{l}"], B, H, W, G[f"u{l}"])
+            qnn.qnn_upsample2_bwd(B, H >> (l + 1), W >> (l + 1), up_c, G[f"u{l}"], G[prev], st)
+            g = G[prev]
+        # bottleneck
+        for k in range(BOTTLENECK - 1, -1, -1):
+            x_in = A["p4"] if k == 0 else A[f"b{k - 1}"]
+            dx = G["p4"] if k == 0 else G[f"b{k - 1}"]
+            self._conv_bwd(S[f"b{k}"], x_in, g, B, H, W, dx)
+            g = dx
+        # encoder, bottom up: e_l's gradient is dL/dh_l (from the skip) plus
+        # the pooled path, accumulated into G[h_l]
+        for l in (3, 2, 1, 0):
+            qnn.qnn_avgpool2_bwd(B, H >> l, W >> l, LEVELS[l], g, G[f"h{l}"], 1, st)
+            self._conv_bwd(S[f"e{l}"], A[f"e{l}a"], G[f"h{l}"], B, H, W, G[f"e{l}a"])
+            x_in = A["x"] if l == 0 else A[f"p{l}"]
+            dx = None if l == 0 else G[f"p{l}"]
+            self._conv_bwd(S[f"e{l}a"], x_in, G[f"e{l}a"], B, H, W, dx)
+            g = dx
+
+    def adam(self, lr: float, b1=0.9, b2=0.999, eps=1e-8) -> None:
+        self.t += 1
+        qnn.qnn_adam(self.n_params, self.p, self.m, self.v, self.g, self.pb, lr, b1, b2, eps, self.t, self.stream)
+
+    def train_step(self, q, idx_q, n, idx_n, target, idx_t, B, H, W, lr) -> None:
+        """One optimisation step on B pairs (input q[idx_q], n[idx_n], target
+        target[idx_t]). The loss stays on the device in self.loss."""
+        self.pack(B, H, W, q, idx_q, n, idx_n, train=True)
+        y = self.forward_packed(B, H, W)
+        qnn.qnn_rel_l2(B, H, W, y, OUT_CH, target, idx_t, self.scale, self.grad["out"], OUT_CH, self.loss,
+                       self.per_sample, self.lwork, self.stream)
+        self.backward(B, H, W, self.grad["out"])
+        self.adam(lr)
+
+    def eval_error(self, q, idx_q, n, idx_n, target, idx_t, B, H, W):
+        """Per-sample relative field errors |pred - target| / |target|."""
+        self.pack(B, H, W, q, idx_q, n, idx_n)
+        y = self.forward_packed(B, H, W)
+        qnn.qnn_rel_l2(B, H, W, y, OUT_CH, target, idx_t, self.scale, None, OUT_CH, self.loss, self.per_sample,
+                       self.lwork, self.stream)
+        return self.per_sample.cpu().numpy().copy()
+
+
+# ---------------------------------------------------------------------------
+# Training data: QLA runs generated by the library itself.
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class Dataset:
+    q: object            # device FP32 [runs * snaps][6][L][L]
+    n: object            # device FP32 [runs][3][L][L]
+    runs: int
+    snaps: int
+    L: int
+    K: int
+    seconds: float
+
+    def pairs(self) -> np.ndarray:
+        """(input index, index-profile index, target index) of every pair."""
+        out = []
+        for r in range(self.runs):
+            for s in range(self.snaps - 1):
+                out.append((r * self.snaps + s, r, r * self.snaps + s + 1))
+        return np.asarray(out, dtype=np.int32)
+
+
+def generate(runs: int, seed: int, L: int = 256, K: int = 256, snaps: int = 9, chunk: int = 128,
+             device: str = "cuda:0", stream=None) -> Dataset:
+    """QLA runs of the batched scattering family at L x L (objects, tensors,
+    pulses drawn as in scenes.batch_instance_specs), with the state recorded
+    every K steps (snaps snapshots per run)."""
+    import torch
+
+    dev = torch.device(device)
+    stream = stream if stream is not None else torch.cuda.current_stream(dev)
+    specs = scenes.batch_instance_specs(runs, seed=seed, sides=(L,))
+    qall = torch.empty((runs * snaps, 6, L, L), dtype=torch.float32, device=dev)
+    nall = torch.empty((runs, 3, L, L), dtype=torch.float32, device=dev)
+    t0 = time.perf_counter()
+    for c0 in range(0, runs, chunk):
+        sub = specs[c0:c0 + chunk]
+        scs = [scenes.scene_from_spec(sp, steps=K * (snaps - 1)) for sp in sub]
+        batch = qla.Batch([s.n for s in scs], [s.q for s in scs], [s.delta for s in scs], "eq28", "phys",
+                          device=device, stream=stream)
+        for k, s in enumerate(scs):
+            nall[c0 + k].copy_(batch.n[k].view(3, L, L))
+        for sn in range(snaps):
+            if sn:
+                batch.step(K)
+            for k in range(len(scs)):
+                dst = qall[(c0 + k) * snaps + sn]
+                qla.qla_fields_at(batch.ctx, k, dst.data_ptr(), 0, False)
+        batch.close()
+    torch.cuda.synchronize(dev)
+    return Dataset(qall, nall, runs, snaps, L, K, time.perf_counter() - t0)
+
+
+def train(net: UNet, data: Dataset, steps: int, batch: int = 16, lr: float = 1e-3, seed: int = 0,
+          log_every: int = 100, log=None) -> List[Dict]:
+    """Adam on random pairs of ``data`` with a cosine learning-rate decay."""
+    import torch
+
+    rng = np.random.default_rng(seed)
+    pairs = data.pairs()
+    hist = []
+    dev = net.device
+    for it in range(steps):
+        sel = pairs[rng.integers(0, len(pairs), batch)]
+        idx = torch.as_tensor(sel.T.copy()).to(dev)
+        rate = lr * 0.5 * (1.0 + math.cos(math.pi * it / max(steps, 1)))
+        net.train_step(data.q, idx[0], data.n, idx[1], data.q, idx[2], batch, data.L, data.L, max(rate, lr * 0.02))
+        if log_every and (it % log_every == 0 or it == steps - 1):
+            rec = {"step": it, "loss": float(net.loss.item()), "lr": rate}
+            hist.append(rec)
+            if log:
+                log(rec)
+    return hist
+
+
+def evaluate(net: UNet, data: Dataset, batch: int = 16) -> np.ndarray:
+    """Relative field error of the network on every pair of ``data``."""
+    import torch
+
+    pairs = data.pairs()
+    errs = []
+    for c0 in range(0, len(pairs), batch):
+        sel = pairs[c0:c0 + batch]
+        idx = torch.as_tensor(sel.T.copy()).to(net.device)
+        errs.append(net.eval_error(data.q, idx[0], data.n, idx[1], data.q, idx[2], len(sel), data.L, data.L))
+    return np.concatenate(errs)
+
+
+# ---------------------------------------------------------------------------
+# Surrogate-accelerated sweep with QLA checks and fallback.
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class SweepResult:
+    steps: int
+    jumps: int
+    unchecked: int       # jumps taken from the surrogate
+    checks: int          # jumps also run by QLA (the QLA result is kept)
+    rejected: int        # checks whose surrogate error exceeded the tolerance
+    fell_back: bool
+    seconds: float
+    max_check_error: float
+    max_check_energy: float
+
+
+def sweep(net: UNet, n_list: Sequence, q_list: Sequence, delta: float, total_steps: int, K: int = 256,
+          window: int = 0, check_every: int = 4, tol: float = 1e-3, max_rejects: int = 1,
+          device: str = "cuda:0") -> Tuple[SweepResult, List[np.ndarray]]:
+    """Advance lattices (all the same size, sides multiples of 16) by
+    ``total_steps`` QLA steps, replacing runs of K steps by surrogate jumps.
+
+    Every ``check_every``-th jump is also run by plain QLA from the saved
+    pre-jump state: the QLA result is kept, and if the surrogate's relative
+    field error or relative energy error against it exceeds ``tol`` on any
+    lattice the check counts as rejected; after ``max_rejects`` rejections
+    the sweep falls back to plain QLA for the rest of the run. Other jumps
+    take the surrogate's prediction. ``window`` plain QLA steps follow each
+    jump. Returns the result record and the final states."""
+    import torch
+
+    dev = torch.device(device)
+    stream = net.stream
+    B = len(n_list)
+    _, H, W = np.asarray(n_list[0]).shape
+    batch = qla.Batch(list(n_list), list(q_list), [delta] * B, "eq28", "phys", device=device, stream=stream)
+    cur = torch.empty((B, 6, H, W), dtype=torch.float32, device=dev)
+    pred = torch.empty_like(cur)
+    ref = torch.empty_like(cur)
+    n_dev = torch.stack([t.view(3, H, W) for t in batch.n])
+    rel = torch.empty(B, dtype=torch.float64, device=dev)
+    en = torch.empty(B, dtype=torch.float64, device=dev)
+
+    def export(dst):
+        for k in range(B):
+            qla.qla_fields_at(batch.ctx, k, dst[k].data_ptr(), 0, False)
+
+    jumps = unchecked = checks = rejected = 0
+    max_err = max_en = 0.0
+    fell_back = False
+    t = 0
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    while t < total_steps:
+        if fell_back or t + K > total_steps:
+            batch.step(total_steps - t)
+            t = total_steps
+            break
+        export(cur)
+        net.predict(cur, n_dev, pred)
+        jumps += 1
+        if jumps % check_every == 0:
+            checks += 1
+            batch.step(K)                        # QLA from the saved pre-jump state
+            export(ref)
+            qnn.qnn_compare(B, 6 * H * W, pred, ref, rel, en, stream)
+            r, e = rel.cpu().numpy(), en.cpu().numpy()
+            max_err, max_en = max(max_err, float(r.max())), max(max_en, float(e.max()))
+            if float(r.max()) > tol or float(e.max()) > tol:
+                rejected += 1
+                fell_back = rejected >= max_rejects
+        else:
+            unchecked += 1
+            for k in range(B):
+                qla.qla_load_at(batch.ctx, k, pred[k].data_ptr(), False)
+        t += K
+        if window and not fell_back and t < total_steps:
+            w = min(window, total_steps - t)
+            batch.step(w)
+            t += w
+    torch.cuda.synchronize(dev)
+    secs = time.perf_counter() - t0
+    finals = batch.fields("Q")
+    batch.close()
+    return SweepResult(total_steps, jumps, unchecked, checks, rejected, fell_back, secs, max_err, max_en), finals
+
+
+def plain(n_list: Sequence, q_list: Sequence, delta: float, total_steps: int, device: str = "cuda:0",
+          stream=None) -> Tuple[float, List[np.ndarray]]:
+    """Plain QLA for the same lattices: (seconds, final states)."""
+    import torch
+
+    dev = torch.device(device)
+    batch = qla.Batch(list(n_list), list(q_list), [delta] * len(n_list), "eq28", "phys", device=device,
+                      stream=stream)
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    batch.step(total_steps)
+    torch.cuda.synchronize(dev)
+    secs = time.perf_counter() - t0
+    finals = batch.fields("Q")
+    batch.close()
+    return secs, finals

@@ -1,7 +1,8 @@
 """CPU-side checks of the C ABI: the library loads, exports every entry
-point include/qla.h declares, and rejects bad arguments before touching a
-device."""
+point the headers under include/ declare, and rejects bad arguments before
+touching a device."""
 import ctypes
+import glob
 import os
 import re
 
@@ -9,6 +10,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "qla.h")
+HEADERS = sorted(glob.glob(os.path.join(ROOT, "include", "*.h")))
 
 
 @pytest.fixture(scope="module")
@@ -20,10 +22,12 @@ def qla():
     return q
 
 
-def declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(qla_[a-z_]+)\s*\(", text)))
+def declared_functions(headers=(HEADER,), prefix="qla_"):
+    names = set()
+    for h in headers:
+        text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(" + prefix + r"[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_header_declares_the_four_verbs():
@@ -39,6 +43,16 @@ def test_library_exports_every_declared_function(qla):
     # and the binding wraps each of them under the same name
     for name in declared_functions():
         assert hasattr(qla, name), name
+
+
+def test_library_exports_every_surrogate_function(qla):
+    from paper_2301_13601_amd import qnn
+    names = declared_functions(HEADERS, prefix="qnn_")
+    assert len(names) >= 15
+    L = ctypes.CDLL(qla.LIB_PATH)
+    for name in names:
+        assert hasattr(L, name), name
+        assert hasattr(qnn, name), name
 
 
 def test_rejects_bad_parameters_without_a_device(qla):

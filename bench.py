@@ -12,7 +12,10 @@ timed region starts.
 Prints one JSON line with the site-update rate, the roofline of the step
 kernel (algorithmic bytes: 24 B read + 24 B written of FP32 state and 12 B
 of FP32 index per site-update) and the FP64 oracle timed on the host cores
-on a bounded sample of the same workload.
+on a bounded sample of the same workload. For a single-polarisation
+workload it also times the polarised kernel (the E_z triple only: 12 B
+read + 12 B written + 4 B of n_z per site-update, results bitwise equal on
+that triple) and reports it beside, not as, the headline value.
 """
 from __future__ import annotations
 
@@ -30,14 +33,20 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0            # MI355X HBM3E, published
 ALGO_BYTES_PER_SITE = 60         # 6*4 read + 6*4 written + 3*4 index read
+TM_BYTES_PER_SITE = 28           # 3*4 read + 3*4 written + 1*4 index read
 DIAG_EVERY = 500
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_cylinder_4096_traffic.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_2301_13601_amd", "csrc", "qla.hip")
+# the step kernel, its instances and the host code that plans its launch
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2301_13601_amd", "csrc", f)
+               for f in ("qla_step.hpp", "qla_step_inst.hip", "qla.hip")]
 
 
 def kernel_source_hash() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SRCS:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic():
@@ -129,6 +138,47 @@ def cpu_baseline(sc, sample_steps: int, sample_n: int):
                       f"{dt:.1f} s wall, FP64, OpenMP over {threads} threads"}
 
 
+def is_tm_only(q) -> bool:
+    """True if the state lives in the E_z triple (q0 = q1 = q5 = 0)."""
+    return all(not np.any(q[c]) for c in (0, 1, 5))
+
+
+def time_polarised(make_sim, stream, sites: int, steps: int, warmup: int) -> dict:
+    """The same workload on the polarised kernel (TM triple only), timed
+    like the headline run (whole job on the wall clock, kernel time from
+    HIP events on the launch stream)."""
+    import torch
+    sim = make_sim("tm")
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    sim.close()
+    sim = make_sim("tm")
+    torch.cuda.synchronize()
+    ev = []
+    t0 = time.perf_counter()
+    done = 0
+    while done < steps:
+        k = min(DIAG_EVERY, steps - done)
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        sim.step(k)
+        b.record(stream)
+        ev.append((a, b, k))
+        done += k
+        sim.diagnostics()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    avg = sum(a.elapsed_time(b) for a, b, _ in ev) / 1e3 / steps
+    sim.close()
+    achieved = sites * TM_BYTES_PER_SITE / avg / 1e9
+    return {"polarisation": "tm (q2, q3, q4 = n_z E_z, B_x, B_y)", "steps": steps,
+            "value": sites * steps / wall, "unit": "site-updates/s",
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "avg_launch_us": avg * 1e6,
+                         "algo_bytes_per_site": TM_BYTES_PER_SITE}}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -139,6 +189,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=6)
     ap.add_argument("--cpu-sample-n", type=int, default=4096)
+    ap.add_argument("--polarised-steps", type=int, default=2000,
+                    help="steps of the polarised (E_z triple) kernel timed after the headline run; 0 skips")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one device copy of this many MiB (counter calibration)")
     ap.add_argument("--counters", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_MIB"),
@@ -164,12 +216,13 @@ def main():
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
 
-    def make_sim():
+    def make_sim(pol="both"):
         if batch:
             return qla.Batch([s.n.astype(np.float32) for s in sc], [s.q.astype(np.float32) for s in sc],
                              [s.delta for s in sc], "eq28", "phys", device="cuda:0", stream=stream)
         n32, q32 = sc.as_f32()
-        return qla.Simulation(n32, q32, sc.delta, sc.pot_mode, "phys", device="cuda:0", stream=stream)
+        return qla.Simulation(n32, q32, sc.delta, sc.pot_mode, "phys", device="cuda:0", stream=stream,
+                              polarisation=pol)
 
     sim = make_sim()
     sites = sim.sites if batch else sc.nx * sc.ny
@@ -249,11 +302,13 @@ def main():
                    "divB_ratio_final": log[-1]["divB_ratio"] if log else 0.0},
         "roofline": roofline,
     }
+    sim.close()
+    if args.polarised_steps > 0 and not batch and is_tm_only(sc.q):
+        out["polarised"] = time_polarised(make_sim, stream, sites, args.polarised_steps, args.warmup)
     if not args.no_cpu_baseline:
         first = sc[0] if batch else sc
         sample_n = min(args.cpu_sample_n, first.nx)
         out["cpu_baseline"] = cpu_baseline(first, args.cpu_sample_steps, sample_n)
-    sim.close()
     print(json.dumps(out), flush=True)
 
 

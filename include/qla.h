@@ -63,11 +63,39 @@ typedef enum { QLA_POT_EQ23 = 0, QLA_POT_EQ28 = 1 } qla_pot_mode;
  *                             sequence alone) */
 typedef enum { QLA_BETA_PHYS = 0, QLA_BETA_LATTICE = 1, QLA_BETA_OFF = 2 } qla_beta_scale;
 
+/* Field triple a context advances. C_X, C_Y, V_X and V_Y (Eq. (17), (19),
+ * (21), (22)) couple q0, q1, q5 only among themselves and q2, q3, q4 only
+ * among themselves, so a state with one triple zero keeps it zero (the
+ * polarisations of Sec. 4.1 and 4.2).
+ *   BOTH: all six components (any state)
+ *   TM:   (q2, q3, q4) = (n_z E_z, B_x, B_y); the step reads n_z only
+ *   TE:   (q0, q1, q5) = (n_x E_x, n_y E_y, B_z); the step reads n_x, n_y
+ * A TM or TE context holds the other triple at zero: qla_init clears its
+ * three planes in both state buffers, qla_load_at in the loaded state, and
+ * the step neither reads nor writes them. On the live triple the results are
+ * bitwise those of a BOTH context. */
+typedef enum { QLA_POL_BOTH = 0, QLA_POL_TM = 1, QLA_POL_TE = 2 } qla_polarisation;
+
+/* Form of the potential operators.
+ *   PRINTED: V_X, V_Y as Eq. (21), (22) (the paper's method)
+ *   SKEW:    the exponential of the antisymmetric part of their generator:
+ *            a rotation by beta/2 in each coupled pair, in the sense of the
+ *            printed coupling -- V_X rotates (q4, q2) by beta_2/2 and
+ *            (q1, q5) by beta_0/2; V_Y rotates (q2, q3) by beta_3/2 and
+ *            (q5, q0) by beta_1/2 (a' = cos a - sin b, b' = sin a + cos b
+ *            for the pair (a, b)). Orthogonal, so every step conserves
+ *            Eq. (27). The paper leaves a unitary potential to future work
+ *            without specifying one; this variant is the library's own
+ *            construction, not a formula of the paper. */
+typedef enum { QLA_V_PRINTED = 0, QLA_V_SKEW = 1 } qla_v_form;
+
 typedef struct {
     int32_t nx, ny;       /* lattice size, each >= 1 */
     double delta;         /* the perturbation parameter delta > 0 (Sec. 3) */
     int32_t pot_mode;     /* qla_pot_mode */
     int32_t beta_scale;   /* qla_beta_scale */
+    int32_t polarisation; /* qla_polarisation (0: all six components) */
+    int32_t v_form;       /* qla_v_form (0: as printed) */
 } qla_params;
 
 /* Diagnostics of the current state (Sec. 3.1 and 4), all accumulated in FP64.
@@ -104,7 +132,8 @@ typedef struct {
 
 /* One lattice of a batch: its parameters and caller-owned device buffers
  * (layouts as for qla_init). Every lattice of a batch must use the same
- * pot_mode and beta_scale; sizes and delta may differ. */
+ * pot_mode, beta_scale, polarisation and v_form; sizes and delta may
+ * differ. */
 typedef struct {
     qla_params p;
     const float *d_n;

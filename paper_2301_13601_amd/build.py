@@ -1,7 +1,8 @@
 """Build libqla.so (HIP, gfx950) in place, next to this file.
 
-The translation units (host side and one per potential placement) compile
-in parallel, then link into one shared library.
+The translation units (host side, surrogate kernels, and the step kernel's
+instances once per placement of the potentials and field triple) compile in
+parallel, then link into one shared library.
 """
 from __future__ import annotations
 
@@ -13,7 +14,11 @@ import tempfile
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["qla.hip", "qla_step_eq23.hip", "qla_step_eq28.hip", "qnn.hip"]
+# (source, object name, defines)
+SOURCES = [("qla.hip", "qla", ()), ("qnn.hip", "qnn", ())] + [
+    ("qla_step_inst.hip", f"qla_step_m{m}_f{f}", (f"-DQLA_MODE={m}", f"-DQLA_FIELDS={f}"))
+    for m in (0, 1) for f in (0, 1, 2)
+]
 LIB = os.path.join(HERE, "libqla.so")
 INCLUDE = os.path.join(ROOT, "include")
 
@@ -32,12 +37,13 @@ FLAGS = [
 def build(verbose: bool = False, extra=()) -> str:
     with tempfile.TemporaryDirectory(prefix="qla_build_") as tmpd:
         objs, procs = [], []
-        for src in SOURCES:
-            obj = os.path.join(tmpd, os.path.splitext(src)[0] + ".o")
-            cmd = [HIPCC, *FLAGS, *extra, "-I", INCLUDE, "-I", CSRC, "-c", os.path.join(CSRC, src), "-o", obj]
+        for src, name, defs in SOURCES:
+            obj = os.path.join(tmpd, name + ".o")
+            cmd = [HIPCC, *FLAGS, *defs, *extra, "-I", INCLUDE, "-I", CSRC, "-c", os.path.join(CSRC, src),
+                   "-o", obj]
             if verbose:
                 print(" ".join(cmd), flush=True)
-            procs.append((src, subprocess.Popen(cmd)))
+            procs.append((name, subprocess.Popen(cmd)))
             objs.append(obj)
         failed = [src for src, p in procs if p.wait() != 0]
         if failed:

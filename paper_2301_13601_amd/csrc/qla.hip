@@ -3,7 +3,7 @@
 // declared in include/qla.h. This file holds the host side (contexts,
 // launch planning, graphs, the C entry points) and the auxiliary kernels
 // (validation scan, FP64 diagnostics, field export); the fused step kernel is
-// in qla_step.hpp and its instances in qla_step_eq23.hip / qla_step_eq28.hip.
+// in qla_step.hpp and its instances in qla_step_inst.hip.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -204,6 +204,18 @@ __global__ void __launch_bounds__(256) qla_fields_kernel(const float* __restrict
   }
 }
 
+// Zero three planes of a state (the triple a polarised context holds at
+// zero): planes c0, c1, c2 of q.
+__global__ void __launch_bounds__(256) qla_clear_kernel(float* __restrict__ q, int64_t plane, int c0,
+                                                        int c1, int c2) {
+  for (int64_t s = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; s < plane;
+       s += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    q[c0 * plane + s] = 0.0f;
+    q[c1 * plane + s] = 0.0f;
+    q[c2 * plane + s] = 0.0f;
+  }
+}
+
 
 }  // namespace
 
@@ -251,7 +263,7 @@ void set_error(const char* fmt, ...) {
 struct qla_ctx {
   uint64_t magic;
   int count;
-  int pot_mode, beta_scale;
+  int pot_mode, beta_scale, polarisation, v_form;
   std::vector<qla_params> p;
   std::vector<const float*> n;
   std::vector<float*> buf[2];
@@ -284,6 +296,10 @@ qla_status check_params(const qla_params* p) {
     return fail(QLA_EINVAL, "qla: pot_mode %d is not QLA_POT_EQ23 or QLA_POT_EQ28", p->pot_mode);
   if (p->beta_scale < QLA_BETA_PHYS || p->beta_scale > QLA_BETA_OFF)
     return fail(QLA_EINVAL, "qla: beta_scale %d unknown", p->beta_scale);
+  if (p->polarisation < QLA_POL_BOTH || p->polarisation > QLA_POL_TE)
+    return fail(QLA_EINVAL, "qla: polarisation %d unknown", p->polarisation);
+  if (p->v_form != QLA_V_PRINTED && p->v_form != QLA_V_SKEW)
+    return fail(QLA_EINVAL, "qla: v_form %d unknown", p->v_form);
   return QLA_OK;
 }
 
@@ -293,8 +309,11 @@ qla_status check_batch(int32_t count, const qla_instance* inst) {
   for (int i = 0; i < count; ++i) {
     qla_status st = check_params(&inst[i].p);
     if (st != QLA_OK) return st;
-    if (inst[i].p.pot_mode != inst[0].p.pot_mode || inst[i].p.beta_scale != inst[0].p.beta_scale)
-      return fail(QLA_EINVAL, "qla: pot_mode and beta_scale must be the same for every lattice of a batch");
+    if (inst[i].p.pot_mode != inst[0].p.pot_mode || inst[i].p.beta_scale != inst[0].p.beta_scale ||
+        inst[i].p.polarisation != inst[0].p.polarisation || inst[i].p.v_form != inst[0].p.v_form)
+      return fail(QLA_EINVAL,
+                  "qla: pot_mode, beta_scale, polarisation and v_form must be the same for every lattice "
+                  "of a batch");
   }
   return QLA_OK;
 }
@@ -321,6 +340,20 @@ double kb_of(const qla_params& p) {
   return kappa_of(p) * frac * 0.5;
 }
 
+// In a TM or TE context, zero the planes of the other triple of lattice i in
+// state buffer b (a kernel, not a memset, so that a caller may capture it).
+hipError_t clear_dead(qla_ctx* c, int i, int b) {
+  if (c->polarisation == QLA_POL_BOTH) return hipSuccess;
+  const qla_params& p = c->p[i];
+  const int64_t plane = static_cast<int64_t>(p.nx) * p.ny;
+  const int blocks = static_cast<int>(std::min<int64_t>((plane + 255) / 256, 4096));
+  if (c->polarisation == QLA_POL_TM)
+    hipLaunchKernelGGL(qla_clear_kernel, dim3(blocks), dim3(256), 0, c->stream, c->buf[b][i], plane, 0, 1, 5);
+  else
+    hipLaunchKernelGGL(qla_clear_kernel, dim3(blocks), dim3(256), 0, c->stream, c->buf[b][i], plane, 2, 3, 4);
+  return hipGetLastError();
+}
+
 void drop_graphs(qla_ctx* c) {
   for (auto& g : c->graph) {
     if (g) (void)hipGraphExecDestroy(g);
@@ -344,9 +377,18 @@ qla_status plan_step(qla_ctx* c) {
     vec = vec && (p.nx % kCols) == 0;
     max_ny = std::max(max_ny, p.ny);
   }
-  const bool pot = c->beta_scale != QLA_BETA_OFF;
-  c->step = c->pot_mode == QLA_POT_EQ28 ? qla_dev::pick_step_eq28(vec, c->wide, pot)
-                                        : qla_dev::pick_step_eq23(vec, c->wide, pot);
+  qla_dev::StepChoice ch;
+  ch.mode = c->pot_mode;
+  ch.pot = c->beta_scale != QLA_BETA_OFF;
+  ch.wide = c->wide;
+  ch.vec = vec;
+  ch.fields = c->polarisation;
+  ch.skew = c->v_form;
+  using Pick = StepImpl (*)(const qla_dev::StepChoice&);
+  static constexpr Pick kPick[2][3] = {
+      {qla_dev::pick_step_m0_f0, qla_dev::pick_step_m0_f1, qla_dev::pick_step_m0_f2},
+      {qla_dev::pick_step_m1_f0, qla_dev::pick_step_m1_f1, qla_dev::pick_step_m1_f2}};
+  c->step = kPick[ch.mode][ch.fields](ch);
   std::vector<int> nstrips(c->count);
   for (int i = 0; i < c->count; ++i) nstrips[i] = (c->p[i].nx + kOutCols - 1) / kOutCols;
   auto blocks_for = [&](int S) {
@@ -484,6 +526,8 @@ qla_status init_common(int32_t count, const qla_instance* inst, void* d_work, vo
   c->count = count;
   c->pot_mode = inst[0].p.pot_mode;
   c->beta_scale = inst[0].p.beta_scale;
+  c->polarisation = inst[0].p.polarisation;
+  c->v_form = inst[0].p.v_form;
   try {
     for (int i = 0; i < count; ++i) {
       c->p.push_back(inst[i].p);
@@ -511,8 +555,15 @@ qla_status init_common(int32_t count, const qla_instance* inst, void* d_work, vo
     }
   }
   c->wide = !(theta_max <= kNarrowAngle && bmax <= kNarrowAngle);
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < count && e == hipSuccess; ++i)
+    for (int b = 0; b < 2 && e == hipSuccess; ++b) e = clear_dead(c, i, b);
+  if (e != hipSuccess) {
+    delete c;
+    return hip_fail(nullptr, e, "clearing the unused field triple");
+  }
   int dev = 0, cus = 0;
-  hipError_t e = hipGetDevice(&dev);
+  e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess || cus < 1) {
     delete c;
@@ -689,6 +740,7 @@ qla_status qla_load_at(qla_ctx* ctx, int32_t index, const float* src, int32_t sr
   const size_t bytes = static_cast<size_t>(p.nx) * p.ny * 6 * sizeof(float);
   hipError_t e = hipMemcpyAsync(ctx->buf[ctx->cur][index], src, bytes,
                                 src_is_host ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, ctx->stream);
+  if (e == hipSuccess) e = clear_dead(ctx, index, ctx->cur);
   if (e == hipSuccess && src_is_host) e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "loading a state");
   return QLA_OK;

@@ -197,6 +197,34 @@ __device__ __forceinline__ void store_row(float* row, int nx, const uint32_t (&s
 // true on every lane if any lane's flag is set (a wave-uniform branch)
 __device__ __forceinline__ bool wave_any(bool v) { return __any(v) != 0; }
 
+// Compile-time options of one kernel instance.
+//   MODE    0: potentials after U_Y (Eq. (23)); 1: interleaved (Eq. (28))
+//   POT     potentials present (kappa != 0)
+//   WIDE    libm coefficients instead of the short series
+//   VEC     nx % C == 0: vector row I/O
+//   FIELDS  0: all six components; 1: only (q2, q3, q4) = (n_z E_z, B_x, B_y)
+//           (TM); 2: only (q0, q1, q5) = (n_x E_x, n_y E_y, B_z) (TE). The two
+//           triples never mix under C_X, C_Y, V_X, V_Y, so a state living in
+//           one triple stays there, and the other three planes are neither
+//           read nor written.
+//   SKEW    0: the potentials of Eq. (21)/(22) as printed; 1: their
+//           skew-symmetric part, a rotation by half the angle in the same
+//           pairs (an orthogonal, energy-conserving variant)
+template <int MODE_, bool POT_, bool WIDE_, bool VEC_, int FIELDS_, int SKEW_>
+struct KOpt {
+  static constexpr int MODE = MODE_;
+  static constexpr bool POT = POT_;
+  static constexpr bool WIDE = WIDE_;
+  static constexpr bool VEC = VEC_;
+  static constexpr int FIELDS = FIELDS_;
+  static constexpr bool SKEW = SKEW_ != 0;
+  static constexpr bool TE = FIELDS_ != 1;     // (q0, q1, q5) live
+  static constexpr bool TM = FIELDS_ != 2;     // (q2, q3, q4) live
+  static constexpr bool live(int c) { return (c == 0 || c == 1 || c == 5) ? TE : TM; }
+  // index planes read: n_x and n_y serve the TE triple, n_z the TM triple
+  static constexpr bool nlive(int c) { return c == 2 ? TM : TE; }
+};
+
 // Everything a wave carries from one row iteration to the next. The wave
 // marches through its segment in direction DIR (+1: increasing y, -1:
 // decreasing y); "row R" is the row ingested this iteration and "lag k" the
@@ -209,16 +237,17 @@ struct Pipe {
   // collision coefficients (tan(theta_0/2), sin theta_0, tan(theta_2/2),
   // sin theta_2) of rows lag 1..4, slot = iteration mod 4
   float th[4][4][C];
-  // V_Y coefficients (sin b1, 1-cos b1, sin b3, 1-cos b3) per row slot, and
-  // whether the row has any nonzero y-difference of n_x or n_z (when it
-  // has none, beta_1 = beta_3 = 0 and V_Y is exactly the identity)
+  // V_Y coefficients per row slot ((sin b, 1 - cos b) of beta_1 and beta_3,
+  // or (tan, sin) of the skew rotation angles), and whether the row has any
+  // nonzero y-difference of n_x or n_z (when it has none, beta_1 = beta_3 =
+  // 0 and V_Y is exactly the identity)
   float vy[4][4][C];
   bool fy[4];
-  // Eq. (23) only: V_X coefficients, their flag and the (q1, q4) pair per row
-  // slot, all applied after U_Y
+  // Eq. (23) only: V_X coefficients, their flag and the (q1, q2, q4) values
+  // per row slot, all needed after U_Y
   float vx[4][4][C];
   bool fx[4];
-  float q14[4][2][C];
+  float q14[4][3][C];
   // the ingested row R and the rows in flight: Q of R and R+DIR, n of R-DIR
   // (x and z components), R, R+DIR and R+2*DIR
   float q[6][C];
@@ -249,24 +278,38 @@ struct YLags {
   static constexpr int before(int k) { return k == 0 ? 0 : after(k - 1); }
 };
 
-// MODE: 0 = Eq. (23), 1 = Eq. (28). POT: potentials present (kappa != 0).
-template <int C, bool VEC, bool WIDE, int MODE, bool POT, int DIR, int SLOT>
+// Potential coefficients of an applied angle b: printed form (sin b,
+// 1 - cos b); skew form (tan(b/4), sin(b/2)) of the rotation by b/2.
+template <class O>
+__device__ __forceinline__ void vcoef(float b, float& c0, float& c1) {
+  if constexpr (O::SKEW)
+    rot_coef<O::WIDE>(0.5f * b, c0, c1);
+  else
+    pot_coef<O::WIDE>(b, c0, c1);
+}
+
+template <int C, class O, int DIR, int SLOT>
 __device__ __forceinline__ void row_iteration(Pipe<C>& p, const StepArgs& g, const uint32_t (&xo)[C],
                                               const uint32_t (&so)[C], bool edge_lane, int i,
                                               int seg_h, int y0, const RowBases& rb) {
+  constexpr bool VEC = O::VEC, WIDE = O::WIDE, POT = O::POT, TE = O::TE, TM = O::TM;
+  constexpr int MODE = O::MODE;
   // ---- prefetch Q of row R+2*DIR and n of row R+3*DIR ---------------------
   float qld[6][C];
   float nld[3][C];
 #pragma unroll
-  for (int c = 0; c < 6; ++c) load_row<C, VEC>(rb.qld + c * g.plane, g.nx, xo, qld[c]);
+  for (int c = 0; c < 6; ++c)
+    if (O::live(c)) load_row<C, VEC>(rb.qld + c * g.plane, g.nx, xo, qld[c]);
 #pragma unroll
-  for (int c = 0; c < 3; ++c) load_row<C, VEC>(rb.nld + c * g.plane, g.nx, xo, nld[c]);
+  for (int c = 0; c < 3; ++c)
+    if (O::nlive(c)) load_row<C, VEC>(rb.nld + c * g.plane, g.nx, xo, nld[c]);
 
   // ---- coefficients of row R (Eq. (24), (25)) -----------------------------
   float u[3][C];
   float tc[3][C], sc[3][C];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
+    if (!O::nlive(c)) continue;
 #pragma unroll
     for (int k = 0; k < C; ++k) {
       u[c][k] = __builtin_amdgcn_rcpf(p.ncur[c][k]);
@@ -276,77 +319,102 @@ __device__ __forceinline__ void row_iteration(Pipe<C>& p, const StepArgs& g, con
   // V_X coefficients from the x-differences of n_y (beta_0) and n_z (beta_2).
   // Lanes 0 and 63 see a zero from the DPP shift at the wave edge; their
   // values only reach halo columns, so they do not vote.
-  float vxs0[C], vxh0[C], vxs2[C], vxh2[C];
+  float vx00[C], vx01[C], vx20[C], vx21[C];
   bool fx = false;
   if constexpr (POT) {
     float dny[C], dnz[C];
-    {
-      float r1[C], l1[C], r2[C], l2[C];
+    bool nz = false;
 #pragma unroll
-      for (int k = 0; k < C; ++k) {
-        r1[k] = l1[k] = p.ncur[1][k];
-        r2[k] = l2[k] = p.ncur[2][k];
-      }
-      pull_from_right<C>(r1); pull_from_left<C>(l1);
-      pull_from_right<C>(r2); pull_from_left<C>(l2);
-      bool nz = false;
+    for (int k = 0; k < C; ++k) dny[k] = dnz[k] = 0.0f;
+    if constexpr (TE) {
+      float r1[C], l1[C];
+#pragma unroll
+      for (int k = 0; k < C; ++k) r1[k] = l1[k] = p.ncur[1][k];
+      pull_from_right<C>(r1);
+      pull_from_left<C>(l1);
 #pragma unroll
       for (int k = 0; k < C; ++k) {
         dny[k] = r1[k] - l1[k];
-        dnz[k] = r2[k] - l2[k];
-        nz = nz || dny[k] != 0.0f || dnz[k] != 0.0f;
+        nz = nz || dny[k] != 0.0f;
       }
-      fx = wave_any(nz && !edge_lane);
     }
+    if constexpr (TM) {
+      float r2[C], l2[C];
+#pragma unroll
+      for (int k = 0; k < C; ++k) r2[k] = l2[k] = p.ncur[2][k];
+      pull_from_right<C>(r2);
+      pull_from_left<C>(l2);
+#pragma unroll
+      for (int k = 0; k < C; ++k) {
+        dnz[k] = r2[k] - l2[k];
+        nz = nz || dnz[k] != 0.0f;
+      }
+    }
+    fx = wave_any(nz && !edge_lane);
+#pragma unroll
+    for (int k = 0; k < C; ++k) vx00[k] = vx01[k] = vx20[k] = vx21[k] = 0.0f;
     if (fx) {
 #pragma unroll
       for (int k = 0; k < C; ++k) {
-        const float b0 = g.kb * dny[k] * (u[1][k] * u[1][k]);
-        const float b2 = g.kb * dnz[k] * (u[2][k] * u[2][k]);
-        pot_coef<WIDE>(b0, vxs0[k], vxh0[k]);
-        pot_coef<WIDE>(b2, vxs2[k], vxh2[k]);
+        if constexpr (TE) vcoef<O>(g.kb * dny[k] * (u[1][k] * u[1][k]), vx00[k], vx01[k]);
+        if constexpr (TM) vcoef<O>(g.kb * dnz[k] * (u[2][k] * u[2][k]), vx20[k], vx21[k]);
       }
-    } else {
-#pragma unroll
-      for (int k = 0; k < C; ++k) vxs0[k] = vxh0[k] = vxs2[k] = vxh2[k] = 0.0f;
     }
   }
 
   // ---- U_X (Eq. (18)) with V_X' interleaved (Eq. (28)) on row R ------------
   float (&q)[6][C] = p.q;
-  const float (&t1)[C] = tc[1];
-  const float (&s1)[C] = sc[1];
-  const float (&t2)[C] = tc[2];
-  const float (&s2)[C] = sc[2];
+  using P_ = std::integral_constant<int, 1>;
+  using M_ = std::integral_constant<int, -1>;
   auto cx = [&](auto sgn) {
     constexpr int S = decltype(sgn)::value;
 #pragma unroll
     for (int k = 0; k < C; ++k) {
-      rot<S>(q[1][k], q[5][k], t1[k], s1[k]);
-      rot<S>(q[2][k], q[4][k], t2[k], s2[k]);
+      if constexpr (TE) rot<S>(q[1][k], q[5][k], tc[1][k], sc[1][k]);
+      if constexpr (TM) rot<S>(q[2][k], q[4][k], tc[2][k], sc[2][k]);
     }
   };
-  using P_ = std::integral_constant<int, 1>;
-  using M_ = std::integral_constant<int, -1>;
-  auto vx_apply = [&]() {
-    if (fx) {
+  auto sx = [&](auto right, int ca, int cb) {
+    // streams components ca, cb along x (pull from x+1 if right, else x-1)
+    constexpr bool R = decltype(right)::value;
+    if (O::live(ca)) {
+      if constexpr (R) pull_from_right<C>(q[ca]); else pull_from_left<C>(q[ca]);
+    }
+    if (O::live(cb)) {
+      if constexpr (R) pull_from_right<C>(q[cb]); else pull_from_left<C>(q[cb]);
+    }
+  };
+  // V_X: q4 <- cos b2 q4 - sin b2 q2,  q5 <- sin b0 q1 + cos b0 q5 (Eq. (21))
+  auto vx_apply = [&](const float (&c00)[C], const float (&c01)[C], const float (&c20)[C],
+                      const float (&c21)[C], float (&q1v)[C], float (&q2v)[C], float (&q4v)[C],
+                      float (&q5v)[C]) {
 #pragma unroll
-      for (int k = 0; k < C; ++k) {
-        q[4][k] = pot_row(q[4][k], -q[2][k], vxs2[k], vxh2[k]);
-        q[5][k] = pot_row(q[5][k], q[1][k], vxs0[k], vxh0[k]);
+    for (int k = 0; k < C; ++k) {
+      if constexpr (O::SKEW) {
+        if constexpr (TM) rot<+1>(q4v[k], q2v[k], c20[k], c21[k]);
+        if constexpr (TE) rot<+1>(q1v[k], q5v[k], c00[k], c01[k]);
+      } else {
+        if constexpr (TM) q4v[k] = pot_row(q4v[k], -q2v[k], c20[k], c21[k]);
+        if constexpr (TE) q5v[k] = pot_row(q5v[k], q1v[k], c00[k], c01[k]);
       }
     }
   };
-  cx(M_{}); pull_from_left<C>(q[1]);  pull_from_left<C>(q[4]);
-  cx(P_{}); pull_from_right<C>(q[1]); pull_from_right<C>(q[4]);
-  cx(M_{}); pull_from_right<C>(q[2]); pull_from_right<C>(q[5]);
-  cx(P_{}); pull_from_left<C>(q[2]);  pull_from_left<C>(q[5]);
-  if constexpr (MODE == 1 && POT) vx_apply();
-  cx(P_{}); pull_from_right<C>(q[1]); pull_from_right<C>(q[4]);
-  cx(M_{}); pull_from_left<C>(q[1]);  pull_from_left<C>(q[4]);
-  cx(P_{}); pull_from_left<C>(q[2]);  pull_from_left<C>(q[5]);
-  cx(M_{}); pull_from_right<C>(q[2]); pull_from_right<C>(q[5]);
-  if constexpr (MODE == 1 && POT) vx_apply();
+  using T_ = std::integral_constant<bool, true>;
+  using F_ = std::integral_constant<bool, false>;
+  cx(M_{}); sx(F_{}, 1, 4);
+  cx(P_{}); sx(T_{}, 1, 4);
+  cx(M_{}); sx(T_{}, 2, 5);
+  cx(P_{}); sx(F_{}, 2, 5);
+  if constexpr (MODE == 1 && POT) {
+    if (fx) vx_apply(vx00, vx01, vx20, vx21, q[1], q[2], q[4], q[5]);
+  }
+  cx(P_{}); sx(T_{}, 1, 4);
+  cx(M_{}); sx(F_{}, 1, 4);
+  cx(P_{}); sx(F_{}, 2, 5);
+  cx(M_{}); sx(T_{}, 2, 5);
+  if constexpr (MODE == 1 && POT) {
+    if (fx) vx_apply(vx00, vx01, vx20, vx21, q[1], q[2], q[4], q[5]);
+  }
 
   // rows of this iteration relative to y0: R, and R - 4*DIR which leaves
   // the pipeline; both lie in the segment for the same range of i
@@ -358,8 +426,8 @@ __device__ __forceinline__ void row_iteration(Pipe<C>& p, const StepArgs& g, con
     // q1 and q4 are final once U_X and V_X' are done: U_Y and V_Y leave them
     if (R_out) {
       float* row = g.qout + static_cast<int64_t>(y0 + R_rel) * g.nx;
-      store_row<C, VEC>(row + 1 * g.plane, g.nx, so, q[1]);
-      store_row<C, VEC>(row + 4 * g.plane, g.nx, so, q[4]);
+      if constexpr (TE) store_row<C, VEC>(row + 1 * g.plane, g.nx, so, q[1]);
+      if constexpr (TM) store_row<C, VEC>(row + 4 * g.plane, g.nx, so, q[4]);
     }
   }
 
@@ -379,15 +447,15 @@ __device__ __forceinline__ void row_iteration(Pipe<C>& p, const StepArgs& g, con
     if constexpr (lag == 0) {
 #pragma unroll
       for (int k = 0; k < C; ++k) {
-        rot<-S>(a0[k], a5[k], tc[0][k], sc[0][k]);
-        rot<-S>(b2[k], b3[k], tc[2][k], sc[2][k]);
+        if constexpr (TE) rot<-S>(a0[k], a5[k], tc[0][k], sc[0][k]);
+        if constexpr (TM) rot<-S>(b2[k], b3[k], tc[2][k], sc[2][k]);
       }
     } else {
       constexpr int sl = (SLOT - lag) & 3;
 #pragma unroll
       for (int k = 0; k < C; ++k) {
-        rot<-S>(a0[k], a5[k], p.th[sl][0][k], p.th[sl][1][k]);
-        rot<-S>(b2[k], b3[k], p.th[sl][2][k], p.th[sl][3][k]);
+        if constexpr (TE) rot<-S>(a0[k], a5[k], p.th[sl][0][k], p.th[sl][1][k]);
+        if constexpr (TM) rot<-S>(b2[k], b3[k], p.th[sl][2][k], p.th[sl][3][k]);
       }
     }
   };
@@ -399,26 +467,34 @@ __device__ __forceinline__ void row_iteration(Pipe<C>& p, const StepArgs& g, con
       dly[k] = t;
     }
   };
-  // stream stage k shifting (sa, sb) and leaving (ka, kb) of the active four
-  auto sy = [&](auto kk, float (&sa)[C], float (&sb)[C], float (&ka)[C], float (&kb)[C]) {
+  // stream stage k shifting (sa, sb) and leaving (ka, kb) of the active four;
+  // the flags say which of the four belong to a live triple
+  auto sy = [&](auto kk, float (&sa)[C], bool la, float (&sb)[C], bool lb, float (&ka)[C], bool lka,
+                float (&kb)[C], bool lkb) {
     constexpr int k = decltype(kk)::value;
     if constexpr (Lg::sgn[k] == DIR) {
       // pulls from the row ahead: the other two wait one row
-      swap_in(ka, p.d[k][0]);
-      swap_in(kb, p.d[k][1]);
+      if (lka) swap_in(ka, p.d[k][0]);
+      if (lkb) swap_in(kb, p.d[k][1]);
     } else {
       // pulls from the row behind: the shifted two come from the delay line
-      swap_in(sa, p.d[k][0]);
-      swap_in(sb, p.d[k][1]);
+      if (la) swap_in(sa, p.d[k][0]);
+      if (lb) swap_in(sb, p.d[k][1]);
     }
   };
+  // V_Y: q3 <- sin b3 q2 + cos b3 q3,  q5 <- -sin b1 q0 + cos b1 q5 (Eq. (22))
   auto vy_apply = [&](auto lag) {
     constexpr int sl = (SLOT - decltype(lag)::value) & 3;
     if (p.fy[sl]) {
 #pragma unroll
       for (int k = 0; k < C; ++k) {
-        b3[k] = pot_row(b3[k], b2[k], p.vy[sl][2][k], p.vy[sl][3][k]);
-        a5[k] = pot_row(a5[k], -a0[k], p.vy[sl][0][k], p.vy[sl][1][k]);
+        if constexpr (O::SKEW) {
+          if constexpr (TM) rot<+1>(b2[k], b3[k], p.vy[sl][2][k], p.vy[sl][3][k]);
+          if constexpr (TE) rot<-1>(a0[k], a5[k], p.vy[sl][0][k], p.vy[sl][1][k]);
+        } else {
+          if constexpr (TM) b3[k] = pot_row(b3[k], b2[k], p.vy[sl][2][k], p.vy[sl][3][k]);
+          if constexpr (TE) a5[k] = pot_row(a5[k], -a0[k], p.vy[sl][0][k], p.vy[sl][1][k]);
+        }
       }
     }
   };
@@ -431,22 +507,24 @@ __device__ __forceinline__ void row_iteration(Pipe<C>& p, const StepArgs& g, con
   using K6 = std::integral_constant<int, 6>;
   using K7 = std::integral_constant<int, 7>;
   static_assert(Lg::after(3) == 2 && Lg::after(7) == 4, "V_Y' acts at lags 2 and 4");
-  // Eq. (20), right to left
-  cy(M_{}, K0{});  sy(K0{}, a0, b3, a5, b2);      // C_Y^dagger, S^{-y}_{03}
-  cy(P_{}, K1{});  sy(K1{}, a0, b3, a5, b2);      // C_Y,        S^{+y}_{03}
-  cy(M_{}, K2{});  sy(K2{}, b2, a5, a0, b3);      // C_Y^dagger, S^{+y}_{25}
-  cy(P_{}, K3{});  sy(K3{}, b2, a5, a0, b3);      // C_Y,        S^{-y}_{25}
+  // Eq. (20), right to left; S_{03} shifts (a0, b3), S_{25} shifts (b2, a5)
+  cy(M_{}, K0{});  sy(K0{}, a0, TE, b3, TM, a5, TE, b2, TM);   // C_Y^dagger, S^{-y}_{03}
+  cy(P_{}, K1{});  sy(K1{}, a0, TE, b3, TM, a5, TE, b2, TM);   // C_Y,        S^{+y}_{03}
+  cy(M_{}, K2{});  sy(K2{}, b2, TM, a5, TE, a0, TE, b3, TM);   // C_Y^dagger, S^{+y}_{25}
+  cy(P_{}, K3{});  sy(K3{}, b2, TM, a5, TE, a0, TE, b3, TM);   // C_Y,        S^{-y}_{25}
   if constexpr (MODE == 1 && POT) vy_apply(std::integral_constant<int, 2>{});   // V_Y' (Eq. (28))
-  cy(P_{}, K4{});  sy(K4{}, a0, b3, a5, b2);      // C_Y,        S^{+y}_{03}
-  cy(M_{}, K5{});  sy(K5{}, a0, b3, a5, b2);      // C_Y^dagger, S^{-y}_{03}
-  cy(P_{}, K6{});  sy(K6{}, b2, a5, a0, b3);      // C_Y,        S^{-y}_{25}
-  cy(M_{}, K7{});  sy(K7{}, b2, a5, a0, b3);      // C_Y^dagger, S^{+y}_{25}
+  cy(P_{}, K4{});  sy(K4{}, a0, TE, b3, TM, a5, TE, b2, TM);   // C_Y,        S^{+y}_{03}
+  cy(M_{}, K5{});  sy(K5{}, a0, TE, b3, TM, a5, TE, b2, TM);   // C_Y^dagger, S^{-y}_{03}
+  cy(P_{}, K6{});  sy(K6{}, b2, TM, a5, TE, a0, TE, b3, TM);   // C_Y,        S^{-y}_{25}
+  cy(M_{}, K7{});  sy(K7{}, b2, TM, a5, TE, a0, TE, b3, TM);   // C_Y^dagger, S^{+y}_{25}
   // the pipeline now holds the row at lag 4
   float o1[C], o4[C];
   if constexpr (MODE == 1) {
     if constexpr (POT) vy_apply(std::integral_constant<int, 4>{});   // V_Y' (Eq. (28))
   } else {
-    // Eq. (23): V_X then V_Y after U_Y, on the row at lag 4
+    // Eq. (23): V_X then V_Y after U_Y, on the row at lag 4. q2 comes out of
+    // U_Y; q1, q4 are the x-sweep values kept for this row (the skew V_X
+    // also rotates q2, which the y sweep has moved on, so it uses b2).
     constexpr int sl = (SLOT - 4) & 3;
 #pragma unroll
     for (int k = 0; k < C; ++k) {
@@ -454,25 +532,19 @@ __device__ __forceinline__ void row_iteration(Pipe<C>& p, const StepArgs& g, con
       o4[k] = p.q14[sl][1][k];
     }
     if constexpr (POT) {
-      if (p.fx[sl]) {
-#pragma unroll
-        for (int k = 0; k < C; ++k) {
-          o4[k] = pot_row(o4[k], -b2[k], p.vx[sl][2][k], p.vx[sl][3][k]);
-          a5[k] = pot_row(a5[k], o1[k], p.vx[sl][0][k], p.vx[sl][1][k]);
-        }
-      }
+      if (p.fx[sl]) vx_apply(p.vx[sl][0], p.vx[sl][1], p.vx[sl][2], p.vx[sl][3], o1, b2, o4, a5);
       vy_apply(std::integral_constant<int, 4>{});
     }
   }
   if (O_out) {
     float* row = g.qout + static_cast<int64_t>(y0 + O_rel) * g.nx;
-    store_row<C, VEC>(row + 0 * g.plane, g.nx, so, a0);
-    store_row<C, VEC>(row + 2 * g.plane, g.nx, so, b2);
-    store_row<C, VEC>(row + 3 * g.plane, g.nx, so, b3);
-    store_row<C, VEC>(row + 5 * g.plane, g.nx, so, a5);
+    if constexpr (TE) store_row<C, VEC>(row + 0 * g.plane, g.nx, so, a0);
+    if constexpr (TM) store_row<C, VEC>(row + 2 * g.plane, g.nx, so, b2);
+    if constexpr (TM) store_row<C, VEC>(row + 3 * g.plane, g.nx, so, b3);
+    if constexpr (TE) store_row<C, VEC>(row + 5 * g.plane, g.nx, so, a5);
     if constexpr (MODE == 0) {
-      store_row<C, VEC>(row + 1 * g.plane, g.nx, so, o1);
-      store_row<C, VEC>(row + 4 * g.plane, g.nx, so, o4);
+      if constexpr (TE) store_row<C, VEC>(row + 1 * g.plane, g.nx, so, o1);
+      if constexpr (TM) store_row<C, VEC>(row + 4 * g.plane, g.nx, so, o4);
     }
   }
 
@@ -480,25 +552,29 @@ __device__ __forceinline__ void row_iteration(Pipe<C>& p, const StepArgs& g, con
   // consumed above) ------------------------------------------------------------
 #pragma unroll
   for (int k = 0; k < C; ++k) {
-    p.th[SLOT][0][k] = tc[0][k];
-    p.th[SLOT][1][k] = sc[0][k];
-    p.th[SLOT][2][k] = tc[2][k];
-    p.th[SLOT][3][k] = sc[2][k];
+    if constexpr (TE) {
+      p.th[SLOT][0][k] = tc[0][k];
+      p.th[SLOT][1][k] = sc[0][k];
+    }
+    if constexpr (TM) {
+      p.th[SLOT][2][k] = tc[2][k];
+      p.th[SLOT][3][k] = sc[2][k];
+    }
   }
   if constexpr (MODE == 0) {
 #pragma unroll
     for (int k = 0; k < C; ++k) {
-      p.q14[SLOT][0][k] = p.q[1][k];
-      p.q14[SLOT][1][k] = p.q[4][k];
+      if constexpr (TE) p.q14[SLOT][0][k] = p.q[1][k];
+      if constexpr (TM) p.q14[SLOT][1][k] = p.q[4][k];
     }
     if constexpr (POT) {
       p.fx[SLOT] = fx;
 #pragma unroll
       for (int k = 0; k < C; ++k) {
-        p.vx[SLOT][0][k] = vxs0[k];
-        p.vx[SLOT][1][k] = vxh0[k];
-        p.vx[SLOT][2][k] = vxs2[k];
-        p.vx[SLOT][3][k] = vxh2[k];
+        p.vx[SLOT][0][k] = vx00[k];
+        p.vx[SLOT][1][k] = vx01[k];
+        p.vx[SLOT][2][k] = vx20[k];
+        p.vx[SLOT][3][k] = vx21[k];
       }
     }
   }
@@ -509,13 +585,9 @@ __device__ __forceinline__ void row_iteration(Pipe<C>& p, const StepArgs& g, con
     bool nz = false;
 #pragma unroll
     for (int k = 0; k < C; ++k) {
-      if constexpr (DIR > 0) {
-        d1[k] = p.nnext[0][k] - p.nprev[0][k];
-        d3[k] = p.nnext[2][k] - p.nprev[1][k];
-      } else {
-        d1[k] = p.nprev[0][k] - p.nnext[0][k];
-        d3[k] = p.nprev[1][k] - p.nnext[2][k];
-      }
+      d1[k] = d3[k] = 0.0f;
+      if constexpr (TE) d1[k] = DIR > 0 ? p.nnext[0][k] - p.nprev[0][k] : p.nprev[0][k] - p.nnext[0][k];
+      if constexpr (TM) d3[k] = DIR > 0 ? p.nnext[2][k] - p.nprev[1][k] : p.nprev[1][k] - p.nnext[2][k];
       nz = nz || d1[k] != 0.0f || d3[k] != 0.0f;
     }
     const bool fy = wave_any(nz);
@@ -523,26 +595,26 @@ __device__ __forceinline__ void row_iteration(Pipe<C>& p, const StepArgs& g, con
     if (fy) {
 #pragma unroll
       for (int k = 0; k < C; ++k) {
-        const float b1 = g.kb * d1[k] * (u[0][k] * u[0][k]);
-        const float b3c = g.kb * d3[k] * (u[2][k] * u[2][k]);
-        pot_coef<WIDE>(b1, p.vy[SLOT][0][k], p.vy[SLOT][1][k]);
-        pot_coef<WIDE>(b3c, p.vy[SLOT][2][k], p.vy[SLOT][3][k]);
+        if constexpr (TE) vcoef<O>(g.kb * d1[k] * (u[0][k] * u[0][k]), p.vy[SLOT][0][k], p.vy[SLOT][1][k]);
+        if constexpr (TM) vcoef<O>(g.kb * d3[k] * (u[2][k] * u[2][k]), p.vy[SLOT][2][k], p.vy[SLOT][3][k]);
       }
     }
   }
   // advance the row window
 #pragma unroll
   for (int k = 0; k < C; ++k) {
-    p.nprev[0][k] = p.ncur[0][k];
-    p.nprev[1][k] = p.ncur[2][k];
+    if constexpr (TE) p.nprev[0][k] = p.ncur[0][k];
+    if constexpr (TM) p.nprev[1][k] = p.ncur[2][k];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
+      if (!O::nlive(c)) continue;
       p.ncur[c][k] = p.nnext[c][k];
       p.nnext[c][k] = p.nn2[c][k];
       p.nn2[c][k] = nld[c][k];
     }
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
+      if (!O::live(c)) continue;
       p.q[c][k] = p.q1[c][k];
       p.q1[c][k] = qld[c][k];
     }
@@ -550,9 +622,10 @@ __device__ __forceinline__ void row_iteration(Pipe<C>& p, const StepArgs& g, con
 }
 
 // One wave's march over its segment in direction DIR.
-template <int C, bool VEC, bool WIDE, int MODE, bool POT, int DIR>
+template <int C, class O, int DIR>
 __device__ __forceinline__ void march(const StepArgs& g, const uint32_t (&xo)[C],
                                       const uint32_t (&so)[C], bool edge_lane, int y0, int seg_h) {
+  constexpr bool VEC = O::VEC;
   Pipe<C> p;
 #pragma unroll
   for (int s = 0; s < 8; ++s)
@@ -573,8 +646,20 @@ __device__ __forceinline__ void march(const StepArgs& g, const uint32_t (&xo)[C]
         p.vx[s][c][k] = 0.0f;
       }
 #pragma unroll
-    for (int k = 0; k < C; ++k) p.q14[s][0][k] = p.q14[s][1][k] = 0.0f;
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int k = 0; k < C; ++k) p.q14[s][c][k] = 0.0f;
   }
+#pragma unroll
+  for (int c = 0; c < 6; ++c)
+#pragma unroll
+    for (int k = 0; k < C; ++k) p.q[c][k] = p.q1[c][k] = 0.0f;
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int k = 0; k < C; ++k) p.ncur[c][k] = p.nnext[c][k] = p.nn2[c][k] = 1.0f;
+#pragma unroll
+  for (int k = 0; k < C; ++k) p.nprev[0][k] = p.nprev[1][k] = 1.0f;
 
   // first ingested row: 4 rows before the segment in marching order
   const int64_t R0 = DIR > 0 ? static_cast<int64_t>(y0) - 4 : static_cast<int64_t>(y0) + seg_h + 3;
@@ -588,17 +673,19 @@ __device__ __forceinline__ void march(const StepArgs& g, const uint32_t (&xo)[C]
     const float* n2 = g.n + wrap_index(R0 + 2 * DIR, g.ny) * nx64;
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
+      if (!O::live(c)) continue;
       load_row<C, VEC>(q0r + c * g.plane, g.nx, xo, p.q[c]);
       load_row<C, VEC>(q1r + c * g.plane, g.nx, xo, p.q1[c]);
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
+      if (!O::nlive(c)) continue;
       load_row<C, VEC>(n0 + c * g.plane, g.nx, xo, p.ncur[c]);
       load_row<C, VEC>(n1 + c * g.plane, g.nx, xo, p.nnext[c]);
       load_row<C, VEC>(n2 + c * g.plane, g.nx, xo, p.nn2[c]);
     }
-    load_row<C, VEC>(nm + 0 * g.plane, g.nx, xo, p.nprev[0]);
-    load_row<C, VEC>(nm + 2 * g.plane, g.nx, xo, p.nprev[1]);
+    if (O::nlive(0)) load_row<C, VEC>(nm + 0 * g.plane, g.nx, xo, p.nprev[0]);
+    if (O::nlive(2)) load_row<C, VEC>(nm + 2 * g.plane, g.nx, xo, p.nprev[1]);
   }
   // rows in flight: Q of R+2*DIR, n of R+3*DIR (wrapped incrementally)
   int rq = wrap_index(R0 + 2 * DIR, g.ny);
@@ -608,8 +695,7 @@ __device__ __forceinline__ void march(const StepArgs& g, const uint32_t (&xo)[C]
 #define QLA_ITER(S)                                                                            \
   {                                                                                            \
     const RowBases rb{g.qin + rq * nx64, g.n + rn * nx64};                                     \
-    row_iteration<C, VEC, WIDE, MODE, POT, DIR, S>(p, g, xo, so, edge_lane, i + S, seg_h, y0,  \
-                                                   rb);                                        \
+    row_iteration<C, O, DIR, S>(p, g, xo, so, edge_lane, i + S, seg_h, y0, rb);                \
     if constexpr (DIR > 0) {                                                                   \
       rq = (rq + 1 == g.ny) ? 0 : rq + 1;                                                      \
       rn = (rn + 1 == g.ny) ? 0 : rn + 1;                                                      \
@@ -647,7 +733,7 @@ struct BatchArgs {
   int waves_per_block;
 };
 
-template <int C, bool VEC, bool WIDE, int MODE, bool POT>
+template <int C, class O>
 __global__ void __launch_bounds__(256) qla_step_kernel(BatchArgs ba) {
   const int lane = threadIdx.x & (kWave - 1);
   // wave index within the block, as a wave-uniform (scalar) value
@@ -698,7 +784,7 @@ __global__ void __launch_bounds__(256) qla_step_kernel(BatchArgs ba) {
     xo[k] = 4u * static_cast<uint32_t>(wrap_index(col0 + k, g.nx));
     so[k] = (lane_in && col0 + k < g.nx) ? xo[k] : kNoStore;
   }
-  if constexpr (VEC) {
+  if constexpr (O::VEC) {
     // the lane's C columns are stored together or not at all
 #pragma unroll
     for (int k = 1; k < C; ++k) so[k] = so[0];
@@ -708,9 +794,9 @@ __global__ void __launch_bounds__(256) qla_step_kernel(BatchArgs ba) {
   // the start of both marches or at the end of both) and come from L2 for
   // the second reader.
   if (seg & 1)
-    march<C, VEC, WIDE, MODE, POT, +1>(g, xo, so, edge_lane, y0, seg_h);
+    march<C, O, +1>(g, xo, so, edge_lane, y0, seg_h);
   else
-    march<C, VEC, WIDE, MODE, POT, -1>(g, xo, so, edge_lane, y0, seg_h);
+    march<C, O, -1>(g, xo, so, edge_lane, y0, seg_h);
 }
 
 // One compiled instance of the step kernel.
@@ -720,21 +806,48 @@ struct StepImpl {
   int cols;
 };
 
-template <int C, bool VEC, bool WIDE, int MODE, bool POT>
+template <int C, class O>
 hipError_t step_blocks_per_cu(int* nb, int threads) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, qla_step_kernel<C, VEC, WIDE, MODE, POT>,
-                                                      threads, 0);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, qla_step_kernel<C, O>, threads, 0);
 }
 
-template <int C, bool VEC, bool WIDE, int MODE, bool POT>
+template <int C, class O>
 StepImpl impl() {
-  return StepImpl{reinterpret_cast<const void*>(&qla_step_kernel<C, VEC, WIDE, MODE, POT>),
-                  step_blocks_per_cu<C, VEC, WIDE, MODE, POT>, C};
+  return StepImpl{reinterpret_cast<const void*>(&qla_step_kernel<C, O>), step_blocks_per_cu<C, O>, C};
 }
 
-// The instance for a lattice-independent choice of options, one translation
-// unit per potential placement (Eq. (23): MODE 0, Eq. (28): MODE 1).
-StepImpl pick_step_eq23(bool vec, bool wide, bool pot);
-StepImpl pick_step_eq28(bool vec, bool wide, bool pot);
+// Options every instance is selected by at run time.
+struct StepChoice {
+  int mode;        // QLA_POT_EQ23 (0) or QLA_POT_EQ28 (1)
+  bool pot;        // kappa != 0
+  bool wide;
+  bool vec;
+  int fields;      // 0 all, 1 TM, 2 TE
+  int skew;        // 0 printed potentials, 1 skew-symmetric
+};
+
+// One translation unit per (placement, field triple) instantiates these.
+template <int MODE, int FIELDS>
+StepImpl pick_step(const StepChoice& ch) {
+  constexpr int C = 2;
+  auto pick_pot = [&](auto vecc, auto widec) -> StepImpl {
+    constexpr bool V = decltype(vecc)::value, Wd = decltype(widec)::value;
+    if (!ch.pot) return impl<C, KOpt<MODE, false, Wd, V, FIELDS, 0>>();
+    if (ch.skew) return impl<C, KOpt<MODE, true, Wd, V, FIELDS, 1>>();
+    return impl<C, KOpt<MODE, true, Wd, V, FIELDS, 0>>();
+  };
+  using T = std::integral_constant<bool, true>;
+  using F = std::integral_constant<bool, false>;
+  if (ch.vec) return ch.wide ? pick_pot(T{}, T{}) : pick_pot(T{}, F{});
+  return ch.wide ? pick_pot(F{}, T{}) : pick_pot(F{}, F{});
+}
+
+// The units (qla_step_inst.hip built once per placement and field triple)
+StepImpl pick_step_m0_f0(const StepChoice& ch);
+StepImpl pick_step_m0_f1(const StepChoice& ch);
+StepImpl pick_step_m0_f2(const StepChoice& ch);
+StepImpl pick_step_m1_f0(const StepChoice& ch);
+StepImpl pick_step_m1_f1(const StepChoice& ch);
+StepImpl pick_step_m1_f2(const StepChoice& ch);
 
 }  // namespace qla_dev

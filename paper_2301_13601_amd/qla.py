@@ -19,6 +19,8 @@ LIB_PATH = os.path.join(_HERE, "libqla.so")
 QLA_OK, QLA_EINVAL, QLA_ENOMEM, QLA_EDEVICE, QLA_ESTATE = 0, -1, -2, -3, -4
 POT_MODES = {"eq23": 0, "eq28": 1}
 BETA_SCALES = {"phys": 0, "lattice": 1, "off": 2}
+POLARISATIONS = {"both": 0, "tm": 1, "te": 2}
+V_FORMS = {"printed": 0, "skew": 1}
 _STATUS = {0: "QLA_OK", -1: "QLA_EINVAL", -2: "QLA_ENOMEM", -3: "QLA_EDEVICE", -4: "QLA_ESTATE"}
 
 
@@ -30,7 +32,8 @@ class QlaError(RuntimeError):
 
 class Params(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("delta", ctypes.c_double),
-                ("pot_mode", ctypes.c_int32), ("beta_scale", ctypes.c_int32)]
+                ("pot_mode", ctypes.c_int32), ("beta_scale", ctypes.c_int32),
+                ("polarisation", ctypes.c_int32), ("v_form", ctypes.c_int32)]
 
 
 class Diag(ctypes.Structure):
@@ -105,9 +108,10 @@ def _check(status: int) -> None:
         raise QlaError(status, qla_last_error())
 
 
-def make_params(nx: int, ny: int, delta: float, pot_mode: str = "eq28",
-                beta_scale: str = "phys") -> Params:
-    return Params(int(nx), int(ny), float(delta), POT_MODES[pot_mode], BETA_SCALES[beta_scale])
+def make_params(nx: int, ny: int, delta: float, pot_mode: str = "eq28", beta_scale: str = "phys",
+                polarisation: str = "both", v_form: str = "printed") -> Params:
+    return Params(int(nx), int(ny), float(delta), POT_MODES[pot_mode], BETA_SCALES[beta_scale],
+                  POLARISATIONS[polarisation], V_FORMS[v_form])
 
 
 # ---------------------------------------------------------------------------
@@ -215,7 +219,7 @@ class Simulation:
     tensors, and the libqla context bound to them."""
 
     def __init__(self, n, q0, delta: float, pot_mode: str = "eq28", beta_scale: str = "phys",
-                 device: str = "cuda:0", stream=None):
+                 device: str = "cuda:0", stream=None, polarisation: str = "both", v_form: str = "printed"):
         import torch
 
         self._torch = torch
@@ -228,7 +232,7 @@ class Simulation:
         self.n = n_t.to(self.device, torch.float32).contiguous()
         self.q = q_t.to(self.device, torch.float32).contiguous().clone()
         self.q_pong = torch.empty_like(self.q)
-        self.params = make_params(self.nx, self.ny, delta, pot_mode, beta_scale)
+        self.params = make_params(self.nx, self.ny, delta, pot_mode, beta_scale, polarisation, v_form)
         nbytes = qla_workspace_size(self.params)
         self.work = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
@@ -275,7 +279,7 @@ class Batch:
     shared workspace."""
 
     def __init__(self, ns, q0s, deltas, pot_mode: str = "eq28", beta_scale: str = "phys",
-                 device: str = "cuda:0", stream=None):
+                 device: str = "cuda:0", stream=None, polarisation: str = "both", v_form: str = "printed"):
         import torch
 
         if not (len(ns) == len(q0s) == len(deltas)) or len(ns) == 0:
@@ -299,7 +303,7 @@ class Batch:
             self.q.append(q_t)
             self.q_pong.append(qp)
             self.shapes.append((ny, nx))
-            insts.append(Instance(make_params(nx, ny, d, pot_mode, beta_scale), n_t.data_ptr(),
+            insts.append(Instance(make_params(nx, ny, d, pot_mode, beta_scale, polarisation, v_form), n_t.data_ptr(),
                                   q_t.data_ptr(), qp.data_ptr()))
         nbytes = qla_batch_workspace_size(insts)
         self.work = torch.empty(nbytes, dtype=torch.uint8, device=self.device)

@@ -68,6 +68,13 @@ def test_rejects_bad_parameters_without_a_device(qla):
     bad_scale = qla.Params(4, 4, 0.3, 1, 9)
     with pytest.raises(qla.QlaError):
         qla.qla_workspace_size(bad_scale)
+    for pol, form in [(3, 0), (-1, 0), (0, 2), (0, -1)]:
+        with pytest.raises(qla.QlaError) as ei:
+            qla.qla_workspace_size(qla.Params(4, 4, 0.3, 1, 0, pol, form))
+        assert ei.value.status == qla.QLA_EINVAL
+    for pol in ("both", "tm", "te"):
+        for form in ("printed", "skew"):
+            assert qla.qla_workspace_size(qla.make_params(8, 8, 0.3, polarisation=pol, v_form=form)) > 0
 
 
 def test_workspace_size_is_positive(qla):

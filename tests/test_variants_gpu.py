@@ -1,0 +1,212 @@
+"""GPU checks of the step kernel's variants, through the C ABI:
+
+* polarised contexts (TM: q2, q3, q4; TE: q0, q1, q5) advance only their
+  triple and agree bit for bit with the six-component kernel on it;
+* the skew-symmetric potentials agree with the oracle's skew variant to the
+  same bar as the printed ones, and conserve energy.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2301_13601_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+LIVE = {"tm": (2, 3, 4), "te": (0, 1, 5)}
+DEAD = {"tm": (0, 1, 5), "te": (2, 3, 4)}
+
+
+@pytest.fixture(scope="module")
+def qla():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2301_13601_amd import qla as q
+    q.lib()
+    return q
+
+
+def _case(tag):
+    print(f"[variants] {tag}", flush=True)
+
+
+def gpu_run(qla, n, q, delta, steps, mode="eq28", beta="phys", pol="both", form="printed", chunks=None):
+    sim = qla.Simulation(np.ascontiguousarray(n, dtype=np.float32), np.ascontiguousarray(q, dtype=np.float32),
+                         delta, mode, beta, polarisation=pol, v_form=form)
+    for k in (chunks or [steps]):
+        sim.step(k)
+    out = sim.fields("Q")
+    sim.close()
+    return out
+
+
+def oracle_run(n, q, delta, steps, mode="eq28", beta="phys", form="printed"):
+    n64 = np.asarray(n, dtype=np.float32).astype(np.float64)
+    q64 = np.asarray(q, dtype=np.float32).astype(np.float64)
+    return O.run(n64, q64, delta, steps, mode, beta, v_form=form)
+
+
+def rel_err(got, want):
+    return float(np.abs(got.astype(np.float64) - want).max() / np.abs(want).max())
+
+
+def _polarised_state(nx, ny, pol, seed):
+    q = scenes.random_state(nx, ny, seed).astype(np.float32)
+    for c in DEAD[pol]:
+        q[c] = 0.0
+    return q
+
+
+# --------------------------------------------------------------------------
+# Polarised contexts.
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("pol", ["tm", "te"])
+@pytest.mark.parametrize("mode", ["eq23", "eq28"])
+@pytest.mark.parametrize("nx,ny,profile", [(130, 66, "smooth"), (131, 67, "smooth"), (40, 24, "rough"),
+                                           (256, 96, "object")])
+@pytest.mark.parametrize("beta", ["phys", "off"])
+def test_polarised_equals_full_kernel_bitwise(qla, pol, mode, nx, ny, profile, beta):
+    seed = 3 * nx + ny
+    if profile == "smooth":
+        n = scenes.smooth_random_profile(nx, ny, seed, 1.0, 3.0)
+    elif profile == "rough":
+        n = scenes.random_profile(nx, ny, seed, 1.0, 3.0)        # wide potential angles
+    else:
+        n = scenes.object_profile(nx, ny, "ellipse", (30, 20), (1.5, 2.0, 3.0), 3.0)
+    q = _polarised_state(nx, ny, pol, seed + 1)
+    _case(f"{pol} {mode} {nx}x{ny} {profile} {beta}")
+    full = gpu_run(qla, n, q, 0.3, 9, mode, beta)
+    part = gpu_run(qla, n, q, 0.3, 9, mode, beta, pol=pol, chunks=[4, 5])
+    for c in DEAD[pol]:
+        assert np.all(full[c] == 0.0) and np.all(part[c] == 0.0), c
+    for c in LIVE[pol]:
+        assert np.array_equal(part[c], full[c]), c
+    # and the full kernel agrees with the oracle on this case
+    assert rel_err(full, oracle_run(n, q, 0.3, 9, mode, beta)) <= TOL
+
+
+@pytest.mark.parametrize("pol", ["tm", "te"])
+def test_polarised_init_and_load_clear_the_other_triple(qla, pol):
+    nx, ny = 96, 40
+    n = scenes.smooth_random_profile(nx, ny, 5, 1.0, 2.5)
+    q = scenes.random_state(nx, ny, 6).astype(np.float32)       # all six nonzero
+    qz = q.copy()
+    for c in DEAD[pol]:
+        qz[c] = 0.0
+    _case(f"{pol} init/load clearing")
+    sim = qla.Simulation(n, q, 0.3, polarisation=pol)
+    assert np.array_equal(sim.fields("Q"), qz)
+    sim.step(5)
+    want = gpu_run(qla, n, qz, 0.3, 5)
+    assert np.array_equal(sim.fields("Q"), want)
+    # a loaded state with nonzero dead planes is cleared too
+    qla.qla_load_at(sim.ctx, 0, q.ctypes.data, True)
+    assert np.array_equal(sim.fields("Q"), qz)
+    sim.step(3)
+    assert np.array_equal(sim.fields("Q"), gpu_run(qla, n, qz, 0.3, 3))
+    sim.close()
+
+
+@pytest.mark.parametrize("pol", ["tm", "te"])
+def test_polarised_batch_equals_single_runs(qla, pol):
+    specs = [(200, 120), (130, 66), (64, 250), (7, 5)]
+    ns, qs, ds = [], [], []
+    for i, (nx, ny) in enumerate(specs):
+        ns.append(scenes.smooth_random_profile(nx, ny, 40 + i, 1.0, 3.0).astype(np.float32))
+        qs.append(_polarised_state(nx, ny, pol, 50 + i))
+        ds.append(0.3 if i % 2 == 0 else 0.2)
+    _case(f"{pol} batch")
+    b = qla.Batch(ns, qs, ds, polarisation=pol)
+    b.step(6)
+    outs = b.fields("Q")
+    b.close()
+    for i in range(len(specs)):
+        assert np.array_equal(outs[i], gpu_run(qla, ns[i], qs[i], ds[i], 6)), i
+
+
+def test_polarised_full_size_bitwise(qla):
+    sc = scenes.config_scale(seed=2, N=4096, steps=10)
+    _case("tm 4096x4096 cylinder pulse, 10 steps, bitwise vs full kernel")
+    full = gpu_run(qla, sc.n, sc.q, sc.delta, sc.steps)
+    part = gpu_run(qla, sc.n, sc.q, sc.delta, sc.steps, pol="tm")
+    for c in (2, 3, 4):
+        assert np.array_equal(part[c], full[c]), c
+    for c in (0, 1, 5):
+        assert np.all(part[c] == 0.0)
+
+
+def test_polarisation_must_match_across_a_batch(qla):
+    n = scenes.uniform_profile(16, 8, (1.5, 2.0, 3.0)).astype(np.float32)
+    q = np.zeros((6, 8, 16), np.float32)
+    import torch
+    insts, keep = [], []
+    for pol in ("tm", "te"):
+        nt = torch.as_tensor(n).cuda()
+        qt = torch.as_tensor(q).cuda()
+        qp = torch.empty_like(qt)
+        keep += [nt, qt, qp]
+        insts.append(qla.Instance(qla.make_params(16, 8, 0.3, polarisation=pol), nt.data_ptr(), qt.data_ptr(),
+                                  qp.data_ptr()))
+    with pytest.raises(qla.QlaError):
+        qla.qla_batch_workspace_size(insts)
+    with pytest.raises(qla.QlaError):
+        qla.qla_workspace_size(qla.Params(16, 8, 0.3, 1, 0, 3, 0))
+    with pytest.raises(qla.QlaError):
+        qla.qla_workspace_size(qla.Params(16, 8, 0.3, 1, 0, 0, 2))
+
+
+# --------------------------------------------------------------------------
+# Skew-symmetric potentials.
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("mode", ["eq23", "eq28"])
+@pytest.mark.parametrize("nx,ny,profile", [(3, 5, "smooth"), (121, 33, "smooth"), (300, 70, "smooth"),
+                                           (40, 24, "rough"), (130, 66, "rough")])
+def test_skew_matches_oracle(qla, mode, nx, ny, profile):
+    seed = 11 * nx + ny
+    if profile == "smooth":
+        n = scenes.smooth_random_profile(nx, ny, seed, 1.0, 3.0)
+    else:
+        n = scenes.random_profile(nx, ny, seed, 1.0, 3.0)
+    q = scenes.random_state(nx, ny, seed + 1)
+    _case(f"skew {mode} {nx}x{ny} {profile}")
+    got = gpu_run(qla, n, q, 0.3, 8, mode, form="skew")
+    want = oracle_run(n, q, 0.3, 8, mode, form="skew")
+    assert rel_err(got, want) <= TOL
+    # and it is not the printed method
+    assert rel_err(got, oracle_run(n, q, 0.3, 8, mode)) > 1e-3
+
+
+@pytest.mark.parametrize("pol", ["Ez", "Ey"])
+def test_skew_full_run_conserves_energy(qla, pol):
+    sc = scenes.config_single()
+    q0 = sc.q if pol == "Ez" else scenes.gaussian_pulse(256, 256, "Ey", 48, 20)
+    _case(f"skew 256x256 {pol} 500 steps")
+    got = gpu_run(qla, sc.n, q0, sc.delta, sc.steps, "eq28", form="skew")
+    want = oracle_run(sc.n, q0, sc.delta, sc.steps, "eq28", form="skew")
+    # FP32 rounding accumulates over the 500 steps at the same absolute rate
+    # as for the printed potentials (measured: 1.4e-5 against 1.0e-5 for
+    # the E_y run, growing slowly, not linearly, with the step count). The
+    # printed runs end with max |q| grown by the energy gain; the skew run
+    # keeps max |q| near its initial 1, so the bar here is 2e-5 of max |q0|.
+    err = float(np.abs(got.astype(np.float64) - want).max() / np.abs(np.asarray(q0, np.float32)).max())
+    assert err <= 2e-5, err
+    e0 = O.energy(np.asarray(q0, np.float32))
+    drift = O.energy(got) / e0 - 1
+    print(f"  energy drift gpu {drift:+.3e} oracle {O.energy(want) / e0 - 1:+.3e}")
+    assert abs(O.energy(want) / e0 - 1) < 1e-12
+    assert abs(drift) < 1e-4
+
+
+@pytest.mark.parametrize("pol", ["tm", "te"])
+def test_skew_polarised_equals_skew_full_bitwise(qla, pol):
+    n = scenes.object_profile(200, 90, "ellipse", (30, 20), (1.5, 2.0, 3.0), 3.0)
+    q = _polarised_state(200, 90, pol, 8)
+    _case(f"skew {pol} bitwise")
+    full = gpu_run(qla, n, q, 0.3, 12, form="skew")
+    part = gpu_run(qla, n, q, 0.3, 12, pol=pol, form="skew")
+    for c in LIVE[pol]:
+        assert np.array_equal(part[c], full[c]), c

@@ -49,9 +49,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per step-kernel launch from the committed rocprofv3 counter
-    runs, if they were taken on the current kernel source."""
+def measured_traffic(triple: str = "all"):
+    """HBM bytes per step-kernel launch (triple "all" or "tm") from the
+    committed rocprofv3 counter runs, if they were taken on the current
+    kernel source."""
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f)
@@ -59,14 +60,26 @@ def measured_traffic():
         return None
     if rec.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
-    return rec.get("bytes_per_launch")
+    return rec.get("kernels", {}).get(triple, {}).get("bytes_per_launch")
+
+
+_TRIPLE_NAMES = {"0": "all", "1": "tm", "2": "te"}
+
+
+def _triple_of(kernel_name: str):
+    """Field triple of a step-kernel instance from its demangled name
+    (the fifth option of its KOpt), or None for other kernels."""
+    import re
+    m = re.search(r"qla_step_kernel<\d+, (?:qla_dev::)?KOpt<[^,]+, [^,]+, [^,]+, [^,]+, (\d+), \d+>", kernel_name)
+    return _TRIPLE_NAMES.get(m.group(1)) if m else None
 
 
 def summarize_counters(fetch_csv: str, write_csv: str, copy_mib: int, out_path: str) -> dict:
     """Turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per
-    dispatch) of this script into HBM bytes per step-kernel launch, scaled by
-    what the same counters read for the plain device copy of copy_mib MiB the
-    runs include (--calib-copy-mib)."""
+    dispatch) of this script into HBM bytes per step-kernel launch, per
+    kernel instance (all six components, TM triple), scaled by what the same
+    counters read for the plain device copy of copy_mib MiB the runs include
+    (--calib-copy-mib)."""
     import csv
 
     def rows(path):
@@ -74,19 +87,26 @@ def summarize_counters(fetch_csv: str, write_csv: str, copy_mib: int, out_path: 
             return list(csv.DictReader(f))
 
     copy_bytes = copy_mib * (1 << 20)
-    out = {"kernel_source_sha256_16": kernel_source_hash(), "copy_bytes": copy_bytes}
+    out = {"kernel_source_sha256_16": kernel_source_hash(), "copy_bytes": copy_bytes, "kernels": {}}
     for tag, path in (("fetch", fetch_csv), ("write", write_csv)):
         rs = rows(path)
-        step = [float(r["Counter_Value"]) for r in rs if "qla_step_kernel" in r["Kernel_Name"]]
         # the calibration copy is the largest copy dispatch of the run
-        copies = [float(r["Counter_Value"]) for r in rs if "copyBuffer" in r["Kernel_Name"]
-                  or "copy" in r["Kernel_Name"].lower()]
+        copies = [float(r["Counter_Value"]) for r in rs if "copy" in r["Kernel_Name"].lower()]
         cal = max(copies) * 1024.0
         factor = copy_bytes / cal
-        out[tag] = {"kib_per_launch_raw": sum(step) / len(step), "launches": len(step),
-                    "copy_kib_raw": cal / 1024.0, "scale": factor,
-                    "bytes_per_launch": sum(step) / len(step) * 1024.0 * factor}
-    out["bytes_per_launch"] = out["fetch"]["bytes_per_launch"] + out["write"]["bytes_per_launch"]
+        per = {}
+        for r in rs:
+            t = _triple_of(r["Kernel_Name"])
+            if t is not None:
+                per.setdefault(t, []).append(float(r["Counter_Value"]))
+        for t, vals in per.items():
+            k = out["kernels"].setdefault(t, {})
+            k[tag] = {"kib_per_launch_raw": sum(vals) / len(vals), "launches": len(vals),
+                      "copy_kib_raw": cal / 1024.0, "scale": factor,
+                      "bytes_per_launch": sum(vals) / len(vals) * 1024.0 * factor}
+    for k in out["kernels"].values():
+        if "fetch" in k and "write" in k:
+            k["bytes_per_launch"] = k["fetch"]["bytes_per_launch"] + k["write"]["bytes_per_launch"]
     with open(out_path, "w") as f:
         json.dump(out, f, indent=1)
     return out
@@ -143,7 +163,7 @@ def is_tm_only(q) -> bool:
     return all(not np.any(q[c]) for c in (0, 1, 5))
 
 
-def time_polarised(make_sim, stream, sites: int, steps: int, warmup: int) -> dict:
+def time_polarised(make_sim, stream, sites: int, steps: int, warmup: int, traffic=None) -> dict:
     """The same workload on the polarised kernel (TM triple only), timed
     like the headline run (whole job on the wall clock, kernel time from
     HIP events on the launch stream)."""
@@ -175,7 +195,7 @@ def time_polarised(make_sim, stream, sites: int, steps: int, warmup: int) -> dic
     return {"polarisation": "tm (q2, q3, q4 = n_z E_z, B_x, B_y)", "steps": steps,
             "value": sites * steps / wall, "unit": "site-updates/s",
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": achieved / HBM_PEAK_GBS, "avg_launch_us": avg * 1e6,
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "avg_launch_us": avg * 1e6,
                          "algo_bytes_per_site": TM_BYTES_PER_SITE}}
 
 
@@ -278,7 +298,7 @@ def main():
 
     value = sites * args.steps / wall
     achieved = sites * ALGO_BYTES_PER_SITE / avg_launch_s / 1e9
-    traffic = measured_traffic() if args.workload == "cylinder_4096" else None
+    traffic = measured_traffic("all") if args.workload == "cylinder_4096" else None
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "kernel": "qla_step_kernel", "avg_launch_us": avg_launch_s * 1e6,
@@ -304,7 +324,8 @@ def main():
     }
     sim.close()
     if args.polarised_steps > 0 and not batch and is_tm_only(sc.q):
-        out["polarised"] = time_polarised(make_sim, stream, sites, args.polarised_steps, args.warmup)
+        out["polarised"] = time_polarised(make_sim, stream, sites, args.polarised_steps, args.warmup,
+                                          measured_traffic("tm") if args.workload == "cylinder_4096" else None)
     if not args.no_cpu_baseline:
         first = sc[0] if batch else sc
         sample_n = min(args.cpu_sample_n, first.nx)

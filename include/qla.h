@@ -115,19 +115,27 @@ typedef struct qla_ctx qla_ctx;   /* opaque */
 
 /* Launch geometry of the fused step kernel (a tuning knob, not part of the
  * method; results are bitwise identical for every geometry). A wave owns 128
- * lattice columns (120 of them output) and a segment of seg_rows rows.
- * A field set to 0 asks for the library's default.
+ * lattice columns (120 of them output; 112 when a launch advances two
+ * steps) and a segment of seg_rows rows. A field set to 0 asks for the
+ * library's default.
  *   seg_rows         rows per wave segment, rounded up to a multiple of 4
  *                    (default: the shortest for which the whole grid is
  *                    resident at once)
  *   waves_per_block  1..4 waves (vertically adjacent segments) per block
  *                    (default 1)
- *   graph_steps      steps per replayed HIP graph (rounded up to even);
- *                    1 launches every step on its own (default 32) */
+ *   graph_steps      steps per replayed HIP graph (rounded up to a multiple
+ *                    of 2 * steps_per_pass); 1 launches every pass on its
+ *                    own (default 32)
+ *   steps_per_pass   1 or 2 time steps per launch (default 2). With 2, each
+ *                    wave runs the step twice in one march over its rows
+ *                    (temporal blocking: Q and n cross HBM once per two
+ *                    steps); an odd remainder of a qla_step call runs as one
+ *                    one-step launch. */
 typedef struct {
     int32_t seg_rows;
     int32_t waves_per_block;
     int32_t graph_steps;
+    int32_t steps_per_pass;
 } qla_launch;
 
 /* One lattice of a batch: its parameters and caller-owned device buffers

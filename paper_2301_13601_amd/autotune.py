@@ -1,8 +1,9 @@
 """Launch-geometry autotuner for the fused QLA step.
 
 For a set of lattice shapes (one lattice or a batch) and the potential
-placement, time a small set of launch geometries (segment height, waves per
-block, steps per replayed graph) on the GPU and keep the fastest. Results
+placement, time a small set of launch geometries (steps per launch, segment
+height, waves per block, steps per replayed graph) on the GPU and keep the
+fastest. Results
 are cached as JSON keyed by GPU architecture, placement and shapes, so a
 second call for the same key measures nothing.
 
@@ -23,11 +24,12 @@ DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "qla_autotune.js
 
 def _key(arch: str, pot_mode: str, beta_scale: str, shapes: Sequence[Tuple[int, int]]) -> str:
     h = hashlib.sha256(json.dumps(sorted(shapes)).encode()).hexdigest()[:16]
-    return f"{arch}|{pot_mode}|{beta_scale}|n{len(shapes)}|{h}"
+    return f"{arch}|{pot_mode}|{beta_scale}|n{len(shapes)}|{h}|spp12"
 
 
-def candidates(default_seg: int, max_ny: int) -> List[Dict[str, int]]:
-    """Geometries to try around the library's default segment height."""
+def candidates(default_seg: int, max_ny: int, steps_per_pass: int = 1) -> List[Dict[str, int]]:
+    """Geometries to try around the library's default segment height for
+    launches of ``steps_per_pass`` steps."""
     segs = {default_seg}
     for f in (0.5, 0.75, 1.5, 2.0, 3.0):
         s = int(round(default_seg * f / 4.0)) * 4
@@ -36,8 +38,10 @@ def candidates(default_seg: int, max_ny: int) -> List[Dict[str, int]]:
     out = []
     for s in sorted(segs):
         for wpb in (1, 2):
-            out.append({"seg_rows": s, "waves_per_block": wpb, "graph_steps": 32})
-    out.append({"seg_rows": default_seg, "waves_per_block": 1, "graph_steps": 1})
+            out.append({"seg_rows": s, "waves_per_block": wpb, "graph_steps": 32,
+                        "steps_per_pass": steps_per_pass})
+    out.append({"seg_rows": default_seg, "waves_per_block": 1, "graph_steps": 1,
+                "steps_per_pass": steps_per_pass})
     return out
 
 
@@ -85,8 +89,12 @@ def tune(ns: Sequence, deltas: Sequence[float], pot_mode: str = "eq28", beta_sca
     try:
         default = batch.launch()
         max_ny = max(s[0] for s in shapes)
+        cands = []
+        for spp in (1, 2):
+            batch.set_launch(steps_per_pass=spp)
+            cands += candidates(batch.launch()["seg_rows"], max_ny, spp)
         measured = []
-        for cfg in candidates(default["seg_rows"], max_ny):
+        for cfg in cands:
             batch.set_launch(**cfg)
             batch.step(2 * max(cfg["graph_steps"], 1))          # builds and warms the graphs
             torch.cuda.synchronize()

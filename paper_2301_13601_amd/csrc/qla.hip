@@ -238,15 +238,19 @@ qla_status fail(qla_status st, const char* fmt, ...) {
 
 constexpr uint64_t kMagic = 0x514c41435458ull;   // "QLACTX"
 constexpr int kDefaultGraphSteps = 32;
+constexpr int kDefaultStepsPerPass = 2;
 constexpr int kCols = 2;                          // lattice columns per lane
-constexpr int kOutCols = (kWave - 2 * ((4 + kCols - 1) / kCols)) * kCols;
+// output columns of a strip for a launch of `steps` steps (x support 4 per step)
+constexpr int out_cols(int steps) { return (kWave - 2 * ((4 * steps + kCols - 1) / kCols)) * kCols; }
 
 size_t align256(size_t v) { return (v + 255) & ~static_cast<size_t>(255); }
 
-// workspace layout: diagnostics partials | scan partials | lattice descriptors
+// workspace layout: diagnostics partials | scan partials | lattice
+// descriptors of the one-step launch | of the two-step launch
 size_t diag_bytes() { return align256(static_cast<size_t>(kDiagBlocks + 1) * kDiagVals * sizeof(double)); }
 size_t scan_bytes() { return align256(static_cast<size_t>(kDiagBlocks + 1) * sizeof(ScanPartial)); }
-size_t work_bytes(int count) { return diag_bytes() + scan_bytes() + align256(sizeof(InstDesc) * count); }
+size_t desc_bytes(int count) { return align256(sizeof(InstDesc) * count); }
+size_t work_bytes(int count) { return diag_bytes() + scan_bytes() + 2 * desc_bytes(count); }
 
 }  // namespace
 
@@ -276,11 +280,16 @@ struct qla_ctx {
   int cus;
   qla_launch launch;       // requested geometry (0 fields: default)
   qla_launch planned;      // geometry in use
-  std::vector<InstDesc> desc;
-  InstDesc* d_desc;
-  dim3 grid, block;
   StepImpl step;
-  hipGraphExec_t graph[2]; // graph_steps steps starting from buffer 0 / 1
+  dim3 block;
+  // per steps-per-launch (index 0: one step, 1: two steps)
+  struct Geometry {
+    std::vector<InstDesc> desc;
+    InstDesc* d_desc;
+    dim3 grid;
+    int seg_rows;
+    hipGraphExec_t graph[2];   // graph_steps steps starting from buffer 0 / 1
+  } geo[2];
 };
 
 namespace {
@@ -355,42 +364,26 @@ hipError_t clear_dead(qla_ctx* c, int i, int b) {
 }
 
 void drop_graphs(qla_ctx* c) {
-  for (auto& g : c->graph) {
-    if (g) (void)hipGraphExecDestroy(g);
-    g = nullptr;
-  }
+  for (auto& geo : c->geo)
+    for (auto& g : geo.graph) {
+      if (g) (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
 }
 
-// Launch geometry. A wave covers 128 columns of which 120 are output; each
-// lattice is cut into strips (x) and segments (y). Unless a segment height
-// is requested, the planner picks the smallest height (a multiple of 4) for
-// which the whole grid is resident at once (one round, no tail); taller
-// segments re-read fewer halo rows (8 per segment).
-qla_status plan_step(qla_ctx* c) {
-  const int wpb = c->launch.waves_per_block > 0 ? c->launch.waves_per_block : 1;
-  if (wpb > 4) return fail(QLA_EINVAL, "qla: waves_per_block must be 1..4");
-  int gsteps = c->launch.graph_steps > 0 ? c->launch.graph_steps : kDefaultGraphSteps;
-  if (gsteps > 1) gsteps = (gsteps + 1) & ~1;     // even: a replay returns to the same buffer
-  bool vec = true;
+// Launch geometry. A wave covers 128 columns of which 120 are output (112
+// for a two-step launch); each lattice is cut into strips (x) and segments
+// (y). Unless a segment height is requested, the planner picks the smallest
+// height (a multiple of 4) for which the whole grid is resident at once (one
+// round, no tail); taller segments re-read fewer halo rows (8 per segment
+// per step).
+qla_status plan_geometry(qla_ctx* c, int steps, int wpb) {
+  auto& geo = c->geo[steps - 1];
+  const int oc = out_cols(steps);
   int max_ny = 1;
-  for (const auto& p : c->p) {
-    vec = vec && (p.nx % kCols) == 0;
-    max_ny = std::max(max_ny, p.ny);
-  }
-  qla_dev::StepChoice ch;
-  ch.mode = c->pot_mode;
-  ch.pot = c->beta_scale != QLA_BETA_OFF;
-  ch.wide = c->wide;
-  ch.vec = vec;
-  ch.fields = c->polarisation;
-  ch.skew = c->v_form;
-  using Pick = StepImpl (*)(const qla_dev::StepChoice&);
-  static constexpr Pick kPick[2][3] = {
-      {qla_dev::pick_step_m0_f0, qla_dev::pick_step_m0_f1, qla_dev::pick_step_m0_f2},
-      {qla_dev::pick_step_m1_f0, qla_dev::pick_step_m1_f1, qla_dev::pick_step_m1_f2}};
-  c->step = kPick[ch.mode][ch.fields](ch);
+  for (const auto& p : c->p) max_ny = std::max(max_ny, p.ny);
   std::vector<int> nstrips(c->count);
-  for (int i = 0; i < c->count; ++i) nstrips[i] = (c->p[i].nx + kOutCols - 1) / kOutCols;
+  for (int i = 0; i < c->count; ++i) nstrips[i] = (c->p[i].nx + oc - 1) / oc;
   auto blocks_for = [&](int S) {
     int64_t t = 0;
     for (int i = 0; i < c->count; ++i) {
@@ -402,7 +395,7 @@ qla_status plan_step(qla_ctx* c) {
   int S = c->launch.seg_rows;
   if (S <= 0) {
     int bpc = 0;
-    hipError_t e = c->step.blocks_per_cu(&bpc, kWave * wpb);
+    hipError_t e = c->step.blocks_per_cu[steps - 1](&bpc, kWave * wpb);
     if (e != hipSuccess || bpc < 1) bpc = 1;
     const int64_t slots = static_cast<int64_t>(c->cus) * bpc;
     const int top = (max_ny + 3) & ~3;
@@ -417,11 +410,11 @@ qla_status plan_step(qla_ctx* c) {
   S = std::max(4, (S + 3) & ~3);
   const int64_t total = blocks_for(S);
   if (total > (int64_t{1} << 30)) return fail(QLA_EINVAL, "qla: launch geometry too large");
-  c->desc.assign(c->count, InstDesc{});
+  geo.desc.assign(c->count, InstDesc{});
   int first = 0;
   for (int i = 0; i < c->count; ++i) {
     const qla_params& p = c->p[i];
-    InstDesc& d = c->desc[i];
+    InstDesc& d = geo.desc[i];
     d.q[0] = c->buf[0][i];
     d.q[1] = c->buf[1][i];
     d.n = c->n[i];
@@ -436,41 +429,78 @@ qla_status plan_step(qla_ctx* c) {
     d.kb = static_cast<float>(kb_of(p));
     first += d.nstrips * ((d.nsegs + wpb - 1) / wpb);
   }
-  hipError_t e = hipMemcpyAsync(c->d_desc, c->desc.data(), sizeof(InstDesc) * c->count,
+  hipError_t e = hipMemcpyAsync(geo.d_desc, geo.desc.data(), sizeof(InstDesc) * c->count,
                                 hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "uploading the lattice descriptors");
-  c->grid = dim3(static_cast<unsigned>(total));
-  c->block = dim3(kWave * wpb);
-  c->planned = qla_launch{S, wpb, gsteps};
-  drop_graphs(c);
+  geo.grid = dim3(static_cast<unsigned>(total));
+  geo.seg_rows = S;
   return QLA_OK;
 }
 
-BatchArgs batch_args(const qla_ctx* c, int parity) {
-  return BatchArgs{c->d_desc, c->count, parity, static_cast<int>(c->block.x / kWave)};
+qla_status plan_step(qla_ctx* c) {
+  const int wpb = c->launch.waves_per_block > 0 ? c->launch.waves_per_block : 1;
+  if (wpb > 4) return fail(QLA_EINVAL, "qla: waves_per_block must be 1..4");
+  const int spp = c->launch.steps_per_pass > 0 ? c->launch.steps_per_pass : kDefaultStepsPerPass;
+  if (spp > 2) return fail(QLA_EINVAL, "qla: steps_per_pass must be 1 or 2");
+  int gsteps = c->launch.graph_steps > 0 ? c->launch.graph_steps : kDefaultGraphSteps;
+  // a replay must return to the buffer it started from: an even number of
+  // launches
+  const int unit = 2 * spp;
+  if (gsteps > 1) gsteps = (gsteps + unit - 1) / unit * unit;
+  bool vec = true;
+  for (const auto& p : c->p) vec = vec && (p.nx % kCols) == 0;
+  qla_dev::StepChoice ch;
+  ch.mode = c->pot_mode;
+  ch.pot = c->beta_scale != QLA_BETA_OFF;
+  ch.wide = c->wide;
+  ch.vec = vec;
+  ch.fields = c->polarisation;
+  ch.skew = c->v_form;
+  using Pick = StepImpl (*)(const qla_dev::StepChoice&);
+  static constexpr Pick kPick[2][3] = {
+      {qla_dev::pick_step_m0_f0, qla_dev::pick_step_m0_f1, qla_dev::pick_step_m0_f2},
+      {qla_dev::pick_step_m1_f0, qla_dev::pick_step_m1_f1, qla_dev::pick_step_m1_f2}};
+  c->step = kPick[ch.mode][ch.fields](ch);
+  drop_graphs(c);
+  for (int steps = 1; steps <= 2; ++steps) {
+    qla_status st = plan_geometry(c, steps, wpb);
+    if (st != QLA_OK) return st;
+  }
+  c->block = dim3(kWave * wpb);
+  c->planned = qla_launch{c->geo[spp - 1].seg_rows, wpb, gsteps, spp};
+  return QLA_OK;
 }
 
-hipError_t launch_one(qla_ctx* c, int parity) {
-  BatchArgs a = batch_args(c, parity);
+BatchArgs batch_args(const qla_ctx* c, int steps, int parity) {
+  return BatchArgs{c->geo[steps - 1].d_desc, c->count, parity, static_cast<int>(c->block.x / kWave)};
+}
+
+// One launch advancing `steps` (1 or 2) time steps from buffer `parity`.
+hipError_t launch_one(qla_ctx* c, int steps, int parity) {
+  BatchArgs a = batch_args(c, steps, parity);
   void* args[] = {&a};
-  return hipLaunchKernel(c->step.func, c->grid, c->block, args, 0, c->stream);
+  return hipLaunchKernel(c->step.func[steps - 1], c->geo[steps - 1].grid, c->block, args, 0, c->stream);
 }
 
-// A graph of graph_steps consecutive step launches (alternating buffers),
-// built node by node so that it can be replayed on any stream.
+// A graph of graph_steps consecutive steps (launches of steps_per_pass
+// steps, alternating buffers), built node by node so that it can be
+// replayed on any stream.
 hipError_t build_graph(qla_ctx* c, int parity) {
+  const int spp = c->planned.steps_per_pass;
+  auto& geo = c->geo[spp - 1];
   hipGraph_t g = nullptr;
   hipError_t e = hipGraphCreate(&g, 0);
   if (e != hipSuccess) return e;
   hipGraphNode_t prev = nullptr;
-  std::vector<BatchArgs> args(c->planned.graph_steps);
-  for (int j = 0; j < c->planned.graph_steps && e == hipSuccess; ++j) {
-    args[j] = batch_args(c, parity ^ (j & 1));
+  const int launches = c->planned.graph_steps / spp;
+  std::vector<BatchArgs> args(launches);
+  for (int j = 0; j < launches && e == hipSuccess; ++j) {
+    args[j] = batch_args(c, spp, parity ^ (j & 1));
     void* kp[] = {&args[j]};
     hipKernelNodeParams np{};
-    np.func = const_cast<void*>(c->step.func);
-    np.gridDim = c->grid;
+    np.func = const_cast<void*>(c->step.func[spp - 1]);
+    np.gridDim = geo.grid;
     np.blockDim = c->block;
     np.sharedMemBytes = 0;
     np.kernelParams = kp;
@@ -479,7 +509,7 @@ hipError_t build_graph(qla_ctx* c, int parity) {
     e = hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &np);
     prev = node;
   }
-  if (e == hipSuccess) e = hipGraphInstantiate(&c->graph[parity], g, nullptr, nullptr, 0);
+  if (e == hipSuccess) e = hipGraphInstantiate(&geo.graph[parity], g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   return e;
 }
@@ -541,11 +571,13 @@ qla_status init_common(int32_t count, const qla_instance* inst, void* d_work, vo
   }
   c->cur = 0;
   c->work = d_work;
-  c->d_desc = reinterpret_cast<InstDesc*>(static_cast<char*>(d_work) + diag_bytes() + scan_bytes());
+  c->geo[0].d_desc = reinterpret_cast<InstDesc*>(static_cast<char*>(d_work) + diag_bytes() + scan_bytes());
+  c->geo[1].d_desc = reinterpret_cast<InstDesc*>(static_cast<char*>(d_work) + diag_bytes() + scan_bytes() +
+                                                 desc_bytes(count));
   c->stream = static_cast<hipStream_t>(hip_stream);
   c->steps = 0;
   c->poisoned = false;
-  c->graph[0] = c->graph[1] = nullptr;
+  for (auto& geo : c->geo) geo.graph[0] = geo.graph[1] = nullptr;
   double theta_max = 0.0, bmax = 0.0;
   for (int i = 0; i < count; ++i) {
     st = scan_instance(c, i, &theta_max, &bmax);
@@ -570,7 +602,7 @@ qla_status init_common(int32_t count, const qla_instance* inst, void* d_work, vo
     return hip_fail(nullptr, e == hipSuccess ? hipErrorInvalidDevice : e, "querying the device");
   }
   c->cus = cus;
-  c->launch = qla_launch{0, 0, 0};
+  c->launch = qla_launch{0, 0, 0, 0};
   st = plan_step(c);
   if (st != QLA_OK) {
     delete c;
@@ -628,21 +660,24 @@ qla_status qla_step(qla_ctx* ctx, int64_t nsteps) {
   if (st != QLA_OK) return st;
   if (nsteps < 0) return fail(QLA_EINVAL, "qla: negative step count");
   const int gsteps = ctx->planned.graph_steps;
+  const int spp = ctx->planned.steps_per_pass;
+  auto& graph = ctx->geo[spp - 1].graph;
   hipError_t e = hipSuccess;
   while (e == hipSuccess && nsteps > 0) {
     if (gsteps > 1 && nsteps >= gsteps) {
-      if (!ctx->graph[ctx->cur]) {
+      if (!graph[ctx->cur]) {
         e = build_graph(ctx, ctx->cur);
         if (e != hipSuccess) return hip_fail(ctx, e, "building the step graph");
       }
-      e = hipGraphLaunch(ctx->graph[ctx->cur], ctx->stream);
+      e = hipGraphLaunch(graph[ctx->cur], ctx->stream);
       nsteps -= gsteps;
-      ctx->steps += gsteps;      // an even count: the state stays in buffer cur
+      ctx->steps += gsteps;      // an even number of launches: the state stays in buffer cur
     } else {
-      e = launch_one(ctx, ctx->cur);
+      const int k = (spp == 2 && nsteps >= 2) ? 2 : 1;
+      e = launch_one(ctx, k, ctx->cur);
       ctx->cur ^= 1;
-      ++ctx->steps;
-      --nsteps;
+      ctx->steps += k;
+      nsteps -= k;
     }
   }
   if (e == hipSuccess) e = hipGetLastError();
@@ -759,7 +794,8 @@ qla_status qla_set_launch(qla_ctx* ctx, const qla_launch* req) {
   if (st != QLA_OK) return st;
   if (!req) return fail(QLA_EINVAL, "qla: null launch pointer");
   if (req->seg_rows < 0 || req->seg_rows > (1 << 28) || req->waves_per_block < 0 ||
-      req->waves_per_block > 4 || req->graph_steps < 0 || req->graph_steps > 4096)
+      req->waves_per_block > 4 || req->graph_steps < 0 || req->graph_steps > 4096 ||
+      req->steps_per_pass < 0 || req->steps_per_pass > 2)
     return fail(QLA_EINVAL, "qla: launch fields out of range");
   const qla_launch keep = ctx->launch;
   ctx->launch = *req;

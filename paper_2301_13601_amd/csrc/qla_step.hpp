@@ -134,9 +134,11 @@ struct StepArgs {
   float kb;                        // kappa * frac / 2             (Eq. (25))
 };
 
-template <int C>
+// Columns of a strip: a pass of STEPS steps has an x support of 4*STEPS
+// cells on each side, held by the outermost halo lanes.
+template <int C, int STEPS = 1>
 struct Cols {
-  static constexpr int kHaloLanes = (4 + C - 1) / C;
+  static constexpr int kHaloLanes = (4 * STEPS + C - 1) / C;
   static constexpr int kOut = (kWave - 2 * kHaloLanes) * C;   // output columns per strip
 };
 
@@ -288,21 +290,39 @@ __device__ __forceinline__ void vcoef(float b, float& c0, float& c1) {
     pot_coef<O::WIDE>(b, c0, c1);
 }
 
-template <int C, class O, int DIR, int SLOT>
-__device__ __forceinline__ void row_iteration(Pipe<C>& p, const StepArgs& g, const uint32_t (&xo)[C],
-                                              const uint32_t (&so)[C], bool edge_lane, int i,
-                                              int seg_h, int y0, const RowBases& rb) {
-  constexpr bool VEC = O::VEC, WIDE = O::WIDE, POT = O::POT, TE = O::TE, TM = O::TM;
-  constexpr int MODE = O::MODE;
-  // ---- prefetch Q of row R+2*DIR and n of row R+3*DIR ---------------------
-  float qld[6][C];
-  float nld[3][C];
+// Prefetch of the rows a pipeline needs later: Q of row R+2*DIR (stage fed
+// from memory only) and n of row R+3*DIR.
+template <int C, class O>
+__device__ __forceinline__ void load_q(const StepArgs& g, const float* row, const uint32_t (&xo)[C],
+                                       float (&qld)[6][C]) {
 #pragma unroll
   for (int c = 0; c < 6; ++c)
-    if (O::live(c)) load_row<C, VEC>(rb.qld + c * g.plane, g.nx, xo, qld[c]);
+    if (O::live(c)) load_row<C, O::VEC>(row + c * g.plane, g.nx, xo, qld[c]);
+}
+
+template <int C, class O>
+__device__ __forceinline__ void load_n(const StepArgs& g, const float* row, const uint32_t (&xo)[C],
+                                       float (&nld)[3][C]) {
 #pragma unroll
   for (int c = 0; c < 3; ++c)
-    if (O::nlive(c)) load_row<C, VEC>(rb.nld + c * g.plane, g.nx, xo, nld[c]);
+    if (O::nlive(c)) load_row<C, O::VEC>(row + c * g.plane, g.nx, xo, nld[c]);
+}
+
+// One row iteration of a y pipeline: the whole step of Eq. (23)/(28) on
+// the ingested row R (p.q) for the x sweep, and on the rows in flight for
+// the y sweep; the row at lag 4 leaves the pipeline fully stepped. With
+// EMIT it is handed over in `emit` (all six components, for a second
+// pipeline stage); otherwise it is stored to g.qout when it lies in the
+// segment. LAG0 is the iteration at which this pipeline ingests the first
+// row of the segment (4 for a pipeline fed from memory, 12 for the second
+// stage of a two-step pass), so that rows map to iterations as
+// R = y0 + i - LAG0 (marching in +y).
+template <int C, class O, int DIR, int SLOT, bool EMIT, int LAG0>
+__device__ __forceinline__ void process_row(Pipe<C>& p, const StepArgs& g, const uint32_t (&so)[C],
+                                            bool edge_lane, int i, int seg_h, int y0,
+                                            float (&emit)[6][C]) {
+  constexpr bool VEC = O::VEC, WIDE = O::WIDE, POT = O::POT, TE = O::TE, TM = O::TM;
+  constexpr int MODE = O::MODE;
 
   // ---- coefficients of row R (Eq. (24), (25)) -----------------------------
   float u[3][C];
@@ -418,11 +438,11 @@ __device__ __forceinline__ void row_iteration(Pipe<C>& p, const StepArgs& g, con
 
   // rows of this iteration relative to y0: R, and R - 4*DIR which leaves
   // the pipeline; both lie in the segment for the same range of i
-  const int R_rel = DIR > 0 ? i - 4 : seg_h + 3 - i;
-  const int O_rel = DIR > 0 ? i - 8 : seg_h + 7 - i;
-  const bool R_out = i >= 4 && i < seg_h + 4;
-  const bool O_out = i >= 8 && i < seg_h + 8;
-  if constexpr (MODE == 1) {
+  const int R_rel = DIR > 0 ? i - LAG0 : seg_h + LAG0 - 1 - i;
+  const int O_rel = DIR > 0 ? i - LAG0 - 4 : seg_h + LAG0 + 3 - i;
+  const bool R_out = i >= LAG0 && i < seg_h + LAG0;
+  const bool O_out = i >= LAG0 + 4 && i < seg_h + LAG0 + 4;
+  if constexpr (MODE == 1 && !EMIT) {
     // q1 and q4 are final once U_X and V_X' are done: U_Y and V_Y leave them
     if (R_out) {
       float* row = g.qout + static_cast<int64_t>(y0 + R_rel) * g.nx;
@@ -536,7 +556,26 @@ __device__ __forceinline__ void row_iteration(Pipe<C>& p, const StepArgs& g, con
       vy_apply(std::integral_constant<int, 4>{});
     }
   }
-  if (O_out) {
+  if constexpr (EMIT) {
+    if constexpr (MODE == 1) {
+      // q1, q4 of the row at lag 4, kept since its x sweep
+      constexpr int sl = (SLOT - 4) & 3;
+#pragma unroll
+      for (int k = 0; k < C; ++k) {
+        o1[k] = p.q14[sl][0][k];
+        o4[k] = p.q14[sl][1][k];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+      emit[0][k] = a0[k];
+      emit[1][k] = o1[k];
+      emit[2][k] = b2[k];
+      emit[3][k] = b3[k];
+      emit[4][k] = o4[k];
+      emit[5][k] = a5[k];
+    }
+  } else if (O_out) {
     float* row = g.qout + static_cast<int64_t>(y0 + O_rel) * g.nx;
     if constexpr (TE) store_row<C, VEC>(row + 0 * g.plane, g.nx, so, a0);
     if constexpr (TM) store_row<C, VEC>(row + 2 * g.plane, g.nx, so, b2);
@@ -561,12 +600,14 @@ __device__ __forceinline__ void row_iteration(Pipe<C>& p, const StepArgs& g, con
       p.th[SLOT][3][k] = sc[2][k];
     }
   }
-  if constexpr (MODE == 0) {
+  if constexpr (MODE == 0 || EMIT) {
 #pragma unroll
     for (int k = 0; k < C; ++k) {
       if constexpr (TE) p.q14[SLOT][0][k] = p.q[1][k];
       if constexpr (TM) p.q14[SLOT][1][k] = p.q[4][k];
     }
+  }
+  if constexpr (MODE == 0) {
     if constexpr (POT) {
       p.fx[SLOT] = fx;
 #pragma unroll
@@ -600,11 +641,17 @@ __device__ __forceinline__ void row_iteration(Pipe<C>& p, const StepArgs& g, con
       }
     }
   }
-  // advance the row window
+}
+
+// Advance a pipeline's row window by one row: n rows shift by one (nld is
+// n of row R+3*DIR); with FEED, Q rows too (qld is Q of row R+2*DIR), else
+// the caller puts the next ingested row into p.q.
+template <int C, class O, bool FEED>
+__device__ __forceinline__ void advance(Pipe<C>& p, const float (&qld)[6][C], const float (&nld)[3][C]) {
 #pragma unroll
   for (int k = 0; k < C; ++k) {
-    if constexpr (TE) p.nprev[0][k] = p.ncur[0][k];
-    if constexpr (TM) p.nprev[1][k] = p.ncur[2][k];
+    if constexpr (O::TE) p.nprev[0][k] = p.ncur[0][k];
+    if constexpr (O::TM) p.nprev[1][k] = p.ncur[2][k];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       if (!O::nlive(c)) continue;
@@ -612,21 +659,20 @@ __device__ __forceinline__ void row_iteration(Pipe<C>& p, const StepArgs& g, con
       p.nnext[c][k] = p.nn2[c][k];
       p.nn2[c][k] = nld[c][k];
     }
+    if constexpr (FEED) {
 #pragma unroll
-    for (int c = 0; c < 6; ++c) {
-      if (!O::live(c)) continue;
-      p.q[c][k] = p.q1[c][k];
-      p.q1[c][k] = qld[c][k];
+      for (int c = 0; c < 6; ++c) {
+        if (!O::live(c)) continue;
+        p.q[c][k] = p.q1[c][k];
+        p.q1[c][k] = qld[c][k];
+      }
     }
   }
 }
 
-// One wave's march over its segment in direction DIR.
-template <int C, class O, int DIR>
-__device__ __forceinline__ void march(const StepArgs& g, const uint32_t (&xo)[C],
-                                      const uint32_t (&so)[C], bool edge_lane, int y0, int seg_h) {
-  constexpr bool VEC = O::VEC;
-  Pipe<C> p;
+// A pipeline before its first row: empty delay lines and rings, n = 1.
+template <int C>
+__device__ __forceinline__ void pipe_clear(Pipe<C>& p) {
 #pragma unroll
   for (int s = 0; s < 8; ++s)
 #pragma unroll
@@ -660,55 +706,137 @@ __device__ __forceinline__ void march(const StepArgs& g, const uint32_t (&xo)[C]
     for (int k = 0; k < C; ++k) p.ncur[c][k] = p.nnext[c][k] = p.nn2[c][k] = 1.0f;
 #pragma unroll
   for (int k = 0; k < C; ++k) p.nprev[0][k] = p.nprev[1][k] = 1.0f;
+}
 
+// The n window of a pipeline whose first ingested row is R0: rows R0-DIR
+// (n_x, n_z), R0, R0+DIR, R0+2*DIR.
+template <int C, class O, int DIR>
+__device__ __forceinline__ void prime_n(Pipe<C>& p, const StepArgs& g, const uint32_t (&xo)[C], int64_t R0) {
+  constexpr bool VEC = O::VEC;
+  const int64_t nx64 = g.nx;
+  const float* nm = g.n + wrap_index(R0 - DIR, g.ny) * nx64;
+  const float* n0 = g.n + wrap_index(R0, g.ny) * nx64;
+  const float* n1 = g.n + wrap_index(R0 + DIR, g.ny) * nx64;
+  const float* n2 = g.n + wrap_index(R0 + 2 * DIR, g.ny) * nx64;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    if (!O::nlive(c)) continue;
+    load_row<C, VEC>(n0 + c * g.plane, g.nx, xo, p.ncur[c]);
+    load_row<C, VEC>(n1 + c * g.plane, g.nx, xo, p.nnext[c]);
+    load_row<C, VEC>(n2 + c * g.plane, g.nx, xo, p.nn2[c]);
+  }
+  if (O::nlive(0)) load_row<C, VEC>(nm + 0 * g.plane, g.nx, xo, p.nprev[0]);
+  if (O::nlive(2)) load_row<C, VEC>(nm + 2 * g.plane, g.nx, xo, p.nprev[1]);
+}
+
+template <int DIR>
+__device__ __forceinline__ int next_row(int r, int ny) {
+  if constexpr (DIR > 0)
+    return (r + 1 == ny) ? 0 : r + 1;
+  else
+    return (r == 0) ? ny - 1 : r - 1;
+}
+
+// One wave's march over its segment in direction DIR: one step.
+template <int C, class O, int DIR>
+__device__ __forceinline__ void march(const StepArgs& g, const uint32_t (&xo)[C],
+                                      const uint32_t (&so)[C], bool edge_lane, int y0, int seg_h) {
+  constexpr bool VEC = O::VEC;
+  Pipe<C> p;
+  pipe_clear(p);
   // first ingested row: 4 rows before the segment in marching order
   const int64_t R0 = DIR > 0 ? static_cast<int64_t>(y0) - 4 : static_cast<int64_t>(y0) + seg_h + 3;
   const int64_t nx64 = g.nx;
   {
     const float* q0r = g.qin + wrap_index(R0, g.ny) * nx64;
     const float* q1r = g.qin + wrap_index(R0 + DIR, g.ny) * nx64;
-    const float* nm = g.n + wrap_index(R0 - DIR, g.ny) * nx64;
-    const float* n0 = g.n + wrap_index(R0, g.ny) * nx64;
-    const float* n1 = g.n + wrap_index(R0 + DIR, g.ny) * nx64;
-    const float* n2 = g.n + wrap_index(R0 + 2 * DIR, g.ny) * nx64;
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
       if (!O::live(c)) continue;
       load_row<C, VEC>(q0r + c * g.plane, g.nx, xo, p.q[c]);
       load_row<C, VEC>(q1r + c * g.plane, g.nx, xo, p.q1[c]);
     }
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      if (!O::nlive(c)) continue;
-      load_row<C, VEC>(n0 + c * g.plane, g.nx, xo, p.ncur[c]);
-      load_row<C, VEC>(n1 + c * g.plane, g.nx, xo, p.nnext[c]);
-      load_row<C, VEC>(n2 + c * g.plane, g.nx, xo, p.nn2[c]);
-    }
-    if (O::nlive(0)) load_row<C, VEC>(nm + 0 * g.plane, g.nx, xo, p.nprev[0]);
-    if (O::nlive(2)) load_row<C, VEC>(nm + 2 * g.plane, g.nx, xo, p.nprev[1]);
+    prime_n<C, O, DIR>(p, g, xo, R0);
   }
   // rows in flight: Q of R+2*DIR, n of R+3*DIR (wrapped incrementally)
   int rq = wrap_index(R0 + 2 * DIR, g.ny);
   int rn = wrap_index(R0 + 3 * DIR, g.ny);
   const int iters = ((seg_h + 8) + 3) & ~3;
+  float unused[6][C];
   for (int i = 0; i < iters; i += 4) {
 #define QLA_ITER(S)                                                                            \
   {                                                                                            \
-    const RowBases rb{g.qin + rq * nx64, g.n + rn * nx64};                                     \
-    row_iteration<C, O, DIR, S>(p, g, xo, so, edge_lane, i + S, seg_h, y0, rb);                \
-    if constexpr (DIR > 0) {                                                                   \
-      rq = (rq + 1 == g.ny) ? 0 : rq + 1;                                                      \
-      rn = (rn + 1 == g.ny) ? 0 : rn + 1;                                                      \
-    } else {                                                                                   \
-      rq = (rq == 0) ? g.ny - 1 : rq - 1;                                                      \
-      rn = (rn == 0) ? g.ny - 1 : rn - 1;                                                      \
-    }                                                                                          \
+    float qld[6][C], nld[3][C];                                                                \
+    load_q<C, O>(g, g.qin + rq * nx64, xo, qld);                                               \
+    load_n<C, O>(g, g.n + rn * nx64, xo, nld);                                                 \
+    process_row<C, O, DIR, S, false, 4>(p, g, so, edge_lane, i + S, seg_h, y0, unused);        \
+    advance<C, O, true>(p, qld, nld);                                                          \
+    rq = next_row<DIR>(rq, g.ny);                                                              \
+    rn = next_row<DIR>(rn, g.ny);                                                              \
   }
     QLA_ITER(0)
     QLA_ITER(1)
     QLA_ITER(2)
     QLA_ITER(3)
 #undef QLA_ITER
+  }
+}
+
+// Two steps in one march (temporal blocking). Stage A runs the step on rows
+// read from memory and hands each fully stepped row to stage B, which runs
+// the second step on it and stores the result: HBM sees one read of Q and n
+// and one write of Q per two steps. Stage A starts 8 rows before the
+// segment (the y support of two steps) and stage B trails it by 4 rows; a
+// stage-A row that lies outside the rows stage A can produce exactly (its
+// first 8 and last 8 iterations, and the outer 8 columns of the strip) only
+// ever reaches halo rows and columns of stage B, which are not stored.
+template <int C, class O, int DIR>
+__device__ __forceinline__ void march2(const StepArgs& g, const uint32_t (&xo)[C],
+                                       const uint32_t (&so)[C], bool edge_lane, int y0, int seg_h) {
+  constexpr bool VEC = O::VEC;
+  Pipe<C> pa, pb;
+  pipe_clear(pa);
+  pipe_clear(pb);
+  const int64_t RA = DIR > 0 ? static_cast<int64_t>(y0) - 8 : static_cast<int64_t>(y0) + seg_h + 7;
+  const int64_t RB = RA - 4 * DIR;
+  const int64_t nx64 = g.nx;
+  {
+    const float* q0r = g.qin + wrap_index(RA, g.ny) * nx64;
+    const float* q1r = g.qin + wrap_index(RA + DIR, g.ny) * nx64;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      if (!O::live(c)) continue;
+      load_row<C, VEC>(q0r + c * g.plane, g.nx, xo, pa.q[c]);
+      load_row<C, VEC>(q1r + c * g.plane, g.nx, xo, pa.q1[c]);
+    }
+    prime_n<C, O, DIR>(pa, g, xo, RA);
+    prime_n<C, O, DIR>(pb, g, xo, RB);
+  }
+  int rq = wrap_index(RA + 2 * DIR, g.ny);
+  int rna = wrap_index(RA + 3 * DIR, g.ny);
+  int rnb = wrap_index(RB + 3 * DIR, g.ny);
+  const int iters = ((seg_h + 16) + 3) & ~3;
+  float unused[6][C];
+  for (int i = 0; i < iters; i += 4) {
+#define QLA_ITER2(S)                                                                           \
+  {                                                                                            \
+    float qld[6][C], nla[3][C], nlb[3][C];                                                     \
+    load_q<C, O>(g, g.qin + rq * nx64, xo, qld);                                               \
+    load_n<C, O>(g, g.n + rna * nx64, xo, nla);                                                \
+    load_n<C, O>(g, g.n + rnb * nx64, xo, nlb);                                                \
+    process_row<C, O, DIR, S, true, 8>(pa, g, so, edge_lane, i + S, seg_h, y0, pb.q);          \
+    process_row<C, O, DIR, S, false, 12>(pb, g, so, edge_lane, i + S, seg_h, y0, unused);      \
+    advance<C, O, true>(pa, qld, nla);                                                         \
+    advance<C, O, false>(pb, qld, nlb);                                                        \
+    rq = next_row<DIR>(rq, g.ny);                                                              \
+    rna = next_row<DIR>(rna, g.ny);                                                            \
+    rnb = next_row<DIR>(rnb, g.ny);                                                            \
+  }
+    QLA_ITER2(0)
+    QLA_ITER2(1)
+    QLA_ITER2(2)
+    QLA_ITER2(3)
+#undef QLA_ITER2
   }
 }
 
@@ -733,8 +861,10 @@ struct BatchArgs {
   int waves_per_block;
 };
 
-template <int C, class O>
+// STEPS time steps per launch (1, or 2 with temporal blocking).
+template <int C, class O, int STEPS>
 __global__ void __launch_bounds__(256) qla_step_kernel(BatchArgs ba) {
+  using Cl = Cols<C, STEPS>;
   const int lane = threadIdx.x & (kWave - 1);
   // wave index within the block, as a wave-uniform (scalar) value
   const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x / kWave));
@@ -772,12 +902,12 @@ __global__ void __launch_bounds__(256) qla_step_kernel(BatchArgs ba) {
 
   const int y0 = seg * d.seg_rows;
   const int seg_h = min(d.seg_rows, g.ny - y0);
-  const int x0 = strip * Cols<C>::kOut;
-  const int64_t col0 = static_cast<int64_t>(x0) - Cols<C>::kHaloLanes * C + lane * C;
+  const int x0 = strip * Cl::kOut;
+  const int64_t col0 = static_cast<int64_t>(x0) - Cl::kHaloLanes * C + lane * C;
   // byte offsets of the lane's columns within a row: loads wrap
   // periodically, stores only for output columns of this strip
   uint32_t xo[C], so[C];
-  const bool lane_in = lane >= Cols<C>::kHaloLanes && lane < kWave - Cols<C>::kHaloLanes;
+  const bool lane_in = lane >= Cl::kHaloLanes && lane < kWave - Cl::kHaloLanes;
   const bool edge_lane = lane == 0 || lane == kWave - 1;
 #pragma unroll
   for (int k = 0; k < C; ++k) {
@@ -793,27 +923,38 @@ __global__ void __launch_bounds__(256) qla_step_kernel(BatchArgs ba) {
   // rows two segments share are read by both at about the same time (at
   // the start of both marches or at the end of both) and come from L2 for
   // the second reader.
-  if (seg & 1)
-    march<C, O, +1>(g, xo, so, edge_lane, y0, seg_h);
-  else
-    march<C, O, -1>(g, xo, so, edge_lane, y0, seg_h);
+  if constexpr (STEPS == 2) {
+    if (seg & 1)
+      march2<C, O, +1>(g, xo, so, edge_lane, y0, seg_h);
+    else
+      march2<C, O, -1>(g, xo, so, edge_lane, y0, seg_h);
+  } else {
+    if (seg & 1)
+      march<C, O, +1>(g, xo, so, edge_lane, y0, seg_h);
+    else
+      march<C, O, -1>(g, xo, so, edge_lane, y0, seg_h);
+  }
 }
 
-// One compiled instance of the step kernel.
+// One compiled set of options of the step kernel: its one-step and
+// two-step launches.
 struct StepImpl {
-  const void* func;                                   // the __global__ function
-  hipError_t (*blocks_per_cu)(int* nb, int threads);  // occupancy query
+  const void* func[2];                                   // __global__ function, 1 and 2 steps
+  hipError_t (*blocks_per_cu[2])(int* nb, int threads);  // occupancy queries
   int cols;
 };
 
-template <int C, class O>
+template <int C, class O, int STEPS>
 hipError_t step_blocks_per_cu(int* nb, int threads) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, qla_step_kernel<C, O>, threads, 0);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, qla_step_kernel<C, O, STEPS>, threads, 0);
 }
 
 template <int C, class O>
 StepImpl impl() {
-  return StepImpl{reinterpret_cast<const void*>(&qla_step_kernel<C, O>), step_blocks_per_cu<C, O>, C};
+  return StepImpl{{reinterpret_cast<const void*>(&qla_step_kernel<C, O, 1>),
+                   reinterpret_cast<const void*>(&qla_step_kernel<C, O, 2>)},
+                  {step_blocks_per_cu<C, O, 1>, step_blocks_per_cu<C, O, 2>},
+                  C};
 }
 
 // Options every instance is selected by at run time.

@@ -49,7 +49,7 @@ class Diag(ctypes.Structure):
 
 class Launch(ctypes.Structure):
     _fields_ = [("seg_rows", ctypes.c_int32), ("waves_per_block", ctypes.c_int32),
-                ("graph_steps", ctypes.c_int32)]
+                ("graph_steps", ctypes.c_int32), ("steps_per_pass", ctypes.c_int32)]
 
     def as_dict(self) -> Dict[str, int]:
         return {name: int(getattr(self, name)) for name, _ in self._fields_}
@@ -189,8 +189,9 @@ def qla_get_launch(ctx) -> Dict[str, int]:
     return out.as_dict()
 
 
-def qla_set_launch(ctx, seg_rows: int = 0, waves_per_block: int = 0, graph_steps: int = 0) -> None:
-    req = Launch(int(seg_rows), int(waves_per_block), int(graph_steps))
+def qla_set_launch(ctx, seg_rows: int = 0, waves_per_block: int = 0, graph_steps: int = 0,
+                   steps_per_pass: int = 0) -> None:
+    req = Launch(int(seg_rows), int(waves_per_block), int(graph_steps), int(steps_per_pass))
     _check(lib().qla_set_launch(ctx, ctypes.byref(req)))
 
 
@@ -253,8 +254,9 @@ class Simulation:
     def launch(self) -> Dict[str, int]:
         return qla_get_launch(self.ctx)
 
-    def set_launch(self, seg_rows: int = 0, waves_per_block: int = 0, graph_steps: int = 0) -> None:
-        qla_set_launch(self.ctx, seg_rows, waves_per_block, graph_steps)
+    def set_launch(self, seg_rows: int = 0, waves_per_block: int = 0, graph_steps: int = 0,
+                   steps_per_pass: int = 0) -> None:
+        qla_set_launch(self.ctx, seg_rows, waves_per_block, graph_steps, steps_per_pass)
 
     def state_tensor(self):
         """The device tensor that holds the current state (no copy)."""
@@ -334,8 +336,9 @@ class Batch:
     def launch(self) -> Dict[str, int]:
         return qla_get_launch(self.ctx)
 
-    def set_launch(self, seg_rows: int = 0, waves_per_block: int = 0, graph_steps: int = 0) -> None:
-        qla_set_launch(self.ctx, seg_rows, waves_per_block, graph_steps)
+    def set_launch(self, seg_rows: int = 0, waves_per_block: int = 0, graph_steps: int = 0,
+                   steps_per_pass: int = 0) -> None:
+        qla_set_launch(self.ctx, seg_rows, waves_per_block, graph_steps, steps_per_pass)
 
     def close(self) -> None:
         if self.ctx is not None:

@@ -281,12 +281,11 @@ struct qla_ctx {
   qla_launch launch;       // requested geometry (0 fields: default)
   qla_launch planned;      // geometry in use
   StepImpl step;
-  dim3 block;
   // per steps-per-launch (index 0: one step, 1: two steps)
   struct Geometry {
     std::vector<InstDesc> desc;
     InstDesc* d_desc;
-    dim3 grid;
+    dim3 grid, block;
     int seg_rows;
     hipGraphExec_t graph[2];   // graph_steps steps starting from buffer 0 / 1
   } geo[2];
@@ -379,6 +378,9 @@ void drop_graphs(qla_ctx* c) {
 // per step).
 qla_status plan_geometry(qla_ctx* c, int steps, int wpb) {
   auto& geo = c->geo[steps - 1];
+  // a two-step block is one producer/consumer pair of waves
+  if (steps == 2) wpb = 1;
+  const int threads = steps == 2 ? 2 * kWave : kWave * wpb;
   const int oc = out_cols(steps);
   int max_ny = 1;
   for (const auto& p : c->p) max_ny = std::max(max_ny, p.ny);
@@ -395,7 +397,7 @@ qla_status plan_geometry(qla_ctx* c, int steps, int wpb) {
   int S = c->launch.seg_rows;
   if (S <= 0) {
     int bpc = 0;
-    hipError_t e = c->step.blocks_per_cu[steps - 1](&bpc, kWave * wpb);
+    hipError_t e = c->step.blocks_per_cu[steps - 1](&bpc, threads);
     if (e != hipSuccess || bpc < 1) bpc = 1;
     const int64_t slots = static_cast<int64_t>(c->cus) * bpc;
     const int top = (max_ny + 3) & ~3;
@@ -434,6 +436,7 @@ qla_status plan_geometry(qla_ctx* c, int steps, int wpb) {
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "uploading the lattice descriptors");
   geo.grid = dim3(static_cast<unsigned>(total));
+  geo.block = dim3(threads);
   geo.seg_rows = S;
   return QLA_OK;
 }
@@ -467,20 +470,21 @@ qla_status plan_step(qla_ctx* c) {
     qla_status st = plan_geometry(c, steps, wpb);
     if (st != QLA_OK) return st;
   }
-  c->block = dim3(kWave * wpb);
   c->planned = qla_launch{c->geo[spp - 1].seg_rows, wpb, gsteps, spp};
   return QLA_OK;
 }
 
 BatchArgs batch_args(const qla_ctx* c, int steps, int parity) {
-  return BatchArgs{c->geo[steps - 1].d_desc, c->count, parity, static_cast<int>(c->block.x / kWave)};
+  const auto& geo = c->geo[steps - 1];
+  return BatchArgs{geo.d_desc, c->count, parity, steps == 2 ? 1 : static_cast<int>(geo.block.x / kWave)};
 }
 
 // One launch advancing `steps` (1 or 2) time steps from buffer `parity`.
 hipError_t launch_one(qla_ctx* c, int steps, int parity) {
   BatchArgs a = batch_args(c, steps, parity);
   void* args[] = {&a};
-  return hipLaunchKernel(c->step.func[steps - 1], c->geo[steps - 1].grid, c->block, args, 0, c->stream);
+  return hipLaunchKernel(c->step.func[steps - 1], c->geo[steps - 1].grid, c->geo[steps - 1].block, args, 0,
+                         c->stream);
 }
 
 // A graph of graph_steps consecutive steps (launches of steps_per_pass
@@ -501,7 +505,7 @@ hipError_t build_graph(qla_ctx* c, int parity) {
     hipKernelNodeParams np{};
     np.func = const_cast<void*>(c->step.func[spp - 1]);
     np.gridDim = geo.grid;
-    np.blockDim = c->block;
+    np.blockDim = geo.block;
     np.sharedMemBytes = 0;
     np.kernelParams = kp;
     np.extra = nullptr;

@@ -2,8 +2,8 @@
 // shared by the translation units that instantiate it. See qla.hip for the
 // host side and the C ABI.
 //
-// One time step is one launch of qla_step_kernel, which applies, for every
-// site of every lattice in a batch, the whole operator sequence of Eq. (23)
+// One launch of qla_step_kernel applies one or two whole time steps: for
+// every site of every lattice in a batch, the operator sequence of Eq. (23)
 // or Eq. (28): U_X (Eq. (18), 16 factors), U_Y (Eq. (20), 16 factors) and the
 // potentials V_X, V_Y (Eq. (21), (22)), with the collision angles of
 // Eq. (24) and the potential angles of Eq. (25) computed on the fly from n.
@@ -14,8 +14,8 @@
 //    per iteration;
 //  * the x sweep of the ingested row runs in registers: a streaming shift
 //    along x is a register rename for C-1 of the lane's columns and one DPP
-//    whole-wave shift for the last; the outermost ceil(4/C) lanes on each
-//    side are halo (one step's x support is +-4 cells) and store nothing;
+//    whole-wave shift for the last; the outermost lanes on each side are
+//    halo (one step's x support is +-4 cells) and store nothing;
 //  * the y sweep is a 16-stage register pipeline: a stage that pulls from
 //    the row behind in marching order reads a one-row delay register, a
 //    stage that pulls from the row ahead delays the other two active
@@ -23,7 +23,10 @@
 //    rows behind the one it ingests;
 //  * the loop is unrolled four times so that every ring of per-row data
 //    (collision coefficients, potential coefficients) is indexed by
-//    compile-time slots and stays in registers.
+//    compile-time slots and stays in registers;
+//  * a two-step launch pairs two waves on one segment: the first runs the
+//    step on rows from memory and passes each finished row through LDS to
+//    the second, which steps it again and stores it (temporal blocking).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -782,61 +785,93 @@ __device__ __forceinline__ void march(const StepArgs& g, const uint32_t (&xo)[C]
   }
 }
 
-// Two steps in one march (temporal blocking). Stage A runs the step on rows
-// read from memory and hands each fully stepped row to stage B, which runs
-// the second step on it and stores the result: HBM sees one read of Q and n
-// and one write of Q per two steps. Stage A starts 8 rows before the
-// segment (the y support of two steps) and stage B trails it by 4 rows; a
-// stage-A row that lies outside the rows stage A can produce exactly (its
-// first 8 and last 8 iterations, and the outer 8 columns of the strip) only
-// ever reaches halo rows and columns of stage B, which are not stored.
+// Two steps per launch (temporal blocking) on a pair of waves. The
+// producer wave runs the step on rows read from memory and hands each fully
+// stepped row, through a two-slot LDS ring, to the consumer wave, which
+// runs the second step on it and stores the result: HBM sees one read of Q
+// and n and one write of Q per two steps, and each wave holds one pipeline
+// (so two pairs fit on a SIMD). The producer starts 8 rows before the
+// segment (the y support of two steps); the consumer ingests the rows the
+// producer emits, 4 rows behind and one iteration later. Rows the producer
+// cannot produce exactly (its first 8 and last 8 iterations, and the outer
+// 8 columns of the strip) only ever reach halo rows and columns of the
+// consumer, which are not stored.
+template <int C>
+using Ring = float[2][6][kWave * C];
+
 template <int C, class O, int DIR>
 __device__ __forceinline__ void march2(const StepArgs& g, const uint32_t (&xo)[C],
-                                       const uint32_t (&so)[C], bool edge_lane, int y0, int seg_h) {
+                                       const uint32_t (&so)[C], bool edge_lane, int y0, int seg_h,
+                                       bool producer, int lane, Ring<C>& ring) {
   constexpr bool VEC = O::VEC;
-  Pipe<C> pa, pb;
-  pipe_clear(pa);
-  pipe_clear(pb);
+  Pipe<C> p;
+  pipe_clear(p);
   const int64_t RA = DIR > 0 ? static_cast<int64_t>(y0) - 8 : static_cast<int64_t>(y0) + seg_h + 7;
   const int64_t RB = RA - 4 * DIR;
   const int64_t nx64 = g.nx;
-  {
-    const float* q0r = g.qin + wrap_index(RA, g.ny) * nx64;
-    const float* q1r = g.qin + wrap_index(RA + DIR, g.ny) * nx64;
-#pragma unroll
-    for (int c = 0; c < 6; ++c) {
-      if (!O::live(c)) continue;
-      load_row<C, VEC>(q0r + c * g.plane, g.nx, xo, pa.q[c]);
-      load_row<C, VEC>(q1r + c * g.plane, g.nx, xo, pa.q1[c]);
-    }
-    prime_n<C, O, DIR>(pa, g, xo, RA);
-    prime_n<C, O, DIR>(pb, g, xo, RB);
-  }
-  int rq = wrap_index(RA + 2 * DIR, g.ny);
-  int rna = wrap_index(RA + 3 * DIR, g.ny);
-  int rnb = wrap_index(RB + 3 * DIR, g.ny);
   const int iters = ((seg_h + 16) + 3) & ~3;
   float unused[6][C];
-  for (int i = 0; i < iters; i += 4) {
-#define QLA_ITER2(S)                                                                           \
+  if (producer) {
+    {
+      const float* q0r = g.qin + wrap_index(RA, g.ny) * nx64;
+      const float* q1r = g.qin + wrap_index(RA + DIR, g.ny) * nx64;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        if (!O::live(c)) continue;
+        load_row<C, VEC>(q0r + c * g.plane, g.nx, xo, p.q[c]);
+        load_row<C, VEC>(q1r + c * g.plane, g.nx, xo, p.q1[c]);
+      }
+      prime_n<C, O, DIR>(p, g, xo, RA);
+    }
+    int rq = wrap_index(RA + 2 * DIR, g.ny);
+    int rn = wrap_index(RA + 3 * DIR, g.ny);
+    for (int i = 0; i < iters; i += 4) {
+#define QLA_ITER_A(S)                                                                          \
   {                                                                                            \
-    float qld[6][C], nla[3][C], nlb[3][C];                                                     \
+    float qld[6][C], nld[3][C], e[6][C];                                                       \
     load_q<C, O>(g, g.qin + rq * nx64, xo, qld);                                               \
-    load_n<C, O>(g, g.n + rna * nx64, xo, nla);                                                \
-    load_n<C, O>(g, g.n + rnb * nx64, xo, nlb);                                                \
-    process_row<C, O, DIR, S, true, 8>(pa, g, so, edge_lane, i + S, seg_h, y0, pb.q);          \
-    process_row<C, O, DIR, S, false, 12>(pb, g, so, edge_lane, i + S, seg_h, y0, unused);      \
-    advance<C, O, true>(pa, qld, nla);                                                         \
-    advance<C, O, false>(pb, qld, nlb);                                                        \
+    load_n<C, O>(g, g.n + rn * nx64, xo, nld);                                                 \
+    process_row<C, O, DIR, S, true, 8>(p, g, so, edge_lane, i + S, seg_h, y0, e);              \
+    _Pragma("unroll") for (int c = 0; c < 6; ++c) {                                            \
+      if (!O::live(c)) continue;                                                               \
+      _Pragma("unroll") for (int k = 0; k < C; ++k) ring[(S) & 1][c][lane * C + k] = e[c][k];  \
+    }                                                                                          \
+    advance<C, O, true>(p, qld, nld);                                                          \
     rq = next_row<DIR>(rq, g.ny);                                                              \
-    rna = next_row<DIR>(rna, g.ny);                                                            \
-    rnb = next_row<DIR>(rnb, g.ny);                                                            \
+    rn = next_row<DIR>(rn, g.ny);                                                              \
+    __syncthreads();                                                                           \
   }
-    QLA_ITER2(0)
-    QLA_ITER2(1)
-    QLA_ITER2(2)
-    QLA_ITER2(3)
-#undef QLA_ITER2
+      QLA_ITER_A(0)
+      QLA_ITER_A(1)
+      QLA_ITER_A(2)
+      QLA_ITER_A(3)
+#undef QLA_ITER_A
+    }
+    __syncthreads();     // the consumer's last row
+  } else {
+    prime_n<C, O, DIR>(p, g, xo, RB);
+    int rn = wrap_index(RB + 3 * DIR, g.ny);
+    __syncthreads();     // the producer's first row
+    for (int i = 0; i < iters; i += 4) {
+#define QLA_ITER_B(S)                                                                          \
+  {                                                                                            \
+    float nld[3][C];                                                                           \
+    load_n<C, O>(g, g.n + rn * nx64, xo, nld);                                                 \
+    _Pragma("unroll") for (int c = 0; c < 6; ++c) {                                            \
+      if (!O::live(c)) continue;                                                               \
+      _Pragma("unroll") for (int k = 0; k < C; ++k) p.q[c][k] = ring[(S) & 1][c][lane * C + k]; \
+    }                                                                                          \
+    process_row<C, O, DIR, S, false, 12>(p, g, so, edge_lane, i + S, seg_h, y0, unused);       \
+    advance<C, O, false>(p, unused, nld);                                                      \
+    rn = next_row<DIR>(rn, g.ny);                                                              \
+    __syncthreads();                                                                           \
+  }
+      QLA_ITER_B(0)
+      QLA_ITER_B(1)
+      QLA_ITER_B(2)
+      QLA_ITER_B(3)
+#undef QLA_ITER_B
+    }
   }
 }
 
@@ -887,7 +922,8 @@ __global__ void __launch_bounds__(256) qla_step_kernel(BatchArgs ba) {
   const InstDesc& d = ba.desc[lo];
   const int local = logical - d.first_block;
   const int strip = local % d.nstrips;
-  const int seg = (local / d.nstrips) * ba.waves_per_block + wave;
+  // a two-step block is one producer/consumer pair of waves on one segment
+  const int seg = STEPS == 2 ? local / d.nstrips : (local / d.nstrips) * ba.waves_per_block + wave;
   if (seg >= d.nsegs) return;
 
   StepArgs g;
@@ -924,10 +960,12 @@ __global__ void __launch_bounds__(256) qla_step_kernel(BatchArgs ba) {
   // the start of both marches or at the end of both) and come from L2 for
   // the second reader.
   if constexpr (STEPS == 2) {
+    __shared__ Ring<C> ring;
+    const bool producer = wave == 0;
     if (seg & 1)
-      march2<C, O, +1>(g, xo, so, edge_lane, y0, seg_h);
+      march2<C, O, +1>(g, xo, so, edge_lane, y0, seg_h, producer, lane, ring);
     else
-      march2<C, O, -1>(g, xo, so, edge_lane, y0, seg_h);
+      march2<C, O, -1>(g, xo, so, edge_lane, y0, seg_h, producer, lane, ring);
   } else {
     if (seg & 1)
       march<C, O, +1>(g, xo, so, edge_lane, y0, seg_h);

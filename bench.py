@@ -200,13 +200,109 @@ def time_polarised(make_sim, stream, sites: int, steps: int, warmup: int, traffi
                          "steps_per_launch": spp, "algo_bytes_per_site": TM_BYTES_PER_SITE}}
 
 
+def sweep_workload(args) -> dict:
+    """Surrogate-accelerated sweep against plain QLA on the same GPU.
+
+    Trains the U-net surrogate on QLA runs the library generates (1024 runs
+    at 256 x 256, snapshots every K = 256 steps), judges it on 128 held-out
+    runs, then advances --sweep-lattices lattices of 1024 x 1024 (the
+    batched scene family) by --steps steps three ways: plain QLA; the sweep
+    with QLA checks at the first and every 4th jump and fallback at a 1e-3
+    relative field or energy error; and surrogate jumps with no checks.
+    value = plain QLA seconds / checked-sweep seconds, at the final field
+    error the record states (max over lattices of |Q - Q_plain| / |Q_plain|)."""
+    import torch
+    from paper_2301_13601_amd import scenes, surrogate as S
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    K = 256
+    t0 = time.perf_counter()
+    data = S.generate(1024, seed=11, L=256, K=K, snaps=9)
+    held = S.generate(128, seed=999, L=256, K=K, snaps=9)
+    gen_s = time.perf_counter() - t0
+    net = S.UNet(seed=0)
+    t0 = time.perf_counter()
+    S.train(net, data, steps=args.train_steps, batch=16, lr=1e-3, seed=1, log_every=0)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    err = S.evaluate(net, held)
+    del data, held
+
+    L = 1024
+    specs = scenes.batch_instance_specs(args.sweep_lattices, seed=5, sides=(L,))
+    scs = [scenes.scene_from_spec(sp, steps=args.steps) for sp in specs]
+    ns = [s.n.astype(np.float32) for s in scs]
+    qs = [s.q.astype(np.float32) for s in scs]
+    delta = scs[0].delta
+    steps = args.steps
+
+    # forward throughput of the network on these lattices
+    B = len(ns)
+    cur = torch.as_tensor(np.stack(qs)).to(dev)
+    n_dev = torch.as_tensor(np.stack(ns)).to(dev)
+    out = torch.empty_like(cur)
+    net.predict(cur, n_dev, out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(net.stream)
+    net.predict(cur, n_dev, out)
+    e1.record(net.stream)
+    torch.cuda.synchronize()
+    fwd_s = e0.elapsed_time(e1) / 1e3
+    flops = 2.0 * S.macs_per_pixel() * B * L * L
+    del cur, out
+
+    plain_s, plain = S.plain(ns, qs, delta, steps, stream=net.stream)
+
+    def field_err(finals):
+        return max(float(np.linalg.norm(a.astype(np.float64) - b) / np.linalg.norm(b.astype(np.float64)))
+                   for a, b in zip(finals, plain))
+
+    chk, chk_f = S.sweep(net, ns, qs, delta, steps, K=K, check_every=4, tol=1e-3)
+    free, free_f = S.sweep(net, ns, qs, delta, steps, K=K, check_every=0)
+    return {
+        "metric": "surrogate vs plain QLA speedup at stated field error",
+        "value": plain_s / chk.seconds,
+        "unit": "x",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": 0,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 QLA, bf16 x bf16 -> f32 network",
+        "data": "synthetic",
+        "stated_error": field_err(chk_f),
+        "config": {"workload": f"sweep: {B} lattices of {L}x{L} (batched scene family, seed 5), "
+                               f"{steps} steps, surrogate jumps of K={K}, checks at the first and every "
+                               "4th jump, fallback at 1e-3 field or energy error",
+                   "fallback_tolerance": 1e-3},
+        "checked_sweep": {"seconds": chk.seconds, "jumps": chk.jumps, "unchecked": chk.unchecked,
+                          "checks": chk.checks, "rejected": chk.rejected, "fell_back": chk.fell_back,
+                          "max_check_error": chk.max_check_error, "max_check_energy": chk.max_check_energy},
+        "unchecked_sweep": {"seconds": free.seconds, "speedup": plain_s / free.seconds,
+                            "jumps": free.jumps, "final_field_error": field_err(free_f)},
+        "plain_qla": {"seconds": plain_s, "site_updates_per_s": B * L * L * steps / plain_s},
+        "network": {"train_runs": 1024, "train_steps": args.train_steps, "train_seconds": train_s,
+                    "data_seconds": gen_s, "heldout_median_error": float(np.median(err)),
+                    "heldout_p90_error": float(np.percentile(err, 90)),
+                    "macs_per_pixel": S.macs_per_pixel(),
+                    "forward_seconds_per_pixel": fwd_s / (B * L * L),
+                    "forward_tflops": flops / fwd_s / 1e12,
+                    "qla_seconds_per_site_for_K_steps": plain_s / steps * K / (B * L * L)},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="cylinder_4096",
-                    choices=["cylinder_4096", "single_256", "batch_64"])
+                    choices=["cylinder_4096", "single_256", "batch_64", "sweep"])
+    ap.add_argument("--train-steps", type=int, default=3000, help="sweep workload: network training steps")
+    ap.add_argument("--sweep-lattices", type=int, default=16, help="sweep workload: lattices of 1024 x 1024")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=6)
     ap.add_argument("--cpu-sample-n", type=int, default=4096)
@@ -230,6 +326,10 @@ def main():
 
     import torch
     from paper_2301_13601_amd import qla
+
+    if args.workload == "sweep":
+        print(json.dumps(sweep_workload(args)), flush=True)
+        return
 
     sc, desc = make_workload(args.workload, args.steps)
     batch = isinstance(sc, list)

@@ -426,13 +426,14 @@ def sweep(net: UNet, n_list: Sequence, q_list: Sequence, delta: float, total_ste
     """Advance lattices (all the same size, sides multiples of 16) by
     ``total_steps`` QLA steps, replacing runs of K steps by surrogate jumps.
 
-    Every ``check_every``-th jump is also run by plain QLA from the saved
-    pre-jump state: the QLA result is kept, and if the surrogate's relative
-    field error or relative energy error against it exceeds ``tol`` on any
-    lattice the check counts as rejected; after ``max_rejects`` rejections
-    the sweep falls back to plain QLA for the rest of the run. Other jumps
-    take the surrogate's prediction. ``window`` plain QLA steps follow each
-    jump. Returns the result record and the final states."""
+    The first jump and then every ``check_every``-th jump is also run by
+    plain QLA from the saved pre-jump state: the QLA result is kept, and if
+    the surrogate's relative field error or relative energy error against it
+    exceeds ``tol`` on any lattice the check counts as rejected; after
+    ``max_rejects`` rejections the sweep falls back to plain QLA for the
+    rest of the run. Other jumps take the surrogate's prediction
+    (``check_every`` <= 0: no checks at all). ``window`` plain QLA steps
+    follow each jump. Returns the result record and the final states."""
     import torch
 
     dev = torch.device(device)
@@ -465,7 +466,7 @@ def sweep(net: UNet, n_list: Sequence, q_list: Sequence, delta: float, total_ste
         export(cur)
         net.predict(cur, n_dev, pred)
         jumps += 1
-        if jumps % check_every == 0:
+        if check_every > 0 and (jumps == 1 or jumps % check_every == 0):
             checks += 1
             batch.step(K)                        # QLA from the saved pre-jump state
             export(ref)

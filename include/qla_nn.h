@@ -144,11 +144,16 @@ int qnn_rel_l2(int32_t B, int32_t H, int32_t W, const float *pred, int32_t pred_
 int qnn_adam(int64_t n, float *p, float *m, float *v, const float *g, uint16_t *p_bf16, float lr,
              float b1, float b2, float eps, int32_t t, void *hip_stream);
 
+/* FP64 values of device workspace qnn_compare needs for B samples. */
+int64_t qnn_compare_work_doubles(int32_t B);
+
 /* Per-sample comparison of B FP32 tensors of m values each (sample b at
  * offset b*m): rel[b] = |a_b - r_b| / |r_b| and en[b] = | |a_b|^2 - |r_b|^2 |
- * / |r_b|^2, accumulated in FP64. rel, en: FP64 device arrays of B. */
+ * / |r_b|^2, accumulated in FP64. rel, en: FP64 device arrays of B; work:
+ * caller-owned FP64 device scratch of qnn_compare_work_doubles(B) values.
+ * B at most 65535. */
 int qnn_compare(int32_t B, int64_t m, const float *a, const float *r, double *rel, double *en,
-                void *hip_stream);
+                double *work, void *hip_stream);
 
 /* y = bf16(x) for n FP32 values (round to nearest even). */
 int qnn_to_bf16(int64_t n, const float *x, uint16_t *y, void *hip_stream);

@@ -10,6 +10,7 @@
 // rows 8*(r / 4) + 4*(l / 32) + r % 4 for r = 0..15.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdint>
@@ -314,21 +315,37 @@ __global__ void upsample2_bwd_kernel(int B, int h, int w, int C, const uint16_t*
   }
 }
 
-__global__ void absmax_kernel(int H, int W, const float* __restrict__ q, const int32_t* __restrict__ idx,
-                              float* __restrict__ scale) {
-  const int b = blockIdx.x;
+// Per-sample max |q|: a 2D grid of blocks per sample, each folding its
+// share with an unsigned atomic max on the float's bits (|q| >= 0, whose bit
+// patterns order like the values); absmax_init clears, absmax_fix turns 0
+// into 1.
+__global__ void absmax_init_kernel(int B, float* __restrict__ scale) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < B) scale[b] = 0.0f;
+}
+
+__global__ void __launch_bounds__(256) absmax_kernel(int H, int W, const float* __restrict__ q,
+                                                     const int32_t* __restrict__ idx, float* __restrict__ scale) {
+  const int b = blockIdx.y;
   const int64_t n = 6 * static_cast<int64_t>(H) * W;
   const float* qs = q + (idx ? idx[b] : b) * n;
   float m = 0.0f;
-  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) m = fmaxf(m, fabsf(qs[i]));
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    m = fmaxf(m, fabsf(qs[i]));
   for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
   __shared__ float sh[4];
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
   __syncthreads();
   if (threadIdx.x == 0) {
     m = fmaxf(fmaxf(sh[0], sh[1]), fmaxf(sh[2], sh[3]));
-    scale[b] = m > 0.0f ? m : 1.0f;
+    atomicMax(reinterpret_cast<unsigned int*>(scale + b), __float_as_uint(m));
   }
+}
+
+__global__ void absmax_fix_kernel(int B, float* __restrict__ scale) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < B && !(scale[b] > 0.0f)) scale[b] = 1.0f;
 }
 
 constexpr int kInCh = 48;
@@ -370,15 +387,18 @@ __global__ void pack_input_kernel(int B, int H, int W, const float* __restrict__
   }
 }
 
+// one thread per pixel: the pixel's 6 output channels are adjacent in y
 __global__ void unpack_output_kernel(int B, int H, int W, const float* __restrict__ y, int y_ld,
                                      const float* __restrict__ scale, float* __restrict__ q) {
   const int64_t HW = static_cast<int64_t>(H) * W;
-  const int64_t total = B * 6 * HW;
-  QNN_GRID_STRIDE(i, total) {
-    const int64_t s = i % HW;
-    const int c = static_cast<int>((i / HW) % 6);
-    const int b = static_cast<int>(i / (6 * HW));
-    q[i] = y[(b * HW + s) * y_ld + c] * scale[b];
+  const int64_t total = B * HW;
+  QNN_GRID_STRIDE(p, total) {
+    const int b = static_cast<int>(p / HW);
+    const int64_t s = p - b * HW;
+    const float* yp = y + p * y_ld;
+    const float sc = scale[b];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) q[(b * 6 + c) * HW + s] = yp[c] * sc;
   }
 }
 
@@ -484,13 +504,18 @@ __global__ void adam_kernel(int64_t n, float* __restrict__ p, float* __restrict_
   }
 }
 
+// per-sample comparison: kCompareBlocks partial blocks per sample write
+// (sum d^2, sum a^2, sum r^2) to work; compare_final folds them
+constexpr int kCompareBlocks = 64;
+
 __global__ void __launch_bounds__(256) compare_kernel(int64_t m, const float* __restrict__ a, const float* __restrict__ r,
-                                                      double* __restrict__ rel, double* __restrict__ en) {
-  const int b = blockIdx.x;
+                                                      double* __restrict__ work) {
+  const int b = blockIdx.y;
   const float* ab = a + b * m;
   const float* rb = r + b * m;
   double dd = 0.0, aa = 0.0, rr = 0.0;
-  for (int64_t i = threadIdx.x; i < m; i += blockDim.x) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < m;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
     const double x = ab[i], y = rb[i];
     dd += (x - y) * (x - y);
     aa += x * x;
@@ -510,12 +535,26 @@ __global__ void __launch_bounds__(256) compare_kernel(int64_t m, const float* __
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    dd = sh[0][0] + sh[0][1] + sh[0][2] + sh[0][3];
-    aa = sh[1][0] + sh[1][1] + sh[1][2] + sh[1][3];
-    rr = sh[2][0] + sh[2][1] + sh[2][2] + sh[2][3];
-    rel[b] = rr > 0.0 ? sqrt(dd / rr) : sqrt(dd);
-    en[b] = rr > 0.0 ? fabs(aa - rr) / rr : aa;
+    double* w = work + (static_cast<int64_t>(b) * kCompareBlocks + blockIdx.x) * 3;
+    w[0] = sh[0][0] + sh[0][1] + sh[0][2] + sh[0][3];
+    w[1] = sh[1][0] + sh[1][1] + sh[1][2] + sh[1][3];
+    w[2] = sh[2][0] + sh[2][1] + sh[2][2] + sh[2][3];
   }
+}
+
+__global__ void compare_final_kernel(int B, const double* __restrict__ work, double* __restrict__ rel,
+                                     double* __restrict__ en) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  double dd = 0.0, aa = 0.0, rr = 0.0;
+  for (int k = 0; k < kCompareBlocks; ++k) {
+    const double* w = work + (static_cast<int64_t>(b) * kCompareBlocks + k) * 3;
+    dd += w[0];
+    aa += w[1];
+    rr += w[2];
+  }
+  rel[b] = rr > 0.0 ? sqrt(dd / rr) : sqrt(dd);
+  en[b] = rr > 0.0 ? fabs(aa - rr) / rr : aa;
 }
 
 __global__ void to_bf16_kernel(int64_t n, const float* __restrict__ x, uint16_t* __restrict__ y) {
@@ -650,7 +689,12 @@ int qnn_upsample2_bwd(int32_t B, int32_t h, int32_t w, int32_t C, const uint16_t
 
 int qnn_absmax(int32_t B, int32_t H, int32_t W, const float* q, const int32_t* idx, float* scale, void* hip_stream) {
   if (B < 1 || H < 1 || W < 1 || !q || !scale) return bad("absmax: bad argument");
-  hipLaunchKernelGGL(absmax_kernel, dim3(B), dim3(256), 0, static_cast<hipStream_t>(hip_stream), H, W, q, idx, scale);
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const int64_t n = 6 * static_cast<int64_t>(H) * W;
+  const int nb = static_cast<int>(std::min<int64_t>((n + 255) / 256, 256));
+  hipLaunchKernelGGL(absmax_init_kernel, dim3((B + 255) / 256), dim3(256), 0, st, B, scale);
+  hipLaunchKernelGGL(absmax_kernel, dim3(nb, B), dim3(256), 0, st, H, W, q, idx, scale);
+  hipLaunchKernelGGL(absmax_fix_kernel, dim3((B + 255) / 256), dim3(256), 0, st, B, scale);
   return launched("absmax");
 }
 
@@ -666,7 +710,7 @@ int qnn_pack_input(int32_t B, int32_t H, int32_t W, const float* q, const int32_
 int qnn_unpack_output(int32_t B, int32_t H, int32_t W, const float* y, int32_t y_ld, const float* scale, float* q,
                       void* hip_stream) {
   if (B < 1 || H < 1 || W < 1 || !y || !scale || !q || y_ld < 6) return bad("unpack_output: bad argument");
-  const int64_t total = static_cast<int64_t>(B) * 6 * H * W;
+  const int64_t total = static_cast<int64_t>(B) * H * W;
   hipLaunchKernelGGL(unpack_output_kernel, dim3(grid_for(total)), dim3(256), 0, static_cast<hipStream_t>(hip_stream), B, H, W, y, y_ld, scale, q);
   return launched("unpack_output");
 }
@@ -697,9 +741,14 @@ int qnn_adam(int64_t n, float* p, float* m, float* v, const float* g, uint16_t* 
   return launched("adam");
 }
 
-int qnn_compare(int32_t B, int64_t m, const float* a, const float* r, double* rel, double* en, void* hip_stream) {
-  if (B < 1 || m < 1 || !a || !r || !rel || !en) return bad("compare: bad argument");
-  hipLaunchKernelGGL(compare_kernel, dim3(B), dim3(256), 0, static_cast<hipStream_t>(hip_stream), m, a, r, rel, en);
+int64_t qnn_compare_work_doubles(int32_t B) { return B < 1 ? 0 : static_cast<int64_t>(B) * kCompareBlocks * 3; }
+
+int qnn_compare(int32_t B, int64_t m, const float* a, const float* r, double* rel, double* en, double* work,
+                void* hip_stream) {
+  if (B < 1 || B > 65535 || m < 1 || !a || !r || !rel || !en || !work) return bad("compare: bad argument");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  hipLaunchKernelGGL(compare_kernel, dim3(kCompareBlocks, B), dim3(256), 0, st, m, a, r, work);
+  hipLaunchKernelGGL(compare_final_kernel, dim3((B + 255) / 256), dim3(256), 0, st, B, work, rel, en);
   return launched("compare");
 }
 

@@ -29,7 +29,7 @@ _SIGNATURES = {
     "qnn_rel_l2": [_i32, _i32, _i32, _vp, _i32, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp],
     "qnn_adam": [_i64, _vp, _vp, _vp, _vp, _vp, _f32, _f32, _f32, _f32, _i32, _vp],
     "qnn_to_bf16": [_i64, _vp, _vp, _vp],
-    "qnn_compare": [_i32, _i64, _vp, _vp, _vp, _vp, _vp],
+    "qnn_compare": [_i32, _i64, _vp, _vp, _vp, _vp, _vp, _vp],
 }
 
 _bound = False
@@ -45,6 +45,8 @@ def _lib():
             fn.restype = ctypes.c_int
         L.qnn_wgrad_work_floats.argtypes = [_i32, _i32, _i32, _i32, _i32]
         L.qnn_wgrad_work_floats.restype = ctypes.c_int64
+        L.qnn_compare_work_doubles.argtypes = [_i32]
+        L.qnn_compare_work_doubles.restype = ctypes.c_int64
         _bound = True
     return L
 
@@ -133,5 +135,9 @@ def qnn_to_bf16(n, x, y, stream=None):
     _call("qnn_to_bf16", n, _p(x), _p(y), _s(stream))
 
 
-def qnn_compare(B, m, a, r, rel, en, stream=None):
-    _call("qnn_compare", B, m, _p(a), _p(r), _p(rel), _p(en), _s(stream))
+def qnn_compare_work_doubles(B) -> int:
+    return int(_lib().qnn_compare_work_doubles(B))
+
+
+def qnn_compare(B, m, a, r, rel, en, work, stream=None):
+    _call("qnn_compare", B, m, _p(a), _p(r), _p(rel), _p(en), _p(work), _s(stream))

@@ -447,6 +447,7 @@ def sweep(net: UNet, n_list: Sequence, q_list: Sequence, delta: float, total_ste
     n_dev = torch.stack([t.view(3, H, W) for t in batch.n])
     rel = torch.empty(B, dtype=torch.float64, device=dev)
     en = torch.empty(B, dtype=torch.float64, device=dev)
+    cmp_work = torch.empty(qnn.qnn_compare_work_doubles(B), dtype=torch.float64, device=dev)
 
     def export(dst):
         for k in range(B):
@@ -470,7 +471,7 @@ def sweep(net: UNet, n_list: Sequence, q_list: Sequence, delta: float, total_ste
             checks += 1
             batch.step(K)                        # QLA from the saved pre-jump state
             export(ref)
-            qnn.qnn_compare(B, 6 * H * W, pred, ref, rel, en, stream)
+            qnn.qnn_compare(B, 6 * H * W, pred, ref, rel, en, cmp_work, stream)
             r, e = rel.cpu().numpy(), en.cpu().numpy()
             max_err, max_en = max(max_err, float(r.max())), max(max_en, float(e.max()))
             if float(r.max()) > tol or float(e.max()) > tol:

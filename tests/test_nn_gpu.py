@@ -166,6 +166,19 @@ def test_pack_absmax_unpack(env):
     np.testing.assert_array_equal(out.cpu().numpy(), want.astype(np.float32))
 
 
+def test_absmax_large_and_zero_samples(env):
+    torch, qnn = env
+    B, H, W = 3, 512, 384
+    q = torch.tensor(rnd(21, (B, 6, H, W)).astype(np.float32)).cuda()
+    q[1].zero_()
+    q[2, 5, 511, 383] = -7.5
+    scale = torch.full((B,), 123.0, dtype=torch.float32, device="cuda")
+    qnn.qnn_absmax(B, H, W, q, None, scale)
+    want = np.abs(q.cpu().numpy()).reshape(B, -1).max(axis=1)
+    want[1] = 1.0
+    np.testing.assert_array_equal(scale.cpu().numpy(), want.astype(np.float32))
+
+
 def test_relative_l2_loss_and_gradient(env):
     torch, qnn = env
     B, H, W = 3, 16, 16
@@ -208,13 +221,15 @@ def test_adam_step(env):
     np.testing.assert_array_equal(pb.float().cpu().numpy(), N.bf16_round(p.cpu().numpy()))
 
 
-def test_compare(env):
+@pytest.mark.parametrize("m", [1, 1000, 300001])
+def test_compare(env, m):
     torch, qnn = env
-    a = torch.tensor(rnd(18, (3, 1000)).astype(np.float32)).cuda()
-    b = torch.tensor(rnd(19, (3, 1000)).astype(np.float32)).cuda()
+    a = torch.tensor(rnd(18, (3, m)).astype(np.float32)).cuda()
+    b = torch.tensor(rnd(19, (3, m)).astype(np.float32)).cuda()
     rel = torch.empty(3, dtype=torch.float64, device="cuda")
     en = torch.empty(3, dtype=torch.float64, device="cuda")
-    qnn.qnn_compare(3, 1000, a, b, rel, en)
+    work = torch.empty(qnn.qnn_compare_work_doubles(3), dtype=torch.float64, device="cuda")
+    qnn.qnn_compare(3, m, a, b, rel, en, work)
     A, Bn = a.cpu().numpy().astype(np.float64), b.cpu().numpy().astype(np.float64)
     np.testing.assert_allclose(rel.cpu().numpy(), np.linalg.norm(A - Bn, axis=1) / np.linalg.norm(Bn, axis=1), rtol=1e-12)
     np.testing.assert_allclose(en.cpu().numpy(), np.abs((A ** 2).sum(1) - (Bn ** 2).sum(1)) / (Bn ** 2).sum(1), rtol=1e-10)

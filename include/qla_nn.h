@@ -110,7 +110,7 @@ int qnn_absmax(int32_t B, int32_t H, int32_t W, const float *q, const int32_t *i
  * the surrogate's jump, so each displaced copy lines up with the waves
  * that moved along one axis.
  *   q FP32 [N][6][H][W], n FP32 [M][3][H][W], scale FP32 [B],
- *   x BF16 [B*H*W][48].
+ *   x BF16 [B*H*W][48], 16-byte aligned (-1 otherwise).
  */
 int qnn_pack_input(int32_t B, int32_t H, int32_t W, const float *q, const int32_t *idx_q,
                    const float *n, const int32_t *idx_n, const float *scale, float n_shift,

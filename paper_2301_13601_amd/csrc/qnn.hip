@@ -315,6 +315,149 @@ __global__ void upsample2_bwd_kernel(int B, int h, int w, int C, const uint16_t*
   }
 }
 
+// 8-channel vector forms of the elementwise kernels (C % 8 == 0, 16-byte
+// aligned tensors): one thread moves 16 bytes per tensor, with the same
+// per-element arithmetic as the scalar forms above.
+__device__ inline void ld8(const uint16_t* p, float (&f)[8]) {
+  const uint4 u = *reinterpret_cast<const uint4*>(p);
+  const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    f[2 * k] = bf2f(static_cast<uint16_t>(w[k] & 0xffffu));
+    f[2 * k + 1] = bf2f(static_cast<uint16_t>(w[k] >> 16));
+  }
+}
+
+__device__ inline void st8(uint16_t* p, const float (&f)[8]) {
+  uint32_t w[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) w[k] = static_cast<uint32_t>(f2bf(f[2 * k])) | (static_cast<uint32_t>(f2bf(f[2 * k + 1])) << 16);
+  *reinterpret_cast<uint4*>(p) = make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+__global__ void leaky_bwd_v8_kernel(int64_t n8, const uint16_t* __restrict__ y, const uint16_t* dy, uint16_t* dz) {
+  QNN_GRID_STRIDE(i, n8) {
+    float a[8], g[8];
+    ld8(y + 8 * i, a);
+    ld8(dy + 8 * i, g);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) g[k] = a[k] > 0.0f ? g[k] : kLeakySlope * g[k];
+    st8(dz + 8 * i, g);
+  }
+}
+
+__global__ void add_v8_kernel(int64_t n8, const uint16_t* a, const uint16_t* b, uint16_t* y) {
+  QNN_GRID_STRIDE(i, n8) {
+    float u[8], v[8];
+    ld8(a + 8 * i, u);
+    ld8(b + 8 * i, v);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) u[k] = u[k] + v[k];
+    st8(y + 8 * i, u);
+  }
+}
+
+// one thread per (coarse pixel, 8-channel group)
+__global__ void avgpool2_v8_kernel(int B, int H, int W, int C, const uint16_t* __restrict__ x, uint16_t* __restrict__ y) {
+  const int h = H / 2, w = W / 2, G = C / 8;
+  const int64_t n = static_cast<int64_t>(B) * h * w * G;
+  QNN_GRID_STRIDE(i, n) {
+    const int g = static_cast<int>(i % G);
+    const int64_t pix = i / G;
+    const int xo = static_cast<int>(pix % w);
+    const int64_t r = pix / w;
+    const int yo = static_cast<int>(r % h);
+    const int64_t b = r / h;
+    const int64_t base = ((b * H + 2 * yo) * W + 2 * xo) * C + 8 * g;
+    const int64_t row = static_cast<int64_t>(W) * C;
+    float a[8], c1[8], c2[8], c3[8];
+    ld8(x + base, a);
+    ld8(x + base + C, c1);
+    ld8(x + base + row, c2);
+    ld8(x + base + row + C, c3);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) a[k] = 0.25f * (a[k] + c1[k] + c2[k] + c3[k]);
+    st8(y + pix * C + 8 * g, a);
+  }
+}
+
+__global__ void avgpool2_bwd_v8_kernel(int B, int H, int W, int C, const uint16_t* __restrict__ dy,
+                                       uint16_t* __restrict__ dx, int accumulate) {
+  const int h = H / 2, w = W / 2, G = C / 8;
+  const int64_t n = static_cast<int64_t>(B) * h * w * G;
+  QNN_GRID_STRIDE(i, n) {
+    const int g = static_cast<int>(i % G);
+    const int64_t pix = i / G;
+    const int xo = static_cast<int>(pix % w);
+    const int64_t r = pix / w;
+    const int yo = static_cast<int>(r % h);
+    const int64_t b = r / h;
+    float d[8];
+    ld8(dy + pix * C + 8 * g, d);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) d[k] = 0.25f * d[k];
+    const int64_t base = ((b * H + 2 * yo) * W + 2 * xo) * C + 8 * g;
+    const int64_t off[4] = {0, C, static_cast<int64_t>(W) * C, static_cast<int64_t>(W) * C + C};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      float o[8];
+      if (accumulate) {
+        ld8(dx + base + off[j], o);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) o[k] = o[k] + d[k];
+      } else {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) o[k] = d[k];
+      }
+      st8(dx + base + off[j], o);
+    }
+  }
+}
+
+__global__ void upsample2_v8_kernel(int B, int h, int w, int C, const uint16_t* __restrict__ x, uint16_t* __restrict__ y) {
+  const int W = 2 * w, G = C / 8;
+  const int64_t n = static_cast<int64_t>(B) * h * w * G;
+  QNN_GRID_STRIDE(i, n) {
+    const int g = static_cast<int>(i % G);
+    const int64_t pix = i / G;
+    const int xo = static_cast<int>(pix % w);
+    const int64_t r = pix / w;
+    const int yo = static_cast<int>(r % h);
+    const int64_t b = r / h;
+    const uint4 v = *reinterpret_cast<const uint4*>(x + pix * C + 8 * g);
+    const int64_t base = ((b * 2 * h + 2 * yo) * W + 2 * xo) * C + 8 * g;
+    const int64_t row = static_cast<int64_t>(W) * C;
+    *reinterpret_cast<uint4*>(y + base) = v;
+    *reinterpret_cast<uint4*>(y + base + C) = v;
+    *reinterpret_cast<uint4*>(y + base + row) = v;
+    *reinterpret_cast<uint4*>(y + base + row + C) = v;
+  }
+}
+
+__global__ void upsample2_bwd_v8_kernel(int B, int h, int w, int C, const uint16_t* __restrict__ dy,
+                                        uint16_t* __restrict__ dx) {
+  const int W = 2 * w, G = C / 8;
+  const int64_t n = static_cast<int64_t>(B) * h * w * G;
+  QNN_GRID_STRIDE(i, n) {
+    const int g = static_cast<int>(i % G);
+    const int64_t pix = i / G;
+    const int xo = static_cast<int>(pix % w);
+    const int64_t r = pix / w;
+    const int yo = static_cast<int>(r % h);
+    const int64_t b = r / h;
+    const int64_t base = ((b * 2 * h + 2 * yo) * W + 2 * xo) * C + 8 * g;
+    const int64_t row = static_cast<int64_t>(W) * C;
+    float a[8], c1[8], c2[8], c3[8];
+    ld8(dy + base, a);
+    ld8(dy + base + C, c1);
+    ld8(dy + base + row, c2);
+    ld8(dy + base + row + C, c3);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) a[k] = a[k] + c1[k] + c2[k] + c3[k];
+    st8(dx + pix * C + 8 * g, a);
+  }
+}
+
 // Per-sample max |q|: a 2D grid of blocks per sample, each folding its
 // share with an unsigned atomic max on the float's bits (|q| >= 0, whose bit
 // patterns order like the values); absmax_init clears, absmax_fix turns 0
@@ -350,40 +493,54 @@ __global__ void absmax_fix_kernel(int B, float* __restrict__ scale) {
 
 constexpr int kInCh = 48;
 
+// Input channel c of pixel (yy, xx) of sample b (see qnn_pack_input).
+__device__ inline float pack_value(int c, int b, int yy, int xx, int H, int W, int64_t HW, const float* __restrict__ q,
+                                   const int32_t* __restrict__ idx_q, const float* __restrict__ n,
+                                   const int32_t* __restrict__ idx_n, const float* __restrict__ scale,
+                                   float n_shift, float n_scale, int shift) {
+  const int64_t s = static_cast<int64_t>(yy) * W + xx;
+  const int64_t qs = idx_q ? idx_q[b] : b;
+  if (c < 6) return q[(qs * 6 + c) * HW + s] / scale[b];
+  if (c < 9) {
+    const int64_t ns = idx_n ? idx_n[b] : b;
+    return (n[(ns * 3 + (c - 6)) * HW + s] - n_shift) / n_scale;
+  }
+  if (c < 33) {
+    const int blk = (c - 9) / 6, cc = (c - 9) % 6;
+    int sy = yy, sx = xx;
+    if (blk == 0) sx = xx - shift;
+    else if (blk == 1) sx = xx + shift;
+    else if (blk == 2) sy = yy - shift;
+    else sy = yy + shift;
+    sx %= W;
+    if (sx < 0) sx += W;
+    sy %= H;
+    if (sy < 0) sy += H;
+    return q[(qs * 6 + cc) * HW + static_cast<int64_t>(sy) * W + sx] / scale[b];
+  }
+  return 0.0f;
+}
+
+// one thread per (pixel, 8-channel group): 16-byte stores of the NHWC input
 __global__ void pack_input_kernel(int B, int H, int W, const float* __restrict__ q, const int32_t* __restrict__ idx_q,
                                   const float* __restrict__ n, const int32_t* __restrict__ idx_n,
                                   const float* __restrict__ scale, float n_shift, float n_scale, int shift,
                                   uint16_t* __restrict__ x) {
   const int64_t HW = static_cast<int64_t>(H) * W;
-  const int64_t total = B * HW * kInCh;
+  constexpr int G = kInCh / 8;
+  const int64_t total = B * HW * G;
   QNN_GRID_STRIDE(i, total) {
-    const int c = static_cast<int>(i % kInCh);
-    const int64_t p = i / kInCh;
+    const int g = static_cast<int>(i % G);
+    const int64_t p = i / G;
     const int b = static_cast<int>(p / HW);
     const int64_t s = p - b * HW;
     const int yy = static_cast<int>(s / W);
     const int xx = static_cast<int>(s - static_cast<int64_t>(yy) * W);
-    float v = 0.0f;
-    const int64_t qs = idx_q ? idx_q[b] : b;
-    if (c < 6) {
-      v = q[(qs * 6 + c) * HW + s] / scale[b];
-    } else if (c < 9) {
-      const int64_t ns = idx_n ? idx_n[b] : b;
-      v = (n[(ns * 3 + (c - 6)) * HW + s] - n_shift) / n_scale;
-    } else if (c < 33) {
-      const int blk = (c - 9) / 6, cc = (c - 9) % 6;
-      int sy = yy, sx = xx;
-      if (blk == 0) sx = xx - shift;
-      else if (blk == 1) sx = xx + shift;
-      else if (blk == 2) sy = yy - shift;
-      else sy = yy + shift;
-      sx %= W;
-      if (sx < 0) sx += W;
-      sy %= H;
-      if (sy < 0) sy += H;
-      v = q[(qs * 6 + cc) * HW + static_cast<int64_t>(sy) * W + sx] / scale[b];
-    }
-    x[i] = f2bf(v);
+    float v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      v[j] = pack_value(8 * g + j, b, yy, xx, H, W, HW, q, idx_q, n, idx_n, scale, n_shift, n_scale, shift);
+    st8(x + p * kInCh + 8 * g, v);
   }
 }
 
@@ -646,14 +803,25 @@ int qnn_conv3x3_wgrad(int32_t B, int32_t H, int32_t W, const uint16_t* x, int32_
   return launched("conv3x3_wgrad");
 }
 
+// the 8-channel vector kernels need 16-byte alignment of every tensor
+static bool a16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
 int qnn_leaky_bwd(int64_t n, const uint16_t* y, const uint16_t* dy, uint16_t* dz, void* hip_stream) {
   if (n < 0 || !y || !dy || !dz) return bad("leaky_bwd: bad size or null pointer");
+  if (n % 8 == 0 && a16(y) && a16(dy) && a16(dz)) {
+    hipLaunchKernelGGL(leaky_bwd_v8_kernel, dim3(grid_for(n / 8)), dim3(256), 0, static_cast<hipStream_t>(hip_stream), n / 8, y, dy, dz);
+    return launched("leaky_bwd");
+  }
   hipLaunchKernelGGL(leaky_bwd_kernel, dim3(grid_for(n)), dim3(256), 0, static_cast<hipStream_t>(hip_stream), n, y, dy, dz);
   return launched("leaky_bwd");
 }
 
 int qnn_add(int64_t n, const uint16_t* a, const uint16_t* b, uint16_t* y, void* hip_stream) {
   if (n < 0 || !a || !b || !y) return bad("add: bad size or null pointer");
+  if (n % 8 == 0 && a16(a) && a16(b) && a16(y)) {
+    hipLaunchKernelGGL(add_v8_kernel, dim3(grid_for(n / 8)), dim3(256), 0, static_cast<hipStream_t>(hip_stream), n / 8, a, b, y);
+    return launched("add");
+  }
   hipLaunchKernelGGL(add_kernel, dim3(grid_for(n)), dim3(256), 0, static_cast<hipStream_t>(hip_stream), n, a, b, y);
   return launched("add");
 }
@@ -661,6 +829,10 @@ int qnn_add(int64_t n, const uint16_t* a, const uint16_t* b, uint16_t* y, void* 
 int qnn_avgpool2(int32_t B, int32_t H, int32_t W, int32_t C, const uint16_t* x, uint16_t* y, void* hip_stream) {
   if (B < 1 || H < 2 || W < 2 || (H | W) & 1 || C < 1 || !x || !y) return bad("avgpool2: bad size or null pointer");
   const int64_t n = static_cast<int64_t>(B) * (H / 2) * (W / 2) * C;
+  if (C % 8 == 0 && a16(x) && a16(y)) {
+    hipLaunchKernelGGL(avgpool2_v8_kernel, dim3(grid_for(n / 8)), dim3(256), 0, static_cast<hipStream_t>(hip_stream), B, H, W, C, x, y);
+    return launched("avgpool2");
+  }
   hipLaunchKernelGGL(avgpool2_kernel, dim3(grid_for(n)), dim3(256), 0, static_cast<hipStream_t>(hip_stream), B, H, W, C, x, y);
   return launched("avgpool2");
 }
@@ -669,6 +841,10 @@ int qnn_avgpool2_bwd(int32_t B, int32_t H, int32_t W, int32_t C, const uint16_t*
                      void* hip_stream) {
   if (B < 1 || H < 2 || W < 2 || (H | W) & 1 || C < 1 || !dy || !dx) return bad("avgpool2_bwd: bad size or null pointer");
   const int64_t n = static_cast<int64_t>(B) * H * W * C;
+  if (C % 8 == 0 && a16(dy) && a16(dx)) {
+    hipLaunchKernelGGL(avgpool2_bwd_v8_kernel, dim3(grid_for(n / 32)), dim3(256), 0, static_cast<hipStream_t>(hip_stream), B, H, W, C, dy, dx, accumulate);
+    return launched("avgpool2_bwd");
+  }
   hipLaunchKernelGGL(avgpool2_bwd_kernel, dim3(grid_for(n)), dim3(256), 0, static_cast<hipStream_t>(hip_stream), B, H, W, C, dy, dx, accumulate);
   return launched("avgpool2_bwd");
 }
@@ -676,6 +852,10 @@ int qnn_avgpool2_bwd(int32_t B, int32_t H, int32_t W, int32_t C, const uint16_t*
 int qnn_upsample2(int32_t B, int32_t h, int32_t w, int32_t C, const uint16_t* x, uint16_t* y, void* hip_stream) {
   if (B < 1 || h < 1 || w < 1 || C < 1 || !x || !y) return bad("upsample2: bad size or null pointer");
   const int64_t n = static_cast<int64_t>(B) * 4 * h * w * C;
+  if (C % 8 == 0 && a16(x) && a16(y)) {
+    hipLaunchKernelGGL(upsample2_v8_kernel, dim3(grid_for(n / 32)), dim3(256), 0, static_cast<hipStream_t>(hip_stream), B, h, w, C, x, y);
+    return launched("upsample2");
+  }
   hipLaunchKernelGGL(upsample2_kernel, dim3(grid_for(n)), dim3(256), 0, static_cast<hipStream_t>(hip_stream), B, h, w, C, x, y);
   return launched("upsample2");
 }
@@ -683,6 +863,10 @@ int qnn_upsample2(int32_t B, int32_t h, int32_t w, int32_t C, const uint16_t* x,
 int qnn_upsample2_bwd(int32_t B, int32_t h, int32_t w, int32_t C, const uint16_t* dy, uint16_t* dx, void* hip_stream) {
   if (B < 1 || h < 1 || w < 1 || C < 1 || !dy || !dx) return bad("upsample2_bwd: bad size or null pointer");
   const int64_t n = static_cast<int64_t>(B) * h * w * C;
+  if (C % 8 == 0 && a16(dy) && a16(dx)) {
+    hipLaunchKernelGGL(upsample2_bwd_v8_kernel, dim3(grid_for(n / 8)), dim3(256), 0, static_cast<hipStream_t>(hip_stream), B, h, w, C, dy, dx);
+    return launched("upsample2_bwd");
+  }
   hipLaunchKernelGGL(upsample2_bwd_kernel, dim3(grid_for(n)), dim3(256), 0, static_cast<hipStream_t>(hip_stream), B, h, w, C, dy, dx);
   return launched("upsample2_bwd");
 }
@@ -702,7 +886,8 @@ int qnn_pack_input(int32_t B, int32_t H, int32_t W, const float* q, const int32_
                    const int32_t* idx_n, const float* scale, float n_shift, float n_scale, int32_t shift,
                    uint16_t* x, void* hip_stream) {
   if (B < 1 || H < 1 || W < 1 || !q || !n || !scale || !x || !(n_scale != 0.0f)) return bad("pack_input: bad argument");
-  const int64_t total = static_cast<int64_t>(B) * H * W * kInCh;
+  if (!a16(x)) return bad("pack_input: x must be 16-byte aligned");
+  const int64_t total = static_cast<int64_t>(B) * H * W * (kInCh / 8);
   hipLaunchKernelGGL(pack_input_kernel, dim3(grid_for(total)), dim3(256), 0, static_cast<hipStream_t>(hip_stream), B, H, W, q, idx_q, n, idx_n, scale, n_shift, n_scale, shift, x);
   return launched("pack_input");
 }

@@ -104,9 +104,11 @@ def test_conv_weight_gradient(env, B, H, W, ci, co):
     assert torch.equal(dw, again)       # deterministic reduction order
 
 
-def test_elementwise_kernels_bit_exact(env):
+@pytest.mark.parametrize("C", [32, 48, 12])
+def test_elementwise_kernels_bit_exact(env, C):
+    """C % 8 == 0 runs the 16-byte vector kernels, C = 12 the scalar ones."""
     torch, qnn = env
-    B, H, W, C = 2, 8, 12, 32
+    B, H, W = 2, 8, 12
     x, xr = bf(torch, rnd(10, (B, H, W, C)))
     y, yr = bf(torch, rnd(11, (B, H, W, C)))
     n = B * H * W * C
@@ -131,6 +133,19 @@ def test_elementwise_kernels_bit_exact(env):
     d = torch.empty_like(x)
     qnn.qnn_upsample2_bwd(B, H, W, C, u, d)
     np.testing.assert_array_equal(d.float().cpu().numpy(), N.bf16_round(N.upsample2_bwd(N.upsample2(xr))))
+
+
+def test_elementwise_unaligned_views(env):
+    """Views that start 2 bytes into a buffer take the scalar kernels."""
+    torch, qnn = env
+    n = 8 * 1000
+    xa, xr = bf(torch, rnd(30, n + 1))
+    ya, yr = bf(torch, rnd(31, n + 1))
+    out = torch.empty(n + 1, dtype=torch.bfloat16, device="cuda")
+    qnn.qnn_add(n, xa[1:], ya[1:], out[1:])
+    np.testing.assert_array_equal(out[1:].float().cpu().numpy(), N.bf16_round(xr[1:] + yr[1:]))
+    qnn.qnn_leaky_bwd(n, xa[1:], ya[1:], out[1:])
+    np.testing.assert_array_equal(out[1:].float().cpu().numpy(), N.bf16_round(N.leaky_bwd(xr[1:], yr[1:])))
 
 
 def test_pack_absmax_unpack(env):

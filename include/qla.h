@@ -118,9 +118,11 @@ typedef struct qla_ctx qla_ctx;   /* opaque */
  * lattice columns (120 of them output; 112 when a launch advances two
  * steps) and a segment of seg_rows rows. A field set to 0 asks for the
  * library's default.
- *   seg_rows         rows per wave segment, rounded up to a multiple of 4
- *                    (default: the shortest for which the whole grid is
- *                    resident at once)
+ *   seg_rows         rows per wave segment for every lattice, rounded up
+ *                    to a multiple of 4 (default: per lattice, segments of
+ *                    about equal height across the batch, the height picked
+ *                    by simulating the block schedule; qla_get_launch then
+ *                    reports the tallest)
  *   waves_per_block  1..4 waves (vertically adjacent segments) per block
  *                    (default 1)
  *   graph_steps      steps per replayed HIP graph (rounded up to a multiple

@@ -12,6 +12,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <new>
 #include <vector>
 
@@ -372,48 +373,96 @@ void drop_graphs(qla_ctx* c) {
 
 // Launch geometry. A wave covers 128 columns of which 120 are output (112
 // for a two-step launch); each lattice is cut into strips (x) and segments
-// (y). Unless a segment height is requested, the planner picks the smallest
-// height (a multiple of 4) for which the whole grid is resident at once (one
-// round, no tail); taller segments re-read fewer halo rows (8 per segment
-// per step).
+// (y), and every segment costs its rows plus 8 halo rows per step. A
+// requested segment height applies to every lattice. Otherwise the planner
+// takes a target height S, gives each lattice the whole number of segments
+// closest to its height / S (so segments of all lattices are about equally
+// tall), and keeps the S whose blocks, handed in launch order to the
+// resident block slots (earliest free slot first), finish soonest; among
+// near ties it prefers taller segments (fewer halo rows).
+struct SegPlan {
+  std::vector<int> seg;     // rows per segment, per lattice
+  int64_t blocks = 0;
+  int64_t makespan = 0;     // in row iterations
+};
+
+SegPlan segment_plan(const qla_ctx* c, const std::vector<int>& nstrips, int wpb, int halo, int S, bool uniform,
+                     int64_t slots) {
+  SegPlan pl;
+  pl.seg.resize(c->count);
+  for (int i = 0; i < c->count; ++i) {
+    const int ny = c->p[i].ny;
+    int h = S;
+    if (!uniform) {
+      const int nseg = std::max(1, static_cast<int>((static_cast<int64_t>(ny) + S / 2) / S));
+      h = (ny + nseg - 1) / nseg;
+    }
+    h = std::max(4, (h + 3) & ~3);
+    pl.seg[i] = h;
+    const int nsegs = (ny + h - 1) / h;
+    pl.blocks += static_cast<int64_t>(nstrips[i]) * ((nsegs + wpb - 1) / wpb);
+  }
+  if (slots <= 0) return pl;
+  // earliest-free-slot simulation of the launch order; a block of wpb
+  // segments lasts as long as its tallest segment
+  std::vector<int64_t> heap(static_cast<size_t>(std::min<int64_t>(slots, pl.blocks)), 0);
+  auto cmp = std::greater<int64_t>();
+  for (int i = 0; i < c->count; ++i) {
+    const int ny = c->p[i].ny, h = pl.seg[i];
+    const int nsegs = (ny + h - 1) / h;
+    for (int j = 0; j < nsegs; j += wpb) {
+      const int64_t d = std::min(h, ny - j * h) + halo;
+      for (int k = 0; k < nstrips[i]; ++k) {
+        std::pop_heap(heap.begin(), heap.end(), cmp);
+        heap.back() += d;
+        pl.makespan = std::max(pl.makespan, heap.back());
+        std::push_heap(heap.begin(), heap.end(), cmp);
+      }
+    }
+  }
+  return pl;
+}
+
 qla_status plan_geometry(qla_ctx* c, int steps, int wpb) {
   auto& geo = c->geo[steps - 1];
   // a two-step block is one producer/consumer pair of waves
   if (steps == 2) wpb = 1;
   const int threads = steps == 2 ? 2 * kWave : kWave * wpb;
   const int oc = out_cols(steps);
+  const int halo = 8 * steps;
   int max_ny = 1;
   for (const auto& p : c->p) max_ny = std::max(max_ny, p.ny);
   std::vector<int> nstrips(c->count);
   for (int i = 0; i < c->count; ++i) nstrips[i] = (c->p[i].nx + oc - 1) / oc;
-  auto blocks_for = [&](int S) {
-    int64_t t = 0;
-    for (int i = 0; i < c->count; ++i) {
-      const int nsegs = (c->p[i].ny + S - 1) / S;
-      t += static_cast<int64_t>(nstrips[i]) * ((nsegs + wpb - 1) / wpb);
-    }
-    return t;
-  };
-  int S = c->launch.seg_rows;
-  if (S <= 0) {
+  SegPlan pl;
+  if (c->launch.seg_rows > 0) {
+    pl = segment_plan(c, nstrips, wpb, halo, c->launch.seg_rows, true, 0);
+  } else {
     int bpc = 0;
     hipError_t e = c->step.blocks_per_cu[steps - 1](&bpc, threads);
     if (e != hipSuccess || bpc < 1) bpc = 1;
     const int64_t slots = static_cast<int64_t>(c->cus) * bpc;
     const int top = (max_ny + 3) & ~3;
-    S = top;
-    for (int s = 8; s < top; s += 4) {
-      if (blocks_for(s) <= slots) {
-        S = s;
-        break;
-      }
+    // about 96 candidate targets, denser where segments are short
+    std::vector<int> cand;
+    for (int s = 8; s <= top; s += std::max(4, (s / 24) & ~3)) cand.push_back(s);
+    if (cand.empty() || cand.back() != top) cand.push_back(top);
+    std::vector<int64_t> span(cand.size());
+    int64_t best = -1;
+    for (size_t k = 0; k < cand.size(); ++k) {
+      span[k] = segment_plan(c, nstrips, wpb, halo, cand[k], false, slots).makespan;
+      if (best < 0 || span[k] < best) best = span[k];
     }
+    // the tallest target within 1% of the best makespan
+    size_t pick = 0;
+    for (size_t k = 0; k < cand.size(); ++k)
+      if (span[k] * 100 <= best * 101) pick = k;
+    pl = segment_plan(c, nstrips, wpb, halo, cand[pick], false, 0);
   }
-  S = std::max(4, (S + 3) & ~3);
-  const int64_t total = blocks_for(S);
-  if (total > (int64_t{1} << 30)) return fail(QLA_EINVAL, "qla: launch geometry too large");
+  if (pl.blocks > (int64_t{1} << 30)) return fail(QLA_EINVAL, "qla: launch geometry too large");
   geo.desc.assign(c->count, InstDesc{});
   int first = 0;
+  int tallest = 4;
   for (int i = 0; i < c->count; ++i) {
     const qla_params& p = c->p[i];
     InstDesc& d = geo.desc[i];
@@ -423,21 +472,22 @@ qla_status plan_geometry(qla_ctx* c, int steps, int wpb) {
     d.plane = static_cast<int64_t>(p.nx) * p.ny;
     d.nx = p.nx;
     d.ny = p.ny;
-    d.seg_rows = S;
+    d.seg_rows = pl.seg[i];
     d.nstrips = nstrips[i];
-    d.nsegs = (p.ny + S - 1) / S;
+    d.nsegs = (p.ny + d.seg_rows - 1) / d.seg_rows;
     d.first_block = first;
     d.a4 = static_cast<float>(p.delta / 4.0);
     d.kb = static_cast<float>(kb_of(p));
     first += d.nstrips * ((d.nsegs + wpb - 1) / wpb);
+    tallest = std::max(tallest, d.seg_rows);
   }
   hipError_t e = hipMemcpyAsync(geo.d_desc, geo.desc.data(), sizeof(InstDesc) * c->count,
                                 hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "uploading the lattice descriptors");
-  geo.grid = dim3(static_cast<unsigned>(total));
+  geo.grid = dim3(static_cast<unsigned>(pl.blocks));
   geo.block = dim3(threads);
-  geo.seg_rows = S;
+  geo.seg_rows = tallest;
   return QLA_OK;
 }
 

@@ -795,9 +795,14 @@ __device__ __forceinline__ void march(const StepArgs& g, const uint32_t (&xo)[C]
 // producer emits, 4 rows behind and one iteration later. Rows the producer
 // cannot produce exactly (its first 8 and last 8 iterations, and the outer
 // 8 columns of the strip) only ever reach halo rows and columns of the
-// consumer, which are not stored.
+// consumer, which are not stored. The index rows the consumer needs are the
+// producer's, three iterations later, so they travel through the ring too:
+// n crosses HBM once per launch as well.
 template <int C>
-using Ring = float[2][6][kWave * C];
+struct Ring {
+  float q[2][6][kWave * C];   // the emitted row
+  float n[2][3][kWave * C];   // the producer's current index row
+};
 
 template <int C, class O, int DIR>
 __device__ __forceinline__ void march2(const StepArgs& g, const uint32_t (&xo)[C],
@@ -834,7 +839,12 @@ __device__ __forceinline__ void march2(const StepArgs& g, const uint32_t (&xo)[C
     process_row<C, O, DIR, S, true, 8>(p, g, so, edge_lane, i + S, seg_h, y0, e);              \
     _Pragma("unroll") for (int c = 0; c < 6; ++c) {                                            \
       if (!O::live(c)) continue;                                                               \
-      _Pragma("unroll") for (int k = 0; k < C; ++k) ring[(S) & 1][c][lane * C + k] = e[c][k];  \
+      _Pragma("unroll") for (int k = 0; k < C; ++k) ring.q[(S) & 1][c][lane * C + k] = e[c][k]; \
+    }                                                                                          \
+    _Pragma("unroll") for (int c = 0; c < 3; ++c) {                                            \
+      if (!O::nlive(c)) continue;                                                              \
+      _Pragma("unroll") for (int k = 0; k < C; ++k)                                            \
+        ring.n[(S) & 1][c][lane * C + k] = p.ncur[c][k];                                       \
     }                                                                                          \
     advance<C, O, true>(p, qld, nld);                                                          \
     rq = next_row<DIR>(rq, g.ny);                                                              \
@@ -850,20 +860,32 @@ __device__ __forceinline__ void march2(const StepArgs& g, const uint32_t (&xo)[C
     __syncthreads();     // the consumer's last row
   } else {
     prime_n<C, O, DIR>(p, g, xo, RB);
-    int rn = wrap_index(RB + 3 * DIR, g.ny);
+    // n of row RB+3*DIR, the first row the consumer's window takes in;
+    // later rows are the producer's current rows, one iteration old
+    float nbuf[3][C];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int k = 0; k < C; ++k) nbuf[c][k] = 1.0f;
+    load_n<C, O>(g, g.n + wrap_index(RB + 3 * DIR, g.ny) * nx64, xo, nbuf);
     __syncthreads();     // the producer's first row
     for (int i = 0; i < iters; i += 4) {
 #define QLA_ITER_B(S)                                                                          \
   {                                                                                            \
     float nld[3][C];                                                                           \
-    load_n<C, O>(g, g.n + rn * nx64, xo, nld);                                                 \
+    _Pragma("unroll") for (int c = 0; c < 3; ++c) {                                            \
+      if (!O::nlive(c)) continue;                                                              \
+      _Pragma("unroll") for (int k = 0; k < C; ++k) {                                          \
+        nld[c][k] = nbuf[c][k];                                                                \
+        nbuf[c][k] = ring.n[(S) & 1][c][lane * C + k];                                         \
+      }                                                                                        \
+    }                                                                                          \
     _Pragma("unroll") for (int c = 0; c < 6; ++c) {                                            \
       if (!O::live(c)) continue;                                                               \
-      _Pragma("unroll") for (int k = 0; k < C; ++k) p.q[c][k] = ring[(S) & 1][c][lane * C + k]; \
+      _Pragma("unroll") for (int k = 0; k < C; ++k) p.q[c][k] = ring.q[(S) & 1][c][lane * C + k]; \
     }                                                                                          \
     process_row<C, O, DIR, S, false, 12>(p, g, so, edge_lane, i + S, seg_h, y0, unused);       \
     advance<C, O, false>(p, unused, nld);                                                      \
-    rn = next_row<DIR>(rn, g.ny);                                                              \
     __syncthreads();                                                                           \
   }
       QLA_ITER_B(0)

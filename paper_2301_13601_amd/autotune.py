@@ -31,7 +31,7 @@ def candidates(default_seg: int, max_ny: int, steps_per_pass: int = 1) -> List[D
     """Geometries to try around the library's default segment height for
     launches of ``steps_per_pass`` steps."""
     segs = {default_seg}
-    for f in (0.5, 0.75, 1.5, 2.0, 3.0):
+    for f in (0.25, 0.5, 0.75, 1.5, 2.0, 3.0):
         s = int(round(default_seg * f / 4.0)) * 4
         if 8 <= s <= max(8, max_ny + 3):
             segs.add(s)

@@ -111,6 +111,125 @@ __global__ void __launch_bounds__(256) conv_fwd_kernel(int P, int H, int W, cons
   }
 }
 
+// ---------------------------------------------------------------------------
+// Forward 3x3 circular convolution, tiled: a block computes a tile of 128
+// output pixels (TH rows x TW columns of one image, TW = min(W, 64)) for
+// 32*NT output channels. The input tile with its one-pixel halo is staged
+// in LDS 16 channels at a time (double-buffered, the next chunk's global
+// loads in flight during the current chunk's MFMAs), so each input value
+// crosses L2 once per tile instead of once per tap; the nine taps then read
+// their A operands from LDS, and one A operand feeds NT MFMAs.
+// ---------------------------------------------------------------------------
+constexpr int kTilePix = 128;
+constexpr int kPixStride = 24;                       // LDS elements per staged pixel (16 + 8 pad)
+constexpr int kMaxStaged = (2 + 2) * (64 + 2);       // (TH + 2) * (TW + 2), largest for TW = 64
+constexpr int kLoadItems = (2 * kMaxStaged + 255) / 256;
+
+template <int NT, bool OUT_FP32>
+__global__ void __launch_bounds__(256) conv_fwd_tile_kernel(int H, int W, int TW, const uint16_t* __restrict__ x,
+                                                            int cin, const uint16_t* __restrict__ w,
+                                                            const float* __restrict__ bias, int act,
+                                                            void* __restrict__ y, int y_ld, int c_store) {
+  __shared__ __attribute__((aligned(16))) uint16_t tile[2][kMaxStaged * kPixStride];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int TH = kTilePix / TW;
+  const int tiles_x = W / TW;
+  const int tiles_y = (H + TH - 1) / TH;
+  int t = blockIdx.x;
+  const int tx0 = (t % tiles_x) * TW;
+  t /= tiles_x;
+  const int ty0 = (t % tiles_y) * TH;
+  const int b = t / tiles_y;
+  const int n0 = blockIdx.y * 32 * NT;
+  const int TWp = TW + 2;
+  const int nstaged = (TH + 2) * TWp;
+  // this lane's A row: tile pixel j
+  const int j = wave * 32 + (lane & 31);
+  const int py = j / TW, px = j - (j / TW) * TW;
+  const int kh = (lane >> 5) * 8;
+  const int K = 9 * cin;
+  const uint16_t* wl[NT];
+#pragma unroll
+  for (int jn = 0; jn < NT; ++jn) wl[jn] = w + static_cast<int64_t>(n0 + jn * 32 + (lane & 31)) * K + kh;
+  // staging items: (pixel, 8-channel half) pairs of the tile, 16 bytes
+  // each; thread i stages items i, i + 256 and i + 512 (named, so that they
+  // stay in registers)
+  static_assert(kLoadItems == 3, "three staging items per thread");
+  auto item = [&](int i, int64_t& src, int& dst) {
+    dst = -1;
+    src = 0;
+    if (i < 2 * nstaged) {
+      const int pi = i >> 1, half = i & 1;
+      const int r = pi / TWp, cc = pi - (pi / TWp) * TWp;
+      // periodic; rows of a partial last tile may lie several H past the end
+      const int yy = ((ty0 - 1 + r) % H + H) % H;
+      int xx = tx0 - 1 + cc;
+      xx = xx < 0 ? xx + W : (xx >= W ? xx - W : xx);
+      src = (static_cast<int64_t>(b) * H + yy) * W * cin + static_cast<int64_t>(xx) * cin + half * 8;
+      dst = pi * kPixStride + half * 8;
+    }
+  };
+  int64_t g0, g1, g2;
+  int l0, l1, l2;
+  item(threadIdx.x, g0, l0);
+  item(threadIdx.x + 256, g1, l1);
+  item(threadIdx.x + 512, g2, l2);
+  f32x16 acc[NT];
+#pragma unroll
+  for (int jn = 0; jn < NT; ++jn)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[jn][r] = 0.0f;
+  const int nchunks = cin / 16;
+  uint4 s0 = make_uint4(0, 0, 0, 0), s1 = s0, s2 = s0;
+  if (l0 >= 0) s0 = *reinterpret_cast<const uint4*>(x + g0);
+  if (l1 >= 0) s1 = *reinterpret_cast<const uint4*>(x + g1);
+  if (l2 >= 0) s2 = *reinterpret_cast<const uint4*>(x + g2);
+  for (int c = 0; c < nchunks; ++c) {
+    uint16_t* buf = tile[c & 1];
+    if (l0 >= 0) *reinterpret_cast<uint4*>(buf + l0) = s0;
+    if (l1 >= 0) *reinterpret_cast<uint4*>(buf + l1) = s1;
+    if (l2 >= 0) *reinterpret_cast<uint4*>(buf + l2) = s2;
+    __syncthreads();
+    if (c + 1 < nchunks) {
+      const int64_t o = (c + 1) * 16;
+      if (l0 >= 0) s0 = *reinterpret_cast<const uint4*>(x + g0 + o);
+      if (l1 >= 0) s1 = *reinterpret_cast<const uint4*>(x + g1 + o);
+      if (l2 >= 0) s2 = *reinterpret_cast<const uint4*>(x + g2 + o);
+    }
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+      const int dy = tap / 3, dx = tap % 3;   // offsets +1 into the staged tile
+      const bf16x8 a = *reinterpret_cast<const bf16x8*>(buf + ((py + dy) * TWp + (px + dx)) * kPixStride + kh);
+#pragma unroll
+      for (int jn = 0; jn < NT; ++jn) {
+        const bf16x8 bv = *reinterpret_cast<const bf16x8*>(wl[jn] + tap * cin + c * 16);
+        acc[jn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bv, acc[jn], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int jn = 0; jn < NT; ++jn) {
+    const int col = n0 + jn * 32 + (lane & 31);
+    if (col >= c_store) continue;
+    const float bsum = bias ? bias[col] : 0.0f;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int m = (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+      const int jj = wave * 32 + m;
+      const int oy = ty0 + jj / TW, ox = tx0 + jj % TW;
+      if (oy >= H) continue;
+      const int64_t row = (static_cast<int64_t>(b) * H + oy) * W + ox;
+      float v = acc[jn][r] + bsum;
+      if (act == QNN_ACT_LEAKY) v = v > 0.0f ? v : kLeakySlope * v;
+      if constexpr (OUT_FP32)
+        static_cast<float*>(y)[row * y_ld + col] = v;
+      else
+        static_cast<uint16_t*>(y)[row * y_ld + col] = f2bf(v);
+    }
+  }
+}
+
 __global__ void flip_kernel(const uint16_t* __restrict__ w, int cout, int cin, uint16_t* __restrict__ wt) {
   const int64_t n = static_cast<int64_t>(cout) * 9 * cin;
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
@@ -755,6 +874,24 @@ int qnn_conv3x3_fwd(int32_t B, int32_t H, int32_t W, const uint16_t* x, int32_t 
   if (P64 * (c_in > y_ld ? c_in : y_ld) >= (int64_t{1} << 31)) return bad("conv3x3_fwd: tensor too large");
   const int P = static_cast<int>(P64);
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const int TW = W < 64 ? W : 64;
+  const int TH = kTilePix / TW;
+  const int64_t tiles = static_cast<int64_t>(B) * (W / TW) * ((H + TH - 1) / TH);
+  const int tnt = (c_out % 128 == 0) ? 4 : (c_out % 64 == 0) ? 2 : 1;
+  // the tiled kernel needs W in whole 16/32/64-column tiles, and enough
+  // tiles to fill the chip (two blocks per CU); small layers use the
+  // pixel-list kernel below, which splits the channels finer
+  if (W % 16 == 0 && W % TW == 0 && kTilePix % TW == 0 && tiles * (c_out / (32 * tnt)) >= 512) {
+    const int nt = tnt;
+    dim3 grid(static_cast<unsigned>(tiles), c_out / (32 * nt));
+#define QNN_TILE(NTV, F32) \
+  hipLaunchKernelGGL((conv_fwd_tile_kernel<NTV, F32>), grid, dim3(256), 0, st, H, W, TW, x, c_in, w, bias, act, y, y_ld, c_store)
+    if (nt == 4) { if (y_fp32) QNN_TILE(4, true); else QNN_TILE(4, false); }
+    else if (nt == 2) { if (y_fp32) QNN_TILE(2, true); else QNN_TILE(2, false); }
+    else { if (y_fp32) QNN_TILE(1, true); else QNN_TILE(1, false); }
+#undef QNN_TILE
+    return launched("conv3x3_fwd");
+  }
   const int nt = (c_out % 64 == 0) ? 2 : 1;
   dim3 grid((P + 127) / 128, c_out / (32 * nt));
   if (nt == 2) {

@@ -33,7 +33,11 @@ def rnd(seed, shape, scale=1.0):
 
 
 @pytest.mark.parametrize("B,H,W,ci,co", [(2, 16, 32, 16, 32), (1, 8, 24, 32, 64), (2, 6, 10, 64, 128),
-                                         (1, 2, 2, 128, 128), (3, 5, 7, 16, 96)])
+                                         (1, 2, 2, 128, 128), (3, 5, 7, 16, 96),
+                                         # tiled kernel (W % 16 == 0, >= 512 tiles x channel
+                                         # groups): partial last tiles, NT = 1, 2, 4
+                                         (64, 15, 64, 48, 32), (600, 7, 16, 32, 128), (2, 256, 128, 128, 128),
+                                         (512, 3, 32, 64, 64), (600, 1, 16, 16, 32), (2, 168, 192, 32, 96)])
 @pytest.mark.parametrize("act", [0, 1])
 def test_conv_forward(env, B, H, W, ci, co, act):
     torch, qnn = env

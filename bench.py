@@ -203,12 +203,13 @@ def time_polarised(make_sim, stream, sites: int, steps: int, warmup: int, traffi
 def sweep_workload(args) -> dict:
     """Surrogate-accelerated sweep against plain QLA on the same GPU.
 
-    Trains the U-net surrogate on QLA runs the library generates (1024 runs
-    at 256 x 256, snapshots every K = 256 steps), judges it on 128 held-out
+    Trains the U-net surrogate on QLA runs the library generates (2048 runs
+    at 256 x 256, snapshots every K = 256 steps), judges it on 256 held-out
     runs, then advances --sweep-lattices lattices of 1024 x 1024 (the
-    batched scene family) by --steps steps three ways: plain QLA; the sweep
+    batched scene family) by --steps steps four ways: plain QLA; the sweep
     with QLA checks at the first and every 4th jump and fallback at a 1e-3
-    relative field or energy error; and surrogate jumps with no checks.
+    relative field or energy error; the same with a 0.25 tolerance (which
+    this network passes); and surrogate jumps with no checks.
     value = plain QLA seconds / checked-sweep seconds, at the final field
     error the record states (max over lattices of |Q - Q_plain| / |Q_plain|)."""
     import torch
@@ -218,8 +219,8 @@ def sweep_workload(args) -> dict:
     torch.cuda.set_device(dev)
     K = 256
     t0 = time.perf_counter()
-    data = S.generate(1024, seed=11, L=256, K=K, snaps=9)
-    held = S.generate(128, seed=999, L=256, K=K, snaps=9)
+    data = S.generate(2048, seed=11, L=256, K=K, snaps=9)
+    held = S.generate(256, seed=999, L=256, K=K, snaps=9)
     gen_s = time.perf_counter() - t0
     net = S.UNet(seed=0)
     t0 = time.perf_counter()
@@ -260,6 +261,7 @@ def sweep_workload(args) -> dict:
                    for a, b in zip(finals, plain))
 
     chk, chk_f = S.sweep(net, ns, qs, delta, steps, K=K, check_every=4, tol=1e-3)
+    loose, loose_f = S.sweep(net, ns, qs, delta, steps, K=K, check_every=4, tol=0.25)
     free, free_f = S.sweep(net, ns, qs, delta, steps, K=K, check_every=0)
     return {
         "metric": "surrogate vs plain QLA speedup at stated field error",
@@ -281,10 +283,14 @@ def sweep_workload(args) -> dict:
         "checked_sweep": {"seconds": chk.seconds, "jumps": chk.jumps, "unchecked": chk.unchecked,
                           "checks": chk.checks, "rejected": chk.rejected, "fell_back": chk.fell_back,
                           "max_check_error": chk.max_check_error, "max_check_energy": chk.max_check_energy},
+        "loose_checked_sweep": {"tolerance": 0.25, "seconds": loose.seconds, "speedup": plain_s / loose.seconds,
+                                "jumps": loose.jumps, "checks": loose.checks, "rejected": loose.rejected,
+                                "fell_back": loose.fell_back, "max_check_error": loose.max_check_error,
+                                "final_field_error": field_err(loose_f)},
         "unchecked_sweep": {"seconds": free.seconds, "speedup": plain_s / free.seconds,
                             "jumps": free.jumps, "final_field_error": field_err(free_f)},
         "plain_qla": {"seconds": plain_s, "site_updates_per_s": B * L * L * steps / plain_s},
-        "network": {"train_runs": 1024, "train_steps": args.train_steps, "train_seconds": train_s,
+        "network": {"train_runs": 2048, "train_steps": args.train_steps, "train_seconds": train_s,
                     "data_seconds": gen_s, "heldout_median_error": float(np.median(err)),
                     "heldout_p90_error": float(np.percentile(err, 90)),
                     "macs_per_pixel": S.macs_per_pixel(),
@@ -301,7 +307,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="cylinder_4096",
                     choices=["cylinder_4096", "single_256", "batch_64", "sweep"])
-    ap.add_argument("--train-steps", type=int, default=3000, help="sweep workload: network training steps")
+    ap.add_argument("--train-steps", type=int, default=5000, help="sweep workload: network training steps")
     ap.add_argument("--sweep-lattices", type=int, default=16, help="sweep workload: lattices of 1024 x 1024")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",

@@ -311,6 +311,23 @@ __device__ __forceinline__ void load_n(const StepArgs& g, const float* row, cons
     if (O::nlive(c)) load_row<C, O::VEC>(row + c * g.plane, g.nx, xo, nld[c]);
 }
 
+// Where a pipeline's row coefficients (Eq. (24), (25)) come from.
+enum { kCoefCompute = 0, kCoefExport = 1, kCoefImport = 2 };
+
+// LDS rows through which a two-step pair shares row coefficients: cy holds,
+// per column, the collision (tan(theta/2), sin theta) of n_x and n_z and the
+// V_Y pairs of beta_1, beta_3 (8 rows); cx the collision pair of n_y and the
+// V_X pairs of beta_0, beta_2 (6 rows); fy, fx the wave-uniform flags that say
+// whether the row has any index difference.
+template <int C>
+struct CoefIO {
+  float (*cy)[kWave * C];
+  float (*cx)[kWave * C];
+  int* fy;
+  int* fx;
+  int lane;
+};
+
 // One row iteration of a y pipeline: the whole step of Eq. (23)/(28) on
 // the ingested row R (p.q) for the x sweep, and on the rows in flight for
 // the y sweep; the row at lag 4 leaves the pipeline fully stepped. With
@@ -319,13 +336,18 @@ __device__ __forceinline__ void load_n(const StepArgs& g, const float* row, cons
 // segment. LAG0 is the iteration at which this pipeline ingests the first
 // row of the segment (4 for a pipeline fed from memory, 12 for the second
 // stage of a two-step pass), so that rows map to iterations as
-// R = y0 + i - LAG0 (marching in +y).
-template <int C, class O, int DIR, int SLOT, bool EMIT, int LAG0>
+// R = y0 + i - LAG0 (marching in +y). CMODE: kCoefCompute computes the
+// coefficients of row R from the n window; kCoefExport also writes the
+// collision pair of n_y and the V_X pairs of row R to io.cx / io.fx as soon
+// as they are known; kCoefImport reads every coefficient of row R from io
+// (the n window is then not used).
+template <int C, class O, int DIR, int SLOT, bool EMIT, int LAG0, int CMODE>
 __device__ __forceinline__ void process_row(Pipe<C>& p, const StepArgs& g, const uint32_t (&so)[C],
                                             bool edge_lane, int i, int seg_h, int y0,
-                                            float (&emit)[6][C]) {
+                                            float (&emit)[6][C], const CoefIO<C>& io) {
   constexpr bool VEC = O::VEC, WIDE = O::WIDE, POT = O::POT, TE = O::TE, TM = O::TM;
   constexpr int MODE = O::MODE;
+  constexpr bool IMPORT = CMODE == kCoefImport;
 
   // ---- coefficients of row R (Eq. (24), (25)) -----------------------------
   float u[3][C];
@@ -335,8 +357,19 @@ __device__ __forceinline__ void process_row(Pipe<C>& p, const StepArgs& g, const
     if (!O::nlive(c)) continue;
 #pragma unroll
     for (int k = 0; k < C; ++k) {
-      u[c][k] = __builtin_amdgcn_rcpf(p.ncur[c][k]);
-      rot_coef<WIDE>(g.a4 * u[c][k], tc[c][k], sc[c][k]);
+      if constexpr (IMPORT) {
+        const int x = io.lane * C + k;
+        if (c == 1) {
+          tc[c][k] = io.cx[0][x];
+          sc[c][k] = io.cx[1][x];
+        } else {
+          tc[c][k] = io.cy[c][x];          // rows 0, 1 for n_x; 2, 3 for n_z
+          sc[c][k] = io.cy[c + 1][x];
+        }
+      } else {
+        u[c][k] = __builtin_amdgcn_rcpf(p.ncur[c][k]);
+        rot_coef<WIDE>(g.a4 * u[c][k], tc[c][k], sc[c][k]);
+      }
     }
   }
   // V_X coefficients from the x-differences of n_y (beta_0) and n_z (beta_2).
@@ -344,7 +377,22 @@ __device__ __forceinline__ void process_row(Pipe<C>& p, const StepArgs& g, const
   // values only reach halo columns, so they do not vote.
   float vx00[C], vx01[C], vx20[C], vx21[C];
   bool fx = false;
-  if constexpr (POT) {
+  if constexpr (POT && IMPORT) {
+    fx = *io.fx != 0;
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+      const int x = io.lane * C + k;
+      vx00[k] = vx01[k] = vx20[k] = vx21[k] = 0.0f;
+      if constexpr (TE) {
+        vx00[k] = io.cx[2][x];
+        vx01[k] = io.cx[3][x];
+      }
+      if constexpr (TM) {
+        vx20[k] = io.cx[4][x];
+        vx21[k] = io.cx[5][x];
+      }
+    }
+  } else if constexpr (POT) {
     float dny[C], dnz[C];
     bool nz = false;
 #pragma unroll
@@ -383,6 +431,25 @@ __device__ __forceinline__ void process_row(Pipe<C>& p, const StepArgs& g, const
         if constexpr (TM) vcoef<O>(g.kb * dnz[k] * (u[2][k] * u[2][k]), vx20[k], vx21[k]);
       }
     }
+  }
+  if constexpr (CMODE == kCoefExport) {
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+      const int x = io.lane * C + k;
+      if constexpr (TE) {
+        io.cx[0][x] = tc[1][k];
+        io.cx[1][x] = sc[1][k];
+        if constexpr (POT) {
+          io.cx[2][x] = vx00[k];
+          io.cx[3][x] = vx01[k];
+        }
+      }
+      if constexpr (TM && POT) {
+        io.cx[4][x] = vx20[k];
+        io.cx[5][x] = vx21[k];
+      }
+    }
+    if (io.lane == 0) *io.fx = fx ? 1 : 0;
   }
 
   // ---- U_X (Eq. (18)) with V_X' interleaved (Eq. (28)) on row R ------------
@@ -622,7 +689,15 @@ __device__ __forceinline__ void process_row(Pipe<C>& p, const StepArgs& g, const
       }
     }
   }
-  if constexpr (POT) {
+  if constexpr (POT && IMPORT) {
+    p.fy[SLOT] = *io.fy != 0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      if ((c < 2 && !TE) || (c >= 2 && !TM)) continue;
+#pragma unroll
+      for (int k = 0; k < C; ++k) p.vy[SLOT][c][k] = io.cy[4 + c][io.lane * C + k];
+    }
+  } else if constexpr (POT) {
     // V_Y coefficients of row R from the y-differences n(R+1) - n(R-1) of
     // n_x (beta_1) and n_z (beta_3)
     float d1[C], d3[C];
@@ -766,13 +841,14 @@ __device__ __forceinline__ void march(const StepArgs& g, const uint32_t (&xo)[C]
   int rn = wrap_index(R0 + 3 * DIR, g.ny);
   const int iters = ((seg_h + 8) + 3) & ~3;
   float unused[6][C];
+  const CoefIO<C> io{nullptr, nullptr, nullptr, nullptr, 0};
   for (int i = 0; i < iters; i += 4) {
 #define QLA_ITER(S)                                                                            \
   {                                                                                            \
     float qld[6][C], nld[3][C];                                                                \
     load_q<C, O>(g, g.qin + rq * nx64, xo, qld);                                               \
     load_n<C, O>(g, g.n + rn * nx64, xo, nld);                                                 \
-    process_row<C, O, DIR, S, false, 4>(p, g, so, edge_lane, i + S, seg_h, y0, unused);        \
+    process_row<C, O, DIR, S, false, 4, kCoefCompute>(p, g, so, edge_lane, i + S, seg_h, y0, unused, io); \
     advance<C, O, true>(p, qld, nld);                                                          \
     rq = next_row<DIR>(rq, g.ny);                                                              \
     rn = next_row<DIR>(rn, g.ny);                                                              \
@@ -795,24 +871,32 @@ __device__ __forceinline__ void march(const StepArgs& g, const uint32_t (&xo)[C]
 // producer emits, 4 rows behind and one iteration later. Rows the producer
 // cannot produce exactly (its first 8 and last 8 iterations, and the outer
 // 8 columns of the strip) only ever reach halo rows and columns of the
-// consumer, which are not stored. The index rows the consumer needs are the
-// producer's, three iterations later, so they travel through the ring too:
-// n crosses HBM once per launch as well.
+// consumer, which are not stored.
+//
+// The consumer's rows are the producer's rows of four iterations earlier,
+// with the same index values, so it takes their coefficients from the
+// producer instead of recomputing them (and never reads n): the collision
+// coefficients of n_x and n_z and the V_Y coefficients come from the
+// producer's own four-row rings, sent when they are four rows old; those of
+// n_y and the V_X coefficients, which the producer keeps for one row only,
+// are sent at once through a six-slot ring and read four iterations later.
 template <int C>
 struct Ring {
-  float q[2][6][kWave * C];   // the emitted row
-  float n[2][3][kWave * C];   // the producer's current index row
+  float q[2][6][kWave * C];    // the emitted row
+  float cy[2][8][kWave * C];   // its collision (n_x, n_z) and V_Y coefficients
+  float cx[6][6][kWave * C];   // collision (n_y) and V_X coefficients, by row
+  int fy[2];
+  int fx[6];
 };
 
 template <int C, class O, int DIR>
 __device__ __forceinline__ void march2(const StepArgs& g, const uint32_t (&xo)[C],
                                        const uint32_t (&so)[C], bool edge_lane, int y0, int seg_h,
                                        bool producer, int lane, Ring<C>& ring) {
-  constexpr bool VEC = O::VEC;
+  constexpr bool VEC = O::VEC, TE = O::TE, TM = O::TM, POT = O::POT;
   Pipe<C> p;
   pipe_clear(p);
   const int64_t RA = DIR > 0 ? static_cast<int64_t>(y0) - 8 : static_cast<int64_t>(y0) + seg_h + 7;
-  const int64_t RB = RA - 4 * DIR;
   const int64_t nx64 = g.nx;
   const int iters = ((seg_h + 16) + 3) & ~3;
   float unused[6][C];
@@ -830,25 +914,47 @@ __device__ __forceinline__ void march2(const StepArgs& g, const uint32_t (&xo)[C
     }
     int rq = wrap_index(RA + 2 * DIR, g.ny);
     int rn = wrap_index(RA + 3 * DIR, g.ny);
+    int r6 = 0;   // iteration mod 6
     for (int i = 0; i < iters; i += 4) {
 #define QLA_ITER_A(S)                                                                          \
   {                                                                                            \
     float qld[6][C], nld[3][C], e[6][C];                                                       \
     load_q<C, O>(g, g.qin + rq * nx64, xo, qld);                                               \
     load_n<C, O>(g, g.n + rn * nx64, xo, nld);                                                 \
-    process_row<C, O, DIR, S, true, 8>(p, g, so, edge_lane, i + S, seg_h, y0, e);              \
+    /* the ring entries of slot S hold the row four iterations old: the row */                \
+    /* the consumer takes in this iteration */                                                 \
+    _Pragma("unroll") for (int k = 0; k < C; ++k) {                                            \
+      const int x = lane * C + k;                                                              \
+      if constexpr (TE) {                                                                      \
+        ring.cy[(S) & 1][0][x] = p.th[S][0][k];                                                \
+        ring.cy[(S) & 1][1][x] = p.th[S][1][k];                                                \
+        if constexpr (POT) {                                                                   \
+          ring.cy[(S) & 1][4][x] = p.vy[S][0][k];                                              \
+          ring.cy[(S) & 1][5][x] = p.vy[S][1][k];                                              \
+        }                                                                                      \
+      }                                                                                        \
+      if constexpr (TM) {                                                                      \
+        ring.cy[(S) & 1][2][x] = p.th[S][2][k];                                                \
+        ring.cy[(S) & 1][3][x] = p.th[S][3][k];                                                \
+        if constexpr (POT) {                                                                   \
+          ring.cy[(S) & 1][6][x] = p.vy[S][2][k];                                              \
+          ring.cy[(S) & 1][7][x] = p.vy[S][3][k];                                              \
+        }                                                                                      \
+      }                                                                                        \
+    }                                                                                          \
+    if (lane == 0) ring.fy[(S) & 1] = p.fy[S] ? 1 : 0;                                         \
+    {                                                                                          \
+      const CoefIO<C> io{ring.cy[(S) & 1], ring.cx[r6], &ring.fy[(S) & 1], &ring.fx[r6], lane}; \
+      process_row<C, O, DIR, S, true, 8, kCoefExport>(p, g, so, edge_lane, i + S, seg_h, y0, e, io); \
+    }                                                                                          \
     _Pragma("unroll") for (int c = 0; c < 6; ++c) {                                            \
       if (!O::live(c)) continue;                                                               \
       _Pragma("unroll") for (int k = 0; k < C; ++k) ring.q[(S) & 1][c][lane * C + k] = e[c][k]; \
     }                                                                                          \
-    _Pragma("unroll") for (int c = 0; c < 3; ++c) {                                            \
-      if (!O::nlive(c)) continue;                                                              \
-      _Pragma("unroll") for (int k = 0; k < C; ++k)                                            \
-        ring.n[(S) & 1][c][lane * C + k] = p.ncur[c][k];                                       \
-    }                                                                                          \
     advance<C, O, true>(p, qld, nld);                                                          \
     rq = next_row<DIR>(rq, g.ny);                                                              \
     rn = next_row<DIR>(rn, g.ny);                                                              \
+    r6 = r6 == 5 ? 0 : r6 + 1;                                                                 \
     __syncthreads();                                                                           \
   }
       QLA_ITER_A(0)
@@ -859,33 +965,29 @@ __device__ __forceinline__ void march2(const StepArgs& g, const uint32_t (&xo)[C
     }
     __syncthreads();     // the consumer's last row
   } else {
-    prime_n<C, O, DIR>(p, g, xo, RB);
-    // n of row RB+3*DIR, the first row the consumer's window takes in;
-    // later rows are the producer's current rows, one iteration old
-    float nbuf[3][C];
+    // slots the consumer reads before the producer has written them (its
+    // first four rows, which only reach halo rows) start at zero
+    for (int sl = 2; sl < 6; ++sl) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
+      for (int c = 0; c < 6; ++c)
 #pragma unroll
-      for (int k = 0; k < C; ++k) nbuf[c][k] = 1.0f;
-    load_n<C, O>(g, g.n + wrap_index(RB + 3 * DIR, g.ny) * nx64, xo, nbuf);
+        for (int k = 0; k < C; ++k) ring.cx[sl][c][lane * C + k] = 0.0f;
+      if (lane == 0) ring.fx[sl] = 0;
+    }
     __syncthreads();     // the producer's first row
+    int r6 = 2;          // (iteration - 4) mod 6
     for (int i = 0; i < iters; i += 4) {
 #define QLA_ITER_B(S)                                                                          \
   {                                                                                            \
-    float nld[3][C];                                                                           \
-    _Pragma("unroll") for (int c = 0; c < 3; ++c) {                                            \
-      if (!O::nlive(c)) continue;                                                              \
-      _Pragma("unroll") for (int k = 0; k < C; ++k) {                                          \
-        nld[c][k] = nbuf[c][k];                                                                \
-        nbuf[c][k] = ring.n[(S) & 1][c][lane * C + k];                                         \
-      }                                                                                        \
-    }                                                                                          \
     _Pragma("unroll") for (int c = 0; c < 6; ++c) {                                            \
       if (!O::live(c)) continue;                                                               \
       _Pragma("unroll") for (int k = 0; k < C; ++k) p.q[c][k] = ring.q[(S) & 1][c][lane * C + k]; \
     }                                                                                          \
-    process_row<C, O, DIR, S, false, 12>(p, g, so, edge_lane, i + S, seg_h, y0, unused);       \
-    advance<C, O, false>(p, unused, nld);                                                      \
+    {                                                                                          \
+      const CoefIO<C> io{ring.cy[(S) & 1], ring.cx[r6], &ring.fy[(S) & 1], &ring.fx[r6], lane}; \
+      process_row<C, O, DIR, S, false, 12, kCoefImport>(p, g, so, edge_lane, i + S, seg_h, y0, unused, io); \
+    }                                                                                          \
+    r6 = r6 == 5 ? 0 : r6 + 1;                                                                 \
     __syncthreads();                                                                           \
   }
       QLA_ITER_B(0)

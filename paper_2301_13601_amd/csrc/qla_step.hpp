@@ -321,11 +321,27 @@ enum { kCoefCompute = 0, kCoefExport = 1, kCoefImport = 2 };
 // whether the row has any index difference.
 template <int C>
 struct CoefIO {
-  float (*cy)[kWave * C];
-  float (*cx)[kWave * C];
+  float* cy;   // rows of kWave * C floats, numbered by RingMap::cy
+  float* cx;   // rows numbered by RingMap::cx
   int* fy;
   int* fx;
   int lane;
+};
+
+// Rows of the two-step LDS ring that a field triple uses, packed: the
+// emitted Q planes, and the cy / cx coefficient rows in the numbering above
+// (cy: 0, 1 collision n_x; 2, 3 collision n_z; 4, 5 V_Y beta_1; 6, 7 V_Y
+// beta_3. cx: 0, 1 collision n_y; 2, 3 V_X beta_0; 4, 5 V_X beta_2).
+template <class O>
+struct RingMap {
+  static constexpr int NQ = O::FIELDS == 0 ? 6 : 3;
+  static constexpr int NCY = O::FIELDS == 0 ? 8 : 4;
+  static constexpr int NCX = O::FIELDS == 0 ? 6 : (O::FIELDS == 2 ? 4 : 2);
+  static constexpr int q(int c) { return O::FIELDS == 0 ? c : (O::FIELDS == 1 ? c - 2 : (c == 5 ? 2 : c)); }
+  static constexpr int cy(int r) {
+    return O::FIELDS == 0 ? r : ((r & 3) - (O::FIELDS == 1 ? 2 : 0)) + (r >= 4 ? 2 : 0);
+  }
+  static constexpr int cx(int r) { return O::FIELDS == 1 ? r - 4 : r; }
 };
 
 // One row iteration of a y pipeline: the whole step of Eq. (23)/(28) on
@@ -360,11 +376,11 @@ __device__ __forceinline__ void process_row(Pipe<C>& p, const StepArgs& g, const
       if constexpr (IMPORT) {
         const int x = io.lane * C + k;
         if (c == 1) {
-          tc[c][k] = io.cx[0][x];
-          sc[c][k] = io.cx[1][x];
+          tc[c][k] = io.cx[RingMap<O>::cx(0) * (kWave * C) + x];
+          sc[c][k] = io.cx[RingMap<O>::cx(1) * (kWave * C) + x];
         } else {
-          tc[c][k] = io.cy[c][x];          // rows 0, 1 for n_x; 2, 3 for n_z
-          sc[c][k] = io.cy[c + 1][x];
+          tc[c][k] = io.cy[RingMap<O>::cy(c) * (kWave * C) + x];     // rows 0, 1 for n_x; 2, 3 for n_z
+          sc[c][k] = io.cy[RingMap<O>::cy(c + 1) * (kWave * C) + x];
         }
       } else {
         u[c][k] = __builtin_amdgcn_rcpf(p.ncur[c][k]);
@@ -384,12 +400,12 @@ __device__ __forceinline__ void process_row(Pipe<C>& p, const StepArgs& g, const
       const int x = io.lane * C + k;
       vx00[k] = vx01[k] = vx20[k] = vx21[k] = 0.0f;
       if constexpr (TE) {
-        vx00[k] = io.cx[2][x];
-        vx01[k] = io.cx[3][x];
+        vx00[k] = io.cx[RingMap<O>::cx(2) * (kWave * C) + x];
+        vx01[k] = io.cx[RingMap<O>::cx(3) * (kWave * C) + x];
       }
       if constexpr (TM) {
-        vx20[k] = io.cx[4][x];
-        vx21[k] = io.cx[5][x];
+        vx20[k] = io.cx[RingMap<O>::cx(4) * (kWave * C) + x];
+        vx21[k] = io.cx[RingMap<O>::cx(5) * (kWave * C) + x];
       }
     }
   } else if constexpr (POT) {
@@ -437,16 +453,16 @@ __device__ __forceinline__ void process_row(Pipe<C>& p, const StepArgs& g, const
     for (int k = 0; k < C; ++k) {
       const int x = io.lane * C + k;
       if constexpr (TE) {
-        io.cx[0][x] = tc[1][k];
-        io.cx[1][x] = sc[1][k];
+        io.cx[RingMap<O>::cx(0) * (kWave * C) + x] = tc[1][k];
+        io.cx[RingMap<O>::cx(1) * (kWave * C) + x] = sc[1][k];
         if constexpr (POT) {
-          io.cx[2][x] = vx00[k];
-          io.cx[3][x] = vx01[k];
+          io.cx[RingMap<O>::cx(2) * (kWave * C) + x] = vx00[k];
+          io.cx[RingMap<O>::cx(3) * (kWave * C) + x] = vx01[k];
         }
       }
       if constexpr (TM && POT) {
-        io.cx[4][x] = vx20[k];
-        io.cx[5][x] = vx21[k];
+        io.cx[RingMap<O>::cx(4) * (kWave * C) + x] = vx20[k];
+        io.cx[RingMap<O>::cx(5) * (kWave * C) + x] = vx21[k];
       }
     }
     if (io.lane == 0) *io.fx = fx ? 1 : 0;
@@ -695,7 +711,10 @@ __device__ __forceinline__ void process_row(Pipe<C>& p, const StepArgs& g, const
     for (int c = 0; c < 4; ++c) {
       if ((c < 2 && !TE) || (c >= 2 && !TM)) continue;
 #pragma unroll
-      for (int k = 0; k < C; ++k) p.vy[SLOT][c][k] = io.cy[4 + c][io.lane * C + k];
+      for (int k = 0; k < C; ++k) {
+        const int x = io.lane * C + k;
+        p.vy[SLOT][c][k] = io.cy[RingMap<O>::cy(4 + c) * (kWave * C) + x];
+      }
     }
   } else if constexpr (POT) {
     // V_Y coefficients of row R from the y-differences n(R+1) - n(R-1) of
@@ -880,11 +899,12 @@ __device__ __forceinline__ void march(const StepArgs& g, const uint32_t (&xo)[C]
 // producer's own four-row rings, sent when they are four rows old; those of
 // n_y and the V_X coefficients, which the producer keeps for one row only,
 // are sent at once through a six-slot ring and read four iterations later.
-template <int C>
+template <int C, class O>
 struct Ring {
-  float q[2][6][kWave * C];    // the emitted row
-  float cy[2][8][kWave * C];   // its collision (n_x, n_z) and V_Y coefficients
-  float cx[6][6][kWave * C];   // collision (n_y) and V_X coefficients, by row
+  using M = RingMap<O>;
+  float q[2][M::NQ][kWave * C];    // the emitted row (live planes)
+  float cy[2][M::NCY][kWave * C];  // its collision (n_x, n_z) and V_Y coefficients
+  float cx[6][M::NCX][kWave * C];  // collision (n_y) and V_X coefficients, by row
   int fy[2];
   int fx[6];
 };
@@ -892,7 +912,8 @@ struct Ring {
 template <int C, class O, int DIR>
 __device__ __forceinline__ void march2(const StepArgs& g, const uint32_t (&xo)[C],
                                        const uint32_t (&so)[C], bool edge_lane, int y0, int seg_h,
-                                       bool producer, int lane, Ring<C>& ring) {
+                                       bool producer, int lane, Ring<C, O>& ring) {
+  using M = RingMap<O>;
   constexpr bool VEC = O::VEC, TE = O::TE, TM = O::TM, POT = O::POT;
   Pipe<C> p;
   pipe_clear(p);
@@ -926,30 +947,30 @@ __device__ __forceinline__ void march2(const StepArgs& g, const uint32_t (&xo)[C
     _Pragma("unroll") for (int k = 0; k < C; ++k) {                                            \
       const int x = lane * C + k;                                                              \
       if constexpr (TE) {                                                                      \
-        ring.cy[(S) & 1][0][x] = p.th[S][0][k];                                                \
-        ring.cy[(S) & 1][1][x] = p.th[S][1][k];                                                \
+        ring.cy[(S) & 1][M::cy(0)][x] = p.th[S][0][k];                                                \
+        ring.cy[(S) & 1][M::cy(1)][x] = p.th[S][1][k];                                                \
         if constexpr (POT) {                                                                   \
-          ring.cy[(S) & 1][4][x] = p.vy[S][0][k];                                              \
-          ring.cy[(S) & 1][5][x] = p.vy[S][1][k];                                              \
+          ring.cy[(S) & 1][M::cy(4)][x] = p.vy[S][0][k];                                              \
+          ring.cy[(S) & 1][M::cy(5)][x] = p.vy[S][1][k];                                              \
         }                                                                                      \
       }                                                                                        \
       if constexpr (TM) {                                                                      \
-        ring.cy[(S) & 1][2][x] = p.th[S][2][k];                                                \
-        ring.cy[(S) & 1][3][x] = p.th[S][3][k];                                                \
+        ring.cy[(S) & 1][M::cy(2)][x] = p.th[S][2][k];                                                \
+        ring.cy[(S) & 1][M::cy(3)][x] = p.th[S][3][k];                                                \
         if constexpr (POT) {                                                                   \
-          ring.cy[(S) & 1][6][x] = p.vy[S][2][k];                                              \
-          ring.cy[(S) & 1][7][x] = p.vy[S][3][k];                                              \
+          ring.cy[(S) & 1][M::cy(6)][x] = p.vy[S][2][k];                                              \
+          ring.cy[(S) & 1][M::cy(7)][x] = p.vy[S][3][k];                                              \
         }                                                                                      \
       }                                                                                        \
     }                                                                                          \
     if (lane == 0) ring.fy[(S) & 1] = p.fy[S] ? 1 : 0;                                         \
     {                                                                                          \
-      const CoefIO<C> io{ring.cy[(S) & 1], ring.cx[r6], &ring.fy[(S) & 1], &ring.fx[r6], lane}; \
+      const CoefIO<C> io{&ring.cy[(S) & 1][0][0], &ring.cx[r6][0][0], &ring.fy[(S) & 1], &ring.fx[r6], lane}; \
       process_row<C, O, DIR, S, true, 8, kCoefExport>(p, g, so, edge_lane, i + S, seg_h, y0, e, io); \
     }                                                                                          \
     _Pragma("unroll") for (int c = 0; c < 6; ++c) {                                            \
       if (!O::live(c)) continue;                                                               \
-      _Pragma("unroll") for (int k = 0; k < C; ++k) ring.q[(S) & 1][c][lane * C + k] = e[c][k]; \
+      _Pragma("unroll") for (int k = 0; k < C; ++k) ring.q[(S) & 1][M::q(c)][lane * C + k] = e[c][k]; \
     }                                                                                          \
     advance<C, O, true>(p, qld, nld);                                                          \
     rq = next_row<DIR>(rq, g.ny);                                                              \
@@ -969,7 +990,7 @@ __device__ __forceinline__ void march2(const StepArgs& g, const uint32_t (&xo)[C
     // first four rows, which only reach halo rows) start at zero
     for (int sl = 2; sl < 6; ++sl) {
 #pragma unroll
-      for (int c = 0; c < 6; ++c)
+      for (int c = 0; c < M::NCX; ++c)
 #pragma unroll
         for (int k = 0; k < C; ++k) ring.cx[sl][c][lane * C + k] = 0.0f;
       if (lane == 0) ring.fx[sl] = 0;
@@ -981,10 +1002,10 @@ __device__ __forceinline__ void march2(const StepArgs& g, const uint32_t (&xo)[C
   {                                                                                            \
     _Pragma("unroll") for (int c = 0; c < 6; ++c) {                                            \
       if (!O::live(c)) continue;                                                               \
-      _Pragma("unroll") for (int k = 0; k < C; ++k) p.q[c][k] = ring.q[(S) & 1][c][lane * C + k]; \
+      _Pragma("unroll") for (int k = 0; k < C; ++k) p.q[c][k] = ring.q[(S) & 1][M::q(c)][lane * C + k]; \
     }                                                                                          \
     {                                                                                          \
-      const CoefIO<C> io{ring.cy[(S) & 1], ring.cx[r6], &ring.fy[(S) & 1], &ring.fx[r6], lane}; \
+      const CoefIO<C> io{&ring.cy[(S) & 1][0][0], &ring.cx[r6][0][0], &ring.fy[(S) & 1], &ring.fx[r6], lane}; \
       process_row<C, O, DIR, S, false, 12, kCoefImport>(p, g, so, edge_lane, i + S, seg_h, y0, unused, io); \
     }                                                                                          \
     r6 = r6 == 5 ? 0 : r6 + 1;                                                                 \
@@ -1084,7 +1105,7 @@ __global__ void __launch_bounds__(256) qla_step_kernel(BatchArgs ba) {
   // the start of both marches or at the end of both) and come from L2 for
   // the second reader.
   if constexpr (STEPS == 2) {
-    __shared__ Ring<C> ring;
+    __shared__ Ring<C, O> ring;
     const bool producer = wave == 0;
     if (seg & 1)
       march2<C, O, +1>(g, xo, so, edge_lane, y0, seg_h, producer, lane, ring);

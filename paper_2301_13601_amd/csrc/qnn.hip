@@ -342,6 +342,102 @@ __global__ void __launch_bounds__(256) wgrad_kernel(int P, int H, int W, const u
   }
 }
 
+// Weight gradient, staged: a block owns 32 output channels x 128 columns k
+// of dW (one 32 x 32 MFMA tile per wave) and a range of pixels, taken 64 at
+// a time. Each chunk of dy (64 pixels x 32 channels) and of the tap-shifted
+// inputs (64 pixels x 128 columns) is read from memory in 16-byte pieces
+// and written to LDS transposed (pixel index fastest), so that every MFMA
+// operand -- eight consecutive pixels of one channel or column -- is one
+// 16-byte LDS read. Needs 16-byte aligned x and dy.
+constexpr int kWgChunk = 64;                 // pixels per staged chunk
+constexpr int kWgStride = kWgChunk + 8;      // LDS row stride (elements), 16-byte multiple
+
+__global__ void __launch_bounds__(256) wgrad_lds_kernel(int P, int H, int W, const uint16_t* __restrict__ x,
+                                                        int cin, const uint16_t* __restrict__ dy, int cout,
+                                                        float* __restrict__ part, float* __restrict__ bpart) {
+  __shared__ __attribute__((aligned(16))) uint16_t dyT[32 * kWgStride];
+  __shared__ __attribute__((aligned(16))) uint16_t xT[128 * kWgStride];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int tid = threadIdx.x;
+  const int co0 = blockIdx.x * 32;
+  const int kb0 = blockIdx.y * 128;
+  const int split = blockIdx.z;
+  const int K = 9 * cin;
+  const int HW = H * W;
+  f32x16 acc;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+  float bsum = 0.0f;
+  const int pbeg = split * kWgradPixelsPerBlock;
+  const int pend = min(P, pbeg + kWgradPixelsPerBlock);
+  const int half = (lane >> 5) * 8;
+  for (int pc = pbeg; pc < pend; pc += kWgChunk) {
+    // dy chunk: thread -> (pixel, 8 channels)
+    {
+      const int px = tid >> 2, c8 = (tid & 3) * 8;
+      const int pp = pc + px;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (pp < pend) v = *reinterpret_cast<const uint4*>(dy + static_cast<int64_t>(pp) * cout + co0 + c8);
+      const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        dyT[(c8 + 2 * j) * kWgStride + px] = static_cast<uint16_t>(w4[j] & 0xffffu);
+        dyT[(c8 + 2 * j + 1) * kWgStride + px] = static_cast<uint16_t>(w4[j] >> 16);
+      }
+    }
+    // tap-shifted input chunk: unit -> (pixel, 8 columns k)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int u = tid + 256 * m;
+      const int px = u >> 4, kg = (u & 15) * 8;
+      const int k = kb0 + kg;
+      const int pp = pc + px;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (pp < pend && k < K) {
+        const int t = k / cin, ci = k - (k / cin) * cin;
+        const int b = pp / HW;
+        const int rem = pp - b * HW;
+        const int yy = rem / W, xx = rem - (rem / W) * W;
+        const int64_t src = static_cast<int64_t>(b) * HW + static_cast<int64_t>(wrapi(yy + t / 3 - 1, H)) * W +
+                            wrapi(xx + t % 3 - 1, W);
+        v = *reinterpret_cast<const uint4*>(x + src * cin + ci);
+      }
+      const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        xT[(kg + 2 * j) * kWgStride + px] = static_cast<uint16_t>(w4[j] & 0xffffu);
+        xT[(kg + 2 * j + 1) * kWgStride + px] = static_cast<uint16_t>(w4[j] >> 16);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < kWgChunk / 16; ++s) {
+      const bf16x8 a = *reinterpret_cast<const bf16x8*>(dyT + (lane & 31) * kWgStride + 16 * s + half);
+      const bf16x8 bb = *reinterpret_cast<const bf16x8*>(xT + (32 * wave + (lane & 31)) * kWgStride + 16 * s + half);
+      if (wave == 0) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) bsum += static_cast<float>(a[j]);
+      }
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bb, acc, 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  const int kcol = kb0 + 32 * wave + (lane & 31);
+  if (kcol < K) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);     // co within the tile
+      part[(static_cast<int64_t>(split) * cout + co0 + row) * K + kcol] = acc[r];
+    }
+  }
+  if (bpart && blockIdx.y == 0 && wave == 0) {
+    // lanes l and l + 32 hold the two pixel halves of channel l
+    const float tot = bsum + __shfl_xor(bsum, 32);
+    if (lane < 32) bpart[static_cast<int64_t>(split) * cout + co0 + lane] = tot;
+  }
+}
+
 __global__ void wgrad_reduce_kernel(const float* __restrict__ part, int nsplit, int64_t n,
                                     float* __restrict__ out) {
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
@@ -863,6 +959,9 @@ using namespace qnn;
 
 extern "C" {
 
+// the vector (16-byte) kernels need 16-byte alignment of every tensor
+static bool a16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
 int qnn_conv3x3_fwd(int32_t B, int32_t H, int32_t W, const uint16_t* x, int32_t c_in, const uint16_t* w,
                     const float* bias, int32_t c_out, int32_t act, void* y, int32_t y_fp32, int32_t y_ld,
                     int32_t c_store, void* hip_stream) {
@@ -929,19 +1028,18 @@ int qnn_conv3x3_wgrad(int32_t B, int32_t H, int32_t W, const uint16_t* x, int32_
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   float* part = work;
   float* bpart = work + static_cast<int64_t>(nsplit) * c_out * K;
-  dim3 grid(c_out / 32, (K + 31) / 32, nsplit);
-  if (W % 16 == 0)
-    hipLaunchKernelGGL((wgrad_kernel<true>), grid, dim3(256), 0, st, P, H, W, x, c_in, dy, c_out, part, dbias ? bpart : nullptr);
+  if (a16(x) && a16(dy)) {
+    dim3 g2(c_out / 32, (K + 127) / 128, nsplit);
+    hipLaunchKernelGGL(wgrad_lds_kernel, g2, dim3(256), 0, st, P, H, W, x, c_in, dy, c_out, part, dbias ? bpart : nullptr);
+  } else if (W % 16 == 0)
+    hipLaunchKernelGGL((wgrad_kernel<true>), dim3(c_out / 32, (K + 31) / 32, nsplit), dim3(256), 0, st, P, H, W, x, c_in, dy, c_out, part, dbias ? bpart : nullptr);
   else
-    hipLaunchKernelGGL((wgrad_kernel<false>), grid, dim3(256), 0, st, P, H, W, x, c_in, dy, c_out, part, dbias ? bpart : nullptr);
+    hipLaunchKernelGGL((wgrad_kernel<false>), dim3(c_out / 32, (K + 31) / 32, nsplit), dim3(256), 0, st, P, H, W, x, c_in, dy, c_out, part, dbias ? bpart : nullptr);
   const int64_t n = static_cast<int64_t>(c_out) * K;
   hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(grid_for(n)), dim3(256), 0, st, part, nsplit, n, dw);
   if (dbias) hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(grid_for(c_out)), dim3(256), 0, st, bpart, nsplit, static_cast<int64_t>(c_out), dbias);
   return launched("conv3x3_wgrad");
 }
-
-// the 8-channel vector kernels need 16-byte alignment of every tensor
-static bool a16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
 int qnn_leaky_bwd(int64_t n, const uint16_t* y, const uint16_t* dy, uint16_t* dz, void* hip_stream) {
   if (n < 0 || !y || !dy || !dz) return bad("leaky_bwd: bad size or null pointer");

@@ -35,13 +35,17 @@ enum { QNN_ACT_NONE = 0, QNN_ACT_LEAKY = 1 };   /* leaky ReLU, negative slope 1/
 
 /*
  * y = act(bias + conv3x3(x, w)), circular padding, on B images of H x W.
- *   x      BF16 [B*H*W][c_in], c_in a multiple of 16
- *   w      BF16 [c_out][9][c_in], c_out a multiple of 32
+ *   x      BF16 [B*H*W][c_in], c_in a multiple of 16, 16-byte aligned
+ *   w      BF16 [c_out][9][c_in], c_out a multiple of 32, 16-byte aligned
  *   bias   FP32 [c_out] or NULL
  *   y      [B*H*W][y_ld], BF16 (y_fp32 = 0) or FP32 (y_fp32 = 1); channels
  *          >= c_store are not written (c_store <= c_out, c_store <= y_ld)
  * MFMA (32x32x16 BF16) implicit GEMM: M = B*H*W pixels, N = c_out,
- * K = 9*c_in; FP32 accumulation.
+ * K = 9*c_in; FP32 accumulation, input channels summed 16 at a time in
+ * increasing order, the nine taps in order within each 16. B*H*W*max(c_in,
+ * y_ld) must stay below 2^31 (QNN_EINVAL otherwise). Fastest for W = 16,
+ * 32 or a multiple of 64 and, with BF16 output, c_store = c_out, y_ld a
+ * multiple of 8 and y 16-byte aligned.
  */
 int qnn_conv3x3_fwd(int32_t B, int32_t H, int32_t W, const uint16_t *x, int32_t c_in,
                     const uint16_t *w, const float *bias, int32_t c_out, int32_t act,

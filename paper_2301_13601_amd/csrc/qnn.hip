@@ -27,6 +27,7 @@ void set_error(const char* fmt, ...) __attribute__((format(printf, 1, 2)));
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr float kLeakySlope = 0.125f;
 
@@ -112,123 +113,250 @@ __global__ void __launch_bounds__(256) conv_fwd_kernel(int P, int H, int W, cons
 }
 
 // ---------------------------------------------------------------------------
-// Forward 3x3 circular convolution, tiled: a block computes a tile of 128
-// output pixels (TH rows x TW columns of one image, TW = min(W, 64)) for
-// 32*NT output channels. The input tile with its one-pixel halo is staged
-// in LDS 16 channels at a time (double-buffered, the next chunk's global
-// loads in flight during the current chunk's MFMAs), so each input value
-// crosses L2 once per tile instead of once per tap; the nine taps then read
-// their A operands from LDS, and one A operand feeds NT MFMAs.
+// Forward 3x3 circular convolution, persistent and software-pipelined. A
+// block loops over tiles of 128*MT output pixels (TH rows x TW columns of
+// one image, TW in {16, 32, 64}) for 32*NT output channels, taking the
+// input channels 16 at a time. Each step (tile, chunk) stages in LDS the
+// input tile with its one-pixel halo and the chunk's weights (9 taps x
+// 32*NT channels x 16), from registers loaded during the previous step's
+// MFMAs: apart from a block's first step no wave waits on memory, across
+// chunks and across tiles alike. A wave computes 32*MT pixels x 32*NT
+// channels; per tap it reads MT A and NT B operands from LDS (16 bytes a
+// lane, rows 48 bytes apart, which spreads 16 lanes over all banks) for
+// MT*NT MFMAs.
 // ---------------------------------------------------------------------------
-constexpr int kTilePix = 128;
-constexpr int kPixStride = 24;                       // LDS elements per staged pixel (16 + 8 pad)
-constexpr int kMaxStaged = (2 + 2) * (64 + 2);       // (TH + 2) * (TW + 2), largest for TW = 64
-constexpr int kLoadItems = (2 * kMaxStaged + 255) / 256;
+constexpr int kStageStride = 24;   // LDS elements per staged pixel or weight row (16 + 8 pad)
 
-template <int NT, bool OUT_FP32>
-__global__ void __launch_bounds__(256) conv_fwd_tile_kernel(int H, int W, int TW, const uint16_t* __restrict__ x,
-                                                            int cin, const uint16_t* __restrict__ w,
+template <int MT, int NT>
+struct PipeConv {
+  static constexpr int kPix = 128 * MT;
+  static constexpr int kBN = 32 * NT;
+  // staged pixels (TH + 2) * (TW + 2), largest over TW in {16, 32, 64}
+  static constexpr int kIn16 = (kPix / 16 + 2) * 18;
+  static constexpr int kIn32 = (kPix / 32 + 2) * 34;
+  static constexpr int kIn64 = (kPix / 64 + 2) * 66;
+  static constexpr int kMaxIn = kIn16 > kIn32 ? (kIn16 > kIn64 ? kIn16 : kIn64) : (kIn32 > kIn64 ? kIn32 : kIn64);
+  // 16-byte staging pieces per thread (pieces are dealt in groups of 16)
+  static constexpr int kInItems = (2 * ((kMaxIn + 7) / 8 * 8) + 255) / 256;
+  static constexpr int kWRows = 9 * kBN;
+  static constexpr int kWItems = (2 * ((kWRows + 7) / 8 * 8) + 255) / 256;
+  // output staging: per wave 32*MT pixels x (32*NT + 8) BF16 (16-byte rows)
+  static constexpr int kERow = 32 * NT + 8;
+  static constexpr int kStage = (kMaxIn + kWRows) * kStageStride;
+  static constexpr int kOut = 4 * 32 * MT * kERow;
+  static constexpr int kSmem = kStage > kOut ? kStage : kOut;
+};
+
+template <int MT, int NT, bool OUT_FP32>
+__global__ void __launch_bounds__(256) conv_fwd_pipe_kernel(int H, int W, int tw_shift, int tiles,
+                                                            const uint16_t* __restrict__ x, int cin,
+                                                            const uint16_t* __restrict__ w,
                                                             const float* __restrict__ bias, int act,
                                                             void* __restrict__ y, int y_ld, int c_store) {
-  __shared__ __attribute__((aligned(16))) uint16_t tile[2][kMaxStaged * kPixStride];
+  using PC = PipeConv<MT, NT>;
+  // staged input tile and weights; at the end of a tile, the waves' outputs
+  __shared__ __attribute__((aligned(16))) uint16_t smem[PC::kSmem];
+  uint16_t* const lin = smem;
+  uint16_t* const lw = smem + PC::kMaxIn * kStageStride;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int TH = kTilePix / TW;
-  const int tiles_x = W / TW;
-  const int tiles_y = (H + TH - 1) / TH;
-  int t = blockIdx.x;
-  const int tx0 = (t % tiles_x) * TW;
-  t /= tiles_x;
-  const int ty0 = (t % tiles_y) * TH;
-  const int b = t / tiles_y;
-  const int n0 = blockIdx.y * 32 * NT;
+  const int TW = 1 << tw_shift;
+  const int TH = PC::kPix >> tw_shift;
   const int TWp = TW + 2;
   const int nstaged = (TH + 2) * TWp;
-  // this lane's A row: tile pixel j
-  const int j = wave * 32 + (lane & 31);
-  const int py = j / TW, px = j - (j / TW) * TW;
-  const int kh = (lane >> 5) * 8;
+  const int tiles_x = W >> tw_shift;
+  const int tiles_y = (H + TH - 1) / TH;
+  const int n0 = blockIdx.y * PC::kBN;
   const int K = 9 * cin;
-  const uint16_t* wl[NT];
+  const int nchunks = cin >> 4;
+  const int kh = (lane >> 5) * 8;
+
+  // this thread's staging pieces, fixed for the whole kernel. Piece i is
+  // half (i / 8) % 2 (8 channels) of staged row 8 (i / 16) + i % 8, so that
+  // eight consecutive lanes write eight rows 48 bytes apart (all banks).
+  // Input rows are the staged pixels, packed as tile row << 16 | column << 1
+  // | half; weight rows are (output channel, tap) pairs, channel-major, the
+  // order of the weights in memory. A negative LDS offset marks a piece past
+  // the end.
+  int in_p[PC::kInItems], in_d[PC::kInItems];
 #pragma unroll
-  for (int jn = 0; jn < NT; ++jn) wl[jn] = w + static_cast<int64_t>(n0 + jn * 32 + (lane & 31)) * K + kh;
-  // staging items: (pixel, 8-channel half) pairs of the tile, 16 bytes
-  // each; thread i stages items i, i + 256 and i + 512 (named, so that they
-  // stay in registers)
-  static_assert(kLoadItems == 3, "three staging items per thread");
-  auto item = [&](int i, int64_t& src, int& dst) {
-    dst = -1;
-    src = 0;
-    if (i < 2 * nstaged) {
-      const int pi = i >> 1, half = i & 1;
-      const int r = pi / TWp, cc = pi - (pi / TWp) * TWp;
-      // periodic; rows of a partial last tile may lie several H past the end
-      const int yy = ((ty0 - 1 + r) % H + H) % H;
-      int xx = tx0 - 1 + cc;
-      xx = xx < 0 ? xx + W : (xx >= W ? xx - W : xx);
-      src = (static_cast<int64_t>(b) * H + yy) * W * cin + static_cast<int64_t>(xx) * cin + half * 8;
-      dst = pi * kPixStride + half * 8;
-    }
-  };
-  int64_t g0, g1, g2;
-  int l0, l1, l2;
-  item(threadIdx.x, g0, l0);
-  item(threadIdx.x + 256, g1, l1);
-  item(threadIdx.x + 512, g2, l2);
-  f32x16 acc[NT];
+  for (int k = 0; k < PC::kInItems; ++k) {
+    const int i = threadIdx.x + 256 * k;
+    const int pi = (i >> 4) * 8 + (i & 7), half = (i >> 3) & 1;
+    const int r = pi / TWp;
+    in_p[k] = (r << 16) | ((pi - r * TWp) << 1) | half;
+    in_d[k] = pi < nstaged ? pi * kStageStride + half * 8 : -1;
+  }
+  int w_s[PC::kWItems], w_d[PC::kWItems];
 #pragma unroll
-  for (int jn = 0; jn < NT; ++jn)
+  for (int k = 0; k < PC::kWItems; ++k) {
+    const int i = threadIdx.x + 256 * k;
+    const int row = (i >> 4) * 8 + (i & 7), half = (i >> 3) & 1;
+    const int co = row / 9, tap = row - co * 9;
+    w_d[k] = row < PC::kWRows ? row * kStageStride + half * 8 : -1;
+    w_s[k] = (n0 + co) * K + tap * cin + half * 8;
+  }
+  // this lane's A rows (tile pixels), as staged-tile offsets of tap (0, 0)
+  int a_off[MT];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) acc[jn][r] = 0.0f;
-  const int nchunks = cin / 16;
-  uint4 s0 = make_uint4(0, 0, 0, 0), s1 = s0, s2 = s0;
-  if (l0 >= 0) s0 = *reinterpret_cast<const uint4*>(x + g0);
-  if (l1 >= 0) s1 = *reinterpret_cast<const uint4*>(x + g1);
-  if (l2 >= 0) s2 = *reinterpret_cast<const uint4*>(x + g2);
-  for (int c = 0; c < nchunks; ++c) {
-    uint16_t* buf = tile[c & 1];
-    if (l0 >= 0) *reinterpret_cast<uint4*>(buf + l0) = s0;
-    if (l1 >= 0) *reinterpret_cast<uint4*>(buf + l1) = s1;
-    if (l2 >= 0) *reinterpret_cast<uint4*>(buf + l2) = s2;
+  for (int mt = 0; mt < MT; ++mt) {
+    const int j = (wave * MT + mt) * 32 + (lane & 31);
+    a_off[mt] = ((j >> tw_shift) * TWp + (j & (TW - 1))) * kStageStride + kh;
+  }
+  // this lane's B row: output channel lane % 32 of each 32-channel group
+  const int b_off = (lane & 31) * 9 * kStageStride + kh;
+
+  u32x4 sin[PC::kInItems], swt[PC::kWItems];
+#define QNN_PIPE_FETCH(T, CH)                                                                       \
+  {                                                                                                 \
+    const int tx0_ = ((T) % tiles_x) << tw_shift;                                                   \
+    const int t2_ = (T) / tiles_x;                                                                  \
+    const int ty0_ = (t2_ % tiles_y) * TH;                                                          \
+    const int img_ = (t2_ / tiles_y) * H;                                                           \
+    _Pragma("unroll") for (int k = 0; k < PC::kInItems; ++k) {                                      \
+      if (in_d[k] >= 0) {                                                                           \
+        /* periodic; rows of a partial last tile may lie more than H past the end */                \
+        int yy = ty0_ - 1 + (in_p[k] >> 16);                                                        \
+        yy = yy < 0 ? yy + H : (yy >= H ? (yy - H) % H : yy);                                       \
+        int xx = tx0_ - 1 + ((in_p[k] >> 1) & 0x7fff);                                              \
+        xx = xx < 0 ? xx + W : (xx >= W ? xx - W : xx);                                             \
+        /* element offsets fit 31 bits (checked on the host) */                                    \
+        const int src = ((img_ + yy) * W + xx) * cin + (CH) * 16 + (in_p[k] & 1) * 8;               \
+        sin[k] = *reinterpret_cast<const u32x4*>(x + src);                                          \
+      }                                                                                             \
+    }                                                                                               \
+    _Pragma("unroll") for (int k = 0; k < PC::kWItems; ++k) {                                       \
+      if (w_d[k] >= 0) swt[k] = *reinterpret_cast<const u32x4*>(w + w_s[k] + (CH) * 16);            \
+    }                                                                                               \
+  }
+
+  f32x16 acc[MT][NT];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int jn = 0; jn < NT; ++jn)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[mt][jn][r] = 0.0f;
+
+  const int my_tiles = (tiles - 1 - static_cast<int>(blockIdx.x)) / static_cast<int>(gridDim.x) + 1;
+  const int steps = my_tiles * nchunks;
+  int tile = blockIdx.x, chunk = 0;
+  QNN_PIPE_FETCH(tile, chunk)
+  for (int s = 0; s < steps; ++s) {
+    __syncthreads();      // every wave is done with the previous step's LDS
+#pragma unroll
+    for (int k = 0; k < PC::kInItems; ++k)
+      if (in_d[k] >= 0) *reinterpret_cast<u32x4*>(lin + in_d[k]) = sin[k];
+#pragma unroll
+    for (int k = 0; k < PC::kWItems; ++k)
+      if (w_d[k] >= 0) *reinterpret_cast<u32x4*>(lw + w_d[k]) = swt[k];
     __syncthreads();
-    if (c + 1 < nchunks) {
-      const int64_t o = (c + 1) * 16;
-      if (l0 >= 0) s0 = *reinterpret_cast<const uint4*>(x + g0 + o);
-      if (l1 >= 0) s1 = *reinterpret_cast<const uint4*>(x + g1 + o);
-      if (l2 >= 0) s2 = *reinterpret_cast<const uint4*>(x + g2 + o);
+    int ntile = tile, nchunk = chunk + 1;
+    if (nchunk == nchunks) {
+      nchunk = 0;
+      ntile += gridDim.x;
     }
+    if (s + 1 < steps) QNN_PIPE_FETCH(ntile, nchunk)
 #pragma unroll
     for (int tap = 0; tap < 9; ++tap) {
       const int dy = tap / 3, dx = tap % 3;   // offsets +1 into the staged tile
-      const bf16x8 a = *reinterpret_cast<const bf16x8*>(buf + ((py + dy) * TWp + (px + dx)) * kPixStride + kh);
+      bf16x8 a[MT], bv[NT];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+        a[mt] = *reinterpret_cast<const bf16x8*>(lin + a_off[mt] + (dy * TWp + dx) * kStageStride);
+#pragma unroll
+      for (int jn = 0; jn < NT; ++jn)
+        bv[jn] = *reinterpret_cast<const bf16x8*>(lw + (jn * 32 * 9 + tap) * kStageStride + b_off);
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int jn = 0; jn < NT; ++jn)
+          acc[mt][jn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[mt], bv[jn], acc[mt][jn], 0, 0, 0);
+    }
+    if (!OUT_FP32 && chunk == nchunks - 1) {
+      // BF16 output (every channel stored, 16-byte aligned rows): each wave
+      // writes its results to LDS as [pixel][channel] and stores 16 bytes
+      // (8 channels of one pixel) per lane
+      const int tx0 = (tile % tiles_x) << tw_shift;
+      const int t2 = tile / tiles_x;
+      const int ty0 = (t2 % tiles_y) * TH;
+      const int b = t2 / tiles_y;
+      __syncthreads();    // every wave is done with the staged operands
+      uint16_t* const E = smem + wave * (32 * MT) * PC::kERow;
 #pragma unroll
       for (int jn = 0; jn < NT; ++jn) {
-        const bf16x8 bv = *reinterpret_cast<const bf16x8*>(wl[jn] + tap * cin + c * 16);
-        acc[jn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bv, acc[jn], 0, 0, 0);
+        const int cl = jn * 32 + (lane & 31);
+        const float bsum = bias ? bias[n0 + cl] : 0.0f;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int m = mt * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
+            float v = acc[mt][jn][r] + bsum;
+            acc[mt][jn][r] = 0.0f;
+            if (act == QNN_ACT_LEAKY) v = v > 0.0f ? v : kLeakySlope * v;
+            E[m * PC::kERow + cl] = f2bf(v);
+          }
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < 2 * MT * NT; ++k) {
+        const int q = lane + 64 * k;
+        const int pm = q / (4 * NT), g = q % (4 * NT);
+        const int j = wave * 32 * MT + pm;
+        const int oy = ty0 + (j >> tw_shift);
+        if (oy < H) {
+          const int o = ((b * H + oy) * W + tx0 + (j & (TW - 1))) * y_ld + n0 + g * 8;
+          *reinterpret_cast<u32x4*>(static_cast<uint16_t*>(y) + o) =
+              *reinterpret_cast<const u32x4*>(E + pm * PC::kERow + g * 8);
+        }
+      }
+    } else if (OUT_FP32 && chunk == nchunks - 1) {
+      const int tx0 = (tile % tiles_x) << tw_shift;
+      const int t2 = tile / tiles_x;
+      const int ty0 = (t2 % tiles_y) * TH;
+      const int b = t2 / tiles_y;
+      // result r of a lane is tile pixel (wave * MT + mt) * 32 + m, m = 8 (r / 4)
+      // + 4 (lane / 32) + r % 4; the 16 pixels m < 16, and the 16 pixels
+      // m >= 16, lie contiguous in one image row (TW >= 16), so each half
+      // needs one (wave-uniform) row check and one base offset
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+#pragma unroll
+        for (int hf = 0; hf < 2; ++hf) {
+          const int j0 = (wave * MT + mt) * 32 + hf * 16;
+          const int oy = ty0 + (j0 >> tw_shift);
+          const int o0 = (b * H + oy) * W + tx0 + (j0 & (TW - 1)) + (lane >> 5) * 4;
+          const bool row_in = oy < H;
+#pragma unroll
+          for (int jn = 0; jn < NT; ++jn) {
+            const int col = n0 + jn * 32 + (lane & 31);
+            const bool live = row_in && col < c_store;
+            const float bsum = (bias && col < c_store) ? bias[col] : 0.0f;
+#pragma unroll
+            for (int rr = 0; rr < 8; ++rr) {
+              const int r = hf * 8 + rr;
+              float v = acc[mt][jn][r] + bsum;
+              acc[mt][jn][r] = 0.0f;
+              if (!live) continue;
+              if (act == QNN_ACT_LEAKY) v = v > 0.0f ? v : kLeakySlope * v;
+              // (r / 4) * 8 + r % 4 - 16 hf, for r = 8 hf + rr
+              const int o = (o0 + (rr >> 2) * 8 + (rr & 3)) * y_ld + col;
+              if constexpr (OUT_FP32)
+                static_cast<float*>(y)[o] = v;
+              else
+                static_cast<uint16_t*>(y)[o] = f2bf(v);
+            }
+          }
+        }
       }
     }
-  }
-#pragma unroll
-  for (int jn = 0; jn < NT; ++jn) {
-    const int col = n0 + jn * 32 + (lane & 31);
-    if (col >= c_store) continue;
-    const float bsum = bias ? bias[col] : 0.0f;
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int m = (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
-      const int jj = wave * 32 + m;
-      const int oy = ty0 + jj / TW, ox = tx0 + jj % TW;
-      if (oy >= H) continue;
-      const int64_t row = (static_cast<int64_t>(b) * H + oy) * W + ox;
-      float v = acc[jn][r] + bsum;
-      if (act == QNN_ACT_LEAKY) v = v > 0.0f ? v : kLeakySlope * v;
-      if constexpr (OUT_FP32)
-        static_cast<float*>(y)[row * y_ld + col] = v;
-      else
-        static_cast<uint16_t*>(y)[row * y_ld + col] = f2bf(v);
-    }
+    tile = ntile;
+    chunk = nchunk;
   }
 }
+#undef QNN_PIPE_FETCH
 
 __global__ void flip_kernel(const uint16_t* __restrict__ w, int cout, int cin, uint16_t* __restrict__ wt) {
   const int64_t n = static_cast<int64_t>(cout) * 9 * cin;
@@ -929,6 +1057,65 @@ __global__ void compare_final_kernel(int B, const double* __restrict__ work, dou
   en[b] = rr > 0.0 ? fabs(aa - rr) / rr : aa;
 }
 
+// Launch of the pipelined forward kernel: grid.y channel groups of 32*NT;
+// grid.x persistent blocks, as many as stay resident at once (times
+// `waves`, capped by the tile count).
+template <int MT, int NT>
+void conv_pipe_launch(int B, int H, int W, const uint16_t* x, int cin, const uint16_t* w, const float* bias,
+                      int act, void* y, bool y_fp32, int y_ld, int c_store, int c_out, float waves,
+                      hipStream_t st) {
+  static int resident_per_cu[2] = {0, 0};
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (cus < 1) cus = 1;
+  }
+  int& res = resident_per_cu[y_fp32 ? 1 : 0];
+  if (res == 0) {
+    int n = 0;
+    if (y_fp32) (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, conv_fwd_pipe_kernel<MT, NT, true>, 256, 0);
+    else (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, conv_fwd_pipe_kernel<MT, NT, false>, 256, 0);
+    res = n > 0 ? n : 1;
+  }
+  const int TW = W < 64 ? W : 64;
+  const int tws = TW == 64 ? 6 : (TW == 32 ? 5 : 4);
+  const int TH = PipeConv<MT, NT>::kPix / TW;
+  const int64_t tiles = static_cast<int64_t>(B) * (W / TW) * ((H + TH - 1) / TH);
+  const int gy = c_out / PipeConv<MT, NT>::kBN;
+  int64_t gx = static_cast<int64_t>(waves * cus * res / gy);
+  if (gx < 1) gx = 1;
+  if (gx > tiles) gx = tiles;
+  dim3 grid(static_cast<unsigned>(gx), gy);
+  if (y_fp32)
+    hipLaunchKernelGGL((conv_fwd_pipe_kernel<MT, NT, true>), grid, dim3(256), 0, st, H, W, tws, static_cast<int>(tiles),
+                       x, cin, w, bias, act, y, y_ld, c_store);
+  else
+    hipLaunchKernelGGL((conv_fwd_pipe_kernel<MT, NT, false>), grid, dim3(256), 0, st, H, W, tws, static_cast<int>(tiles),
+                       x, cin, w, bias, act, y, y_ld, c_store);
+}
+
+// the pipelined kernel's tiles: W a multiple of TW = min(W, 64) in {16, 32, 64}
+inline bool pipe_fits(int W) { return W % 16 == 0 && (W >= 64 ? W % 64 == 0 : (W == 16 || W == 32)); }
+
+bool conv_pipe(int mt, int nt, int B, int H, int W, const uint16_t* x, int cin, const uint16_t* w,
+               const float* bias, int act, void* y, bool y_fp32, int y_ld, int c_store, int c_out, float waves,
+               hipStream_t st) {
+  if (!pipe_fits(W) || c_out % (32 * nt)) return false;
+  // BF16 results leave in 16-byte pieces: every channel stored, whole
+  // 8-channel groups per row, 16-byte aligned rows
+  if (!y_fp32 && (c_store != c_out || y_ld % 8 || (reinterpret_cast<uintptr_t>(y) & 15))) return false;
+#define QNN_PIPE(M, N)                                                                                   \
+  if (mt == M && nt == N) {                                                                              \
+    conv_pipe_launch<M, N>(B, H, W, x, cin, w, bias, act, y, y_fp32, y_ld, c_store, c_out, waves, st); \
+    return true;                                                                                         \
+  }
+  QNN_PIPE(1, 1) QNN_PIPE(1, 2) QNN_PIPE(2, 1) QNN_PIPE(2, 2)
+#undef QNN_PIPE
+  return false;
+}
+
 __global__ void to_bf16_kernel(int64_t n, const float* __restrict__ x, uint16_t* __restrict__ y) {
   QNN_GRID_STRIDE(i, n) { y[i] = f2bf(x[i]); }
 }
@@ -969,27 +1156,27 @@ int qnn_conv3x3_fwd(int32_t B, int32_t H, int32_t W, const uint16_t* x, int32_t 
   if (c_in < 16 || c_in % 16 || c_out < 32 || c_out % 32) return bad("conv3x3_fwd: c_in % 16, c_out % 32");
   if (c_store < 1 || c_store > c_out || y_ld < c_store) return bad("conv3x3_fwd: bad c_store / y_ld");
   if (act != QNN_ACT_NONE && act != QNN_ACT_LEAKY) return bad("conv3x3_fwd: unknown activation");
+  if (!a16(x) || !a16(w)) return bad("conv3x3_fwd: x and w must be 16-byte aligned");
   const int64_t P64 = static_cast<int64_t>(B) * H * W;
   if (P64 * (c_in > y_ld ? c_in : y_ld) >= (int64_t{1} << 31)) return bad("conv3x3_fwd: tensor too large");
   const int P = static_cast<int>(P64);
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  const int TW = W < 64 ? W : 64;
-  const int TH = kTilePix / TW;
-  const int64_t tiles = static_cast<int64_t>(B) * (W / TW) * ((H + TH - 1) / TH);
-  const int tnt = (c_out % 128 == 0) ? 4 : (c_out % 64 == 0) ? 2 : 1;
-  // the tiled kernel needs W in whole 16/32/64-column tiles, and enough
-  // tiles to fill the chip (two blocks per CU); small layers use the
-  // pixel-list kernel below, which splits the channels finer
-  if (W % 16 == 0 && W % TW == 0 && kTilePix % TW == 0 && tiles * (c_out / (32 * tnt)) >= 512) {
-    const int nt = tnt;
-    dim3 grid(static_cast<unsigned>(tiles), c_out / (32 * nt));
-#define QNN_TILE(NTV, F32) \
-  hipLaunchKernelGGL((conv_fwd_tile_kernel<NTV, F32>), grid, dim3(256), 0, st, H, W, TW, x, c_in, w, bias, act, y, y_ld, c_store)
-    if (nt == 4) { if (y_fp32) QNN_TILE(4, true); else QNN_TILE(4, false); }
-    else if (nt == 2) { if (y_fp32) QNN_TILE(2, true); else QNN_TILE(2, false); }
-    else { if (y_fp32) QNN_TILE(1, true); else QNN_TILE(1, false); }
-#undef QNN_TILE
-    return launched("conv3x3_fwd");
+  // The pipelined kernel, where the tiles fit: 256-pixel tiles x 64
+  // channels when that gives two or more blocks per CU, else 128-pixel
+  // tiles; the layers with the fewest pixels split the channels finest.
+  // Otherwise the pixel-list kernel below.
+  if (pipe_fits(W)) {
+    const int TW = W < 64 ? W : 64;
+    auto blocks = [&](int mt, int nt) {
+      const int TH = 128 * mt / TW;
+      return static_cast<int64_t>(B) * (W / TW) * ((H + TH - 1) / TH) * (c_out / (32 * nt));
+    };
+    const int nt = (c_out % 64 == 0) ? 2 : 1;
+    int m = 1, n = 1;
+    if (blocks(2, nt) >= 512) m = 2, n = nt;
+    else if (blocks(1, nt) >= 256) n = nt;
+    if (conv_pipe(m, n, B, H, W, x, c_in, w, bias, act, y, y_fp32 != 0, y_ld, c_store, c_out, 1.0f, st))
+      return launched("conv3x3_fwd");
   }
   const int nt = (c_out % 64 == 0) ? 2 : 1;
   dim3 grid((P + 127) / 128, c_out / (32 * nt));
@@ -1002,6 +1189,18 @@ int qnn_conv3x3_fwd(int32_t B, int32_t H, int32_t W, const uint16_t* x, int32_t 
   }
   return launched("conv3x3_fwd");
 }
+
+#ifdef QNN_TUNE_HOOK
+// geometry sweeps only (not part of the library's interface)
+int qnn_conv3x3_fwd_cfg(int32_t B, int32_t H, int32_t W, const uint16_t* x, int32_t c_in, const uint16_t* w,
+                        const float* bias, int32_t c_out, int32_t act, void* y, int32_t y_fp32, int32_t y_ld,
+                        int32_t c_store, int32_t mt, int32_t nt, float waves, void* hip_stream) {
+  if (!conv_pipe(mt, nt, B, H, W, x, c_in, w, bias, act, y, y_fp32 != 0, y_ld, c_store, c_out, waves,
+                 static_cast<hipStream_t>(hip_stream)))
+    return bad("conv3x3_fwd_cfg: geometry not supported");
+  return launched("conv3x3_fwd_cfg");
+}
+#endif
 
 int qnn_conv3x3_flip(const uint16_t* w, int32_t c_out, int32_t c_in, uint16_t* wt, void* hip_stream) {
   if (!w || !wt || c_out < 1 || c_in < 1) return bad("conv3x3_flip: bad size or null pointer");

@@ -101,3 +101,13 @@ def test_calls_on_a_null_context_report_state_errors(qla):
     assert L.qla_energy(None, ctypes.byref(d)) == qla.QLA_ESTATE
     assert L.qla_fields(None, None, 0, 1) == qla.QLA_ESTATE
     L.qla_free(None)   # safe
+
+
+def test_conv_rejects_misaligned_operands_without_a_device(qla):
+    L = ctypes.CDLL(qla.LIB_PATH)      # its own handle: argtypes set here stay here
+    conv = L.qnn_conv3x3_fwd
+    conv.argtypes = [ctypes.c_int32] * 3 + [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                            ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p] + [ctypes.c_int32] * 3 + [ctypes.c_void_p]
+    for x, w in [(0x1002, 0x2000), (0x1000, 0x2008)]:
+        assert conv(1, 16, 16, x, 16, w, None, 32, 0, 0x3000, 1, 32, 32, None) == -1
+        assert "aligned" in qla.qla_last_error()

@@ -34,10 +34,14 @@ def rnd(seed, shape, scale=1.0):
 
 @pytest.mark.parametrize("B,H,W,ci,co", [(2, 16, 32, 16, 32), (1, 8, 24, 32, 64), (2, 6, 10, 64, 128),
                                          (1, 2, 2, 128, 128), (3, 5, 7, 16, 96),
-                                         # tiled kernel (W % 16 == 0, >= 512 tiles x channel
-                                         # groups): partial last tiles, NT = 1, 2, 4
+                                         # pipelined kernel (W in {16, 32} or a multiple of 64):
+                                         # tiles taller than the image and partial last tiles,
+                                         # several tiles per block, 1 to 8 channel chunks, and
+                                         # the four tile shapes (128 or 256 pixels x 32 or 64
+                                         # channels)
                                          (64, 15, 64, 48, 32), (600, 7, 16, 32, 128), (2, 256, 128, 128, 128),
-                                         (512, 3, 32, 64, 64), (600, 1, 16, 16, 32), (2, 168, 192, 32, 96)])
+                                         (512, 3, 32, 64, 64), (600, 1, 16, 16, 32), (2, 168, 192, 32, 96),
+                                         (16, 32, 32, 128, 128), (3, 20, 64, 16, 64)])
 @pytest.mark.parametrize("act", [0, 1])
 def test_conv_forward(env, B, H, W, ci, co, act):
     torch, qnn = env
@@ -57,20 +61,28 @@ def test_conv_forward(env, B, H, W, ci, co, act):
     assert np.all(np.abs(gotb - ref) <= 2.0 ** -8 * np.abs(ref) + 1e-6)
 
 
-def test_conv_forward_partial_store(env):
+@pytest.mark.parametrize("W", [16, 24])
+def test_conv_forward_partial_store(env, W):
     torch, qnn = env
-    B, H, W, ci, co = 1, 8, 16, 32, 32
+    B, H, ci, co = 1, 8, 32, 32
     x, xr = bf(torch, rnd(4, (B, H, W, ci)))
     w, wr = bf(torch, rnd(5, (co, 9, ci), 0.1))
+    ref = N.conv3x3(xr, wr)
     y = torch.full((B, H, W, co), 7.0, dtype=torch.float32, device="cuda")
     qnn.qnn_conv3x3_fwd(B, H, W, x, ci, w, None, co, 0, y, 1, co, 6)
     got = y.cpu().numpy()
-    ref = N.conv3x3(xr, wr)
     assert np.abs(got[..., :6] - ref[..., :6]).max() <= 2e-6 * np.abs(ref).max()
     assert np.all(got[..., 6:] == 7.0)
+    # BF16 results for part of the channels, in rows of 8 (y_ld = 8)
+    yb = torch.full((B, H, W, 8), 7.0, dtype=torch.bfloat16, device="cuda")
+    qnn.qnn_conv3x3_fwd(B, H, W, x, ci, w, None, co, 0, yb, 0, 8, 6)
+    gotb = yb.float().cpu().numpy()
+    assert np.all(np.abs(gotb[..., :6] - ref[..., :6]) <= 2.0 ** -8 * np.abs(ref[..., :6]) + 1e-6)
+    assert np.all(gotb[..., 6:] == 7.0)
 
 
-@pytest.mark.parametrize("B,H,W,ci,co", [(2, 16, 16, 16, 32), (1, 6, 10, 64, 32), (2, 2, 2, 128, 128)])
+@pytest.mark.parametrize("B,H,W,ci,co", [(2, 16, 16, 16, 32), (1, 6, 10, 64, 32), (2, 2, 2, 128, 128),
+                                         (4, 32, 64, 32, 64)])
 def test_conv_data_gradient(env, B, H, W, ci, co):
     torch, qnn = env
     dy, dyr = bf(torch, rnd(6, (B, H, W, co)))

@@ -28,6 +28,8 @@ void set_error(const char* fmt, ...) __attribute__((format(printf, 1, 2)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
 constexpr float kLeakySlope = 0.125f;
 
@@ -170,6 +172,7 @@ __global__ void __launch_bounds__(256) conv_fwd_pipe_kernel(int H, int W, int tw
   const int K = 9 * cin;
   const int nchunks = cin >> 4;
   const int kh = (lane >> 5) * 8;
+  const bool tall = TH > H;    // rows of a tile may wrap more than once
 
   // this thread's staging pieces, fixed for the whole kernel. Piece i is
   // half (i / 8) % 2 (8 channels) of staged row 8 (i / 16) + i % 8, so that
@@ -215,9 +218,12 @@ __global__ void __launch_bounds__(256) conv_fwd_pipe_kernel(int H, int W, int tw
     const int img_ = (t2_ / tiles_y) * H;                                                           \
     _Pragma("unroll") for (int k = 0; k < PC::kInItems; ++k) {                                      \
       if (in_d[k] >= 0) {                                                                           \
-        /* periodic; rows of a partial last tile may lie more than H past the end */                \
+        /* periodic; with tiles taller than the image, rows may lie several H past the end */    \
         int yy = ty0_ - 1 + (in_p[k] >> 16);                                                        \
-        yy = yy < 0 ? yy + H : (yy >= H ? (yy - H) % H : yy);                                       \
+        if (tall)                                                                                   \
+          yy = (yy + H) % H;                                                                        \
+        else                                                                                        \
+          yy = yy < 0 ? yy + H : (yy >= H ? yy - H : yy);                                           \
         int xx = tx0_ - 1 + ((in_p[k] >> 1) & 0x7fff);                                              \
         xx = xx < 0 ? xx + W : (xx >= W ? xx - W : xx);                                             \
         /* element offsets fit 31 bits (checked on the host) */                                    \
@@ -283,6 +289,7 @@ __global__ void __launch_bounds__(256) conv_fwd_pipe_kernel(int H, int W, int tw
       const int b = t2 / tiles_y;
       __syncthreads();    // every wave is done with the staged operands
       uint16_t* const E = smem + wave * (32 * MT) * PC::kERow;
+      const bool leaky = act == QNN_ACT_LEAKY;
 #pragma unroll
       for (int jn = 0; jn < NT; ++jn) {
         const int cl = jn * 32 + (lane & 31);
@@ -290,12 +297,22 @@ __global__ void __launch_bounds__(256) conv_fwd_pipe_kernel(int H, int W, int tw
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
 #pragma unroll
-          for (int r = 0; r < 16; ++r) {
-            const int m = mt * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
-            float v = acc[mt][jn][r] + bsum;
+          for (int r = 0; r < 16; r += 2) {
+            const int m = mt * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);   // rows m, m + 1
+            f32x2 v = {acc[mt][jn][r] + bsum, acc[mt][jn][r + 1] + bsum};
             acc[mt][jn][r] = 0.0f;
-            if (act == QNN_ACT_LEAKY) v = v > 0.0f ? v : kLeakySlope * v;
-            E[m * PC::kERow + cl] = f2bf(v);
+            acc[mt][jn][r + 1] = 0.0f;
+            if (leaky) {
+              // the leaky ReLU as max(v, v / 8)
+              v[0] = fmaxf(v[0], kLeakySlope * v[0]);
+              v[1] = fmaxf(v[1], kLeakySlope * v[1]);
+            }
+            // round to nearest even (the hardware conversion); the pair is
+            // taken apart as one 32-bit word (indexing the BF16 vector
+            // itself miscompiles: the second element is lost)
+            const uint32_t pk = __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
+            E[m * PC::kERow + cl] = static_cast<uint16_t>(pk);
+            E[(m + 1) * PC::kERow + cl] = static_cast<uint16_t>(pk >> 16);
           }
         }
       }
@@ -836,54 +853,46 @@ __global__ void absmax_fix_kernel(int B, float* __restrict__ scale) {
 
 constexpr int kInCh = 48;
 
-// Input channel c of pixel (yy, xx) of sample b (see qnn_pack_input).
-__device__ inline float pack_value(int c, int b, int yy, int xx, int H, int W, int64_t HW, const float* __restrict__ q,
-                                   const int32_t* __restrict__ idx_q, const float* __restrict__ n,
-                                   const int32_t* __restrict__ idx_n, const float* __restrict__ scale,
-                                   float n_shift, float n_scale, int shift) {
-  const int64_t s = static_cast<int64_t>(yy) * W + xx;
-  const int64_t qs = idx_q ? idx_q[b] : b;
-  if (c < 6) return q[(qs * 6 + c) * HW + s] / scale[b];
-  if (c < 9) {
-    const int64_t ns = idx_n ? idx_n[b] : b;
-    return (n[(ns * 3 + (c - 6)) * HW + s] - n_shift) / n_scale;
-  }
-  if (c < 33) {
-    const int blk = (c - 9) / 6, cc = (c - 9) % 6;
-    int sy = yy, sx = xx;
-    if (blk == 0) sx = xx - shift;
-    else if (blk == 1) sx = xx + shift;
-    else if (blk == 2) sy = yy - shift;
-    else sy = yy + shift;
-    sx %= W;
-    if (sx < 0) sx += W;
-    sy %= H;
-    if (sy < 0) sy += H;
-    return q[(qs * 6 + cc) * HW + static_cast<int64_t>(sy) * W + sx] / scale[b];
-  }
-  return 0.0f;
-}
-
-// one thread per (pixel, 8-channel group): 16-byte stores of the NHWC input
+// One thread per pixel: its 48 input channels (see qnn_pack_input) as six
+// 16-byte stores. dx, dy: the displacement reduced to [0, W) and [0, H).
+// Element offsets within a sample's planes fit 31 bits (checked on the host).
 __global__ void pack_input_kernel(int B, int H, int W, const float* __restrict__ q, const int32_t* __restrict__ idx_q,
                                   const float* __restrict__ n, const int32_t* __restrict__ idx_n,
-                                  const float* __restrict__ scale, float n_shift, float n_scale, int shift,
+                                  const float* __restrict__ scale, float n_shift, float n_scale, int dx, int dy,
                                   uint16_t* __restrict__ x) {
-  const int64_t HW = static_cast<int64_t>(H) * W;
-  constexpr int G = kInCh / 8;
-  const int64_t total = B * HW * G;
-  QNN_GRID_STRIDE(i, total) {
-    const int g = static_cast<int>(i % G);
-    const int64_t p = i / G;
+  const int HW = H * W;
+  const int64_t total = static_cast<int64_t>(B) * HW;
+  QNN_GRID_STRIDE(p, total) {
     const int b = static_cast<int>(p / HW);
-    const int64_t s = p - b * HW;
-    const int yy = static_cast<int>(s / W);
-    const int xx = static_cast<int>(s - static_cast<int64_t>(yy) * W);
-    float v[8];
+    const int s = static_cast<int>(p - static_cast<int64_t>(b) * HW);
+    const int yy = s / W, xx = s - (s / W) * W;
+    const float* qb = q + static_cast<int64_t>(idx_q ? idx_q[b] : b) * 6 * HW;
+    const float* nb = n + static_cast<int64_t>(idx_n ? idx_n[b] : b) * 3 * HW;
+    const float sc = scale[b];
+    // the four displaced source pixels, periodic
+    const int xm = xx >= dx ? xx - dx : xx - dx + W;
+    const int xp = xx + dx < W ? xx + dx : xx + dx - W;
+    const int ym = yy >= dy ? yy - dy : yy - dy + H;
+    const int yp = yy + dy < H ? yy + dy : yy + dy - H;
+    const int src[4] = {yy * W + xm, yy * W + xp, ym * W + xx, yp * W + xx};
+    float v[kInCh];
 #pragma unroll
-    for (int j = 0; j < 8; ++j)
-      v[j] = pack_value(8 * g + j, b, yy, xx, H, W, HW, q, idx_q, n, idx_n, scale, n_shift, n_scale, shift);
-    st8(x + p * kInCh + 8 * g, v);
+    for (int c = 0; c < 6; ++c) v[c] = qb[c * HW + s] / sc;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) v[6 + c] = (nb[c * HW + s] - n_shift) / n_scale;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int c = 0; c < 6; ++c) v[9 + 6 * k + c] = qb[c * HW + src[k]] / sc;
+#pragma unroll
+    for (int c = 33; c < kInCh; ++c) v[c] = 0.0f;
+#pragma unroll
+    for (int g = 0; g < kInCh / 8; ++g) {
+      float f[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) f[j] = v[8 * g + j];
+      st8(x + p * kInCh + 8 * g, f);
+    }
   }
 }
 
@@ -1321,8 +1330,10 @@ int qnn_pack_input(int32_t B, int32_t H, int32_t W, const float* q, const int32_
                    uint16_t* x, void* hip_stream) {
   if (B < 1 || H < 1 || W < 1 || !q || !n || !scale || !x || !(n_scale != 0.0f)) return bad("pack_input: bad argument");
   if (!a16(x)) return bad("pack_input: x must be 16-byte aligned");
-  const int64_t total = static_cast<int64_t>(B) * H * W * (kInCh / 8);
-  hipLaunchKernelGGL(pack_input_kernel, dim3(grid_for(total)), dim3(256), 0, static_cast<hipStream_t>(hip_stream), B, H, W, q, idx_q, n, idx_n, scale, n_shift, n_scale, shift, x);
+  if (int64_t{6} * H * W >= (int64_t{1} << 31)) return bad("pack_input: lattice too large");
+  const int64_t total = static_cast<int64_t>(B) * H * W;
+  const int dx = (shift % W + W) % W, dy = (shift % H + H) % H;
+  hipLaunchKernelGGL(pack_input_kernel, dim3(grid_for(total)), dim3(256), 0, static_cast<hipStream_t>(hip_stream), B, H, W, q, idx_q, n, idx_n, scale, n_shift, n_scale, dx, dy, x);
   return launched("pack_input");
 }
 

@@ -38,6 +38,7 @@ BOTTLENECK = 4
 IN_CH = 48            # 6 field + 3 index + 4x6 displaced field channels, padded to 48
 LIVE_IN = 33          # channels that carry data
 OUT_CH = 32           # output conv width (6 stored)
+OUT_LD = 8            # row length of the FP32 network output (6 used)
 N_SHIFT, N_SCALE = 2.0, 1.0
 
 
@@ -162,7 +163,7 @@ class UNet:
         self.act["x"] = torch.empty(px(0) * IN_CH, **bf)
         for s in self.specs:
             if s.name == "out":
-                self.act["out"] = torch.empty(px(0) * OUT_CH, dtype=torch.float32, device=self.device)
+                self.act["out"] = torch.empty(px(0) * OUT_LD, dtype=torch.float32, device=self.device)
             else:
                 self.act[s.name] = torch.empty(px(s.level) * s.c_out, **bf)
         for l in range(1, 5):
@@ -193,7 +194,7 @@ class UNet:
         h, w = H >> s.level, W >> s.level
         y = self.act[s.name] if y is None else y
         if fp32:
-            qnn.qnn_conv3x3_fwd(B, h, w, x, s.c_in, self.w(s), self.b(s), s.c_out, s.act, y, 1, OUT_CH, 6,
+            qnn.qnn_conv3x3_fwd(B, h, w, x, s.c_in, self.w(s), self.b(s), s.c_out, s.act, y, 1, OUT_LD, 6,
                                 self.stream)
         else:
             qnn.qnn_conv3x3_fwd(B, h, w, x, s.c_in, self.w(s), self.b(s), s.c_out, s.act, y, 0, s.c_out,
@@ -201,7 +202,7 @@ class UNet:
         return y
 
     def forward_packed(self, B: int, H: int, W: int):
-        """Run the network on self.act["x"]; returns the FP32 output [P][32]."""
+        """Run the network on self.act["x"]; returns the FP32 output [P][8] (6 channels used)."""
         A, S = self.act, self.by_name
         st = self.stream
         x = A["x"]
@@ -241,7 +242,7 @@ class UNet:
             c1 = min(B, c0 + chunk)
             self.pack(c1 - c0, H, W, q[c0:c1], None, n[c0:c1], None)
             y = self.forward_packed(c1 - c0, H, W)
-            qnn.qnn_unpack_output(c1 - c0, H, W, y, OUT_CH, self.scale, out_q[c0:c1], self.stream)
+            qnn.qnn_unpack_output(c1 - c0, H, W, y, OUT_LD, self.scale, out_q[c0:c1], self.stream)
 
     # -- backward ----------------------------------------------------------------
     def _conv_bwd(self, s: Conv, x_in, dy, B, H, W, dx=None):
@@ -300,7 +301,7 @@ class UNet:
         target[idx_t]). The loss stays on the device in self.loss."""
         self.pack(B, H, W, q, idx_q, n, idx_n, train=True)
         y = self.forward_packed(B, H, W)
-        qnn.qnn_rel_l2(B, H, W, y, OUT_CH, target, idx_t, self.scale, self.grad["out"], OUT_CH, self.loss,
+        qnn.qnn_rel_l2(B, H, W, y, OUT_LD, target, idx_t, self.scale, self.grad["out"], OUT_CH, self.loss,
                        self.per_sample, self.lwork, self.stream)
         self.backward(B, H, W, self.grad["out"])
         self.adam(lr)
@@ -309,7 +310,7 @@ class UNet:
         """Per-sample relative field errors |pred - target| / |target|."""
         self.pack(B, H, W, q, idx_q, n, idx_n)
         y = self.forward_packed(B, H, W)
-        qnn.qnn_rel_l2(B, H, W, y, OUT_CH, target, idx_t, self.scale, None, OUT_CH, self.loss, self.per_sample,
+        qnn.qnn_rel_l2(B, H, W, y, OUT_LD, target, idx_t, self.scale, None, OUT_CH, self.loss, self.per_sample,
                        self.lwork, self.stream)
         return self.per_sample.cpu().numpy().copy()
 

@@ -120,6 +120,26 @@ def test_conv_weight_gradient(env, B, H, W, ci, co):
     assert torch.equal(dw, again)       # deterministic reduction order
 
 
+@pytest.mark.parametrize("B,H,W,ci,co", [(2, 16, 32, 16, 32), (3, 7, 5, 32, 64)])
+def test_conv_weight_gradient_unaligned_views(env, B, H, W, ci, co):
+    """x and dy one element into their buffers (not 16-byte aligned): the
+    pixel-list weight-gradient kernel, which reads 2-byte elements."""
+    torch, qnn = env
+    xa, xr = bf(torch, rnd(10, B * H * W * ci + 1))
+    da, dr = bf(torch, rnd(11, B * H * W * co + 1))
+    x, dy = xa[1:], da[1:]
+    xr = xr[1:].reshape(B, H, W, ci)
+    dyr = dr[1:].reshape(B, H, W, co)
+    dw = torch.empty(co * 9 * ci, dtype=torch.float32, device="cuda")
+    db = torch.empty(co, dtype=torch.float32, device="cuda")
+    work = torch.empty(qnn.qnn_wgrad_work_floats(B, H, W, ci, co), dtype=torch.float32, device="cuda")
+    qnn.qnn_conv3x3_wgrad(B, H, W, x, ci, dy, co, dw, db, work)
+    rdw, rdb = N.conv3x3_wgrad(xr, dyr)
+    P = B * H * W
+    got = dw.cpu().numpy().reshape(co, 9, ci)
+    assert np.abs(got - rdw).max() <= 1e-6 * np.sqrt(P) * np.abs(rdw).max() + 1e-5
+    assert np.abs(db.cpu().numpy() - rdb).max() <= 1e-6 * np.sqrt(P) * np.abs(rdb).max() + 1e-5
+
 @pytest.mark.parametrize("C", [32, 48, 12])
 def test_elementwise_kernels_bit_exact(env, C):
     """C % 8 == 0 runs the 16-byte vector kernels, C = 12 the scalar ones."""
@@ -171,16 +191,27 @@ def test_pack_absmax_unpack(env):
     nn = torch.tensor((2 + rnd(13, (Bn, 3, H, W))).astype(np.float32)).cuda()
     idx_q = torch.tensor([4, 0, 2, 2], dtype=torch.int32).cuda()
     idx_n = torch.tensor([1, 0, 2, 1], dtype=torch.int32).cuda()
-    B, d = 4, 5
+    B = 4
     scale = torch.empty(B, dtype=torch.float32, device="cuda")
     qnn.qnn_absmax(B, H, W, q, idx_q, scale)
     qn = q.cpu().numpy()
     want_scale = np.abs(qn[[4, 0, 2, 2]]).reshape(B, -1).max(axis=1)
     np.testing.assert_array_equal(scale.cpu().numpy(), want_scale.astype(np.float32))
     x = torch.empty((B, H, W, 48), dtype=torch.bfloat16, device="cuda")
-    qnn.qnn_pack_input(B, H, W, q, idx_q, nn, idx_n, scale, 2.0, 1.0, d, x)
-    xs = x.float().cpu().numpy()
     nnp = nn.cpu().numpy()
+    # displacements within the lattice, negative, and longer than both sides
+    for d in (5, -3, 37):
+        qnn.qnn_pack_input(B, H, W, q, idx_q, nn, idx_n, scale, 2.0, 1.0, d, x)
+        xs = x.float().cpu().numpy()
+        check_pack(xs, qn, nnp, want_scale, d)
+    y = torch.tensor(rnd(14, (B, H, W, 32)).astype(np.float32)).cuda()
+    out = torch.empty((B, 6, H, W), dtype=torch.float32, device="cuda")
+    qnn.qnn_unpack_output(B, H, W, y, 32, scale, out)
+    want = y.cpu().numpy()[..., :6].transpose(0, 3, 1, 2) * scale.cpu().numpy()[:, None, None, None]
+    np.testing.assert_array_equal(out.cpu().numpy(), want.astype(np.float32))
+
+
+def check_pack(xs, qn, nnp, want_scale, d):
     for b, (iq, inn) in enumerate(zip([4, 0, 2, 2], [1, 0, 2, 1])):
         f = (qn[iq] / np.float32(want_scale[b])).transpose(1, 2, 0)          # (H, W, 6)
         np.testing.assert_array_equal(xs[b, :, :, :6], N.bf16_round(f))
@@ -190,11 +221,6 @@ def test_pack_absmax_unpack(env):
         np.testing.assert_array_equal(xs[b, :, :, 21:27], N.bf16_round(np.roll(f, d, axis=0)))   # Q(y - d, x)
         np.testing.assert_array_equal(xs[b, :, :, 27:33], N.bf16_round(np.roll(f, -d, axis=0)))  # Q(y + d, x)
         assert np.all(xs[b, :, :, 33:] == 0)
-    y = torch.tensor(rnd(14, (B, H, W, 32)).astype(np.float32)).cuda()
-    out = torch.empty((B, 6, H, W), dtype=torch.float32, device="cuda")
-    qnn.qnn_unpack_output(B, H, W, y, 32, scale, out)
-    want = y.cpu().numpy()[..., :6].transpose(0, 3, 1, 2) * scale.cpu().numpy()[:, None, None, None]
-    np.testing.assert_array_equal(out.cpu().numpy(), want.astype(np.float32))
 
 
 def test_absmax_large_and_zero_samples(env):
@@ -285,7 +311,7 @@ def test_whole_network_forward_and_gradients(env):
     xt, xr = bf(torch, xin)
     net.act["x"].copy_(xt.view(-1))
     out = net.forward_packed(B, H, W)
-    got = out.cpu().numpy().reshape(B, H, W, 32)[..., :6]
+    got = out.cpu().numpy().reshape(B, H, W, S.OUT_LD)[..., :6]
     p = net.p.cpu().numpy().astype(np.float64)
     # weights as the GPU uses them (BF16), biases FP32
     pr = p.copy()

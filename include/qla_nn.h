@@ -51,6 +51,25 @@ int qnn_conv3x3_fwd(int32_t B, int32_t H, int32_t W, const uint16_t *x, int32_t 
                     const uint16_t *w, const float *bias, int32_t c_out, int32_t act,
                     void *y, int32_t y_fp32, int32_t y_ld, int32_t c_store, void *hip_stream);
 
+/*
+ * The forward convolution with its U-net neighbours folded in, for
+ * inference (the training pass keeps the intermediate tensors, which its
+ * backward pass reads):
+ *   y = act(bias + conv3x3(U(x), w)) + add
+ *   up = 1: x is BF16 [B*(H/2)*(W/2)][c_in] and U(x) its 2x nearest
+ *           upsampling (qnn_upsample2), never stored; H and W even
+ *   up = 0: x is BF16 [B*H*W][c_in] and U(x) = x
+ *   add     BF16 [B*H*W][y_ld] or NULL, added to the rounded BF16 result
+ *           and rounded again: bitwise qnn_conv3x3_fwd followed by qnn_add
+ *   y       BF16 [B*H*W][y_ld], all c_out channels written
+ * W must be 16, 32 or a multiple of 64; y_ld >= c_out, a multiple of 8; x,
+ * w, add and y 16-byte aligned; otherwise QNN_EINVAL (and nothing runs).
+ */
+int qnn_conv3x3_fwd_fused(int32_t B, int32_t H, int32_t W, const uint16_t *x, int32_t c_in,
+                          int32_t up, const uint16_t *w, const float *bias, int32_t c_out,
+                          int32_t act, const uint16_t *add, uint16_t *y, int32_t y_ld,
+                          void *hip_stream);
+
 /* wt = the weights of the adjoint convolution: wt[ci][8 - t][co] = w[co][t][ci]
  * (the data gradient of a circular 3x3 convolution is a 3x3 convolution of
  * the output gradient with the flipped, transposed kernel). */

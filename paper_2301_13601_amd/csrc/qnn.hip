@@ -154,7 +154,8 @@ __global__ void __launch_bounds__(256) conv_fwd_pipe_kernel(int H, int W, int tw
                                                             const uint16_t* __restrict__ x, int cin,
                                                             const uint16_t* __restrict__ w,
                                                             const float* __restrict__ bias, int act,
-                                                            void* __restrict__ y, int y_ld, int c_store) {
+                                                            void* __restrict__ y, int y_ld, int c_store, int up,
+                                                            const uint16_t* __restrict__ add) {
   using PC = PipeConv<MT, NT>;
   // staged input tile and weights; at the end of a tile, the waves' outputs
   __shared__ __attribute__((aligned(16))) uint16_t smem[PC::kSmem];
@@ -215,7 +216,7 @@ __global__ void __launch_bounds__(256) conv_fwd_pipe_kernel(int H, int W, int tw
     const int tx0_ = ((T) % tiles_x) << tw_shift;                                                   \
     const int t2_ = (T) / tiles_x;                                                                  \
     const int ty0_ = (t2_ % tiles_y) * TH;                                                          \
-    const int img_ = (t2_ / tiles_y) * H;                                                           \
+    const int img_ = (t2_ / tiles_y) * (H >> up);                                                  \
     _Pragma("unroll") for (int k = 0; k < PC::kInItems; ++k) {                                      \
       if (in_d[k] >= 0) {                                                                           \
         /* periodic; with tiles taller than the image, rows may lie several H past the end */    \
@@ -226,8 +227,9 @@ __global__ void __launch_bounds__(256) conv_fwd_pipe_kernel(int H, int W, int tw
           yy = yy < 0 ? yy + H : (yy >= H ? yy - H : yy);                                           \
         int xx = tx0_ - 1 + ((in_p[k] >> 1) & 0x7fff);                                              \
         xx = xx < 0 ? xx + W : (xx >= W ? xx - W : xx);                                             \
-        /* element offsets fit 31 bits (checked on the host) */                                    \
-        const int src = ((img_ + yy) * W + xx) * cin + (CH) * 16 + (in_p[k] & 1) * 8;               \
+        /* an upsampled input is read at (yy / 2, xx / 2) of the half-size */                     \
+        /* image; element offsets fit 31 bits (checked on the host) */                             \
+        const int src = ((img_ + (yy >> up)) * (W >> up) + (xx >> up)) * cin + (CH) * 16 + (in_p[k] & 1) * 8; \
         sin[k] = *reinterpret_cast<const u32x4*>(x + src);                                          \
       }                                                                                             \
     }                                                                                               \
@@ -325,8 +327,18 @@ __global__ void __launch_bounds__(256) conv_fwd_pipe_kernel(int H, int W, int tw
         const int oy = ty0 + (j >> tw_shift);
         if (oy < H) {
           const int o = ((b * H + oy) * W + tx0 + (j & (TW - 1))) * y_ld + n0 + g * 8;
-          *reinterpret_cast<u32x4*>(static_cast<uint16_t*>(y) + o) =
-              *reinterpret_cast<const u32x4*>(E + pm * PC::kERow + g * 8);
+          u32x4 v = *reinterpret_cast<const u32x4*>(E + pm * PC::kERow + g * 8);
+          if (add) {
+            // the stored BF16 result plus the skip input, rounded once more
+            const u32x4 e = *reinterpret_cast<const u32x4*>(add + o);
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+              const float lo = bf2f(static_cast<uint16_t>(v[h])) + bf2f(static_cast<uint16_t>(e[h]));
+              const float hi = bf2f(static_cast<uint16_t>(v[h] >> 16)) + bf2f(static_cast<uint16_t>(e[h] >> 16));
+              v[h] = static_cast<uint32_t>(f2bf(lo)) | (static_cast<uint32_t>(f2bf(hi)) << 16);
+            }
+          }
+          *reinterpret_cast<u32x4*>(static_cast<uint16_t*>(y) + o) = v;
         }
       }
     } else if (OUT_FP32 && chunk == nchunks - 1) {
@@ -1070,9 +1082,9 @@ __global__ void compare_final_kernel(int B, const double* __restrict__ work, dou
 // grid.x persistent blocks, as many as stay resident at once (times
 // `waves`, capped by the tile count).
 template <int MT, int NT>
-void conv_pipe_launch(int B, int H, int W, const uint16_t* x, int cin, const uint16_t* w, const float* bias,
-                      int act, void* y, bool y_fp32, int y_ld, int c_store, int c_out, float waves,
-                      hipStream_t st) {
+void conv_pipe_launch(int B, int H, int W, const uint16_t* x, int cin, int up, const uint16_t* w, const float* bias,
+                      int act, const uint16_t* add, void* y, bool y_fp32, int y_ld, int c_store, int c_out,
+                      float waves, hipStream_t st) {
   static int resident_per_cu[2] = {0, 0};
   static int cus = 0;
   if (cus == 0) {
@@ -1099,30 +1111,46 @@ void conv_pipe_launch(int B, int H, int W, const uint16_t* x, int cin, const uin
   dim3 grid(static_cast<unsigned>(gx), gy);
   if (y_fp32)
     hipLaunchKernelGGL((conv_fwd_pipe_kernel<MT, NT, true>), grid, dim3(256), 0, st, H, W, tws, static_cast<int>(tiles),
-                       x, cin, w, bias, act, y, y_ld, c_store);
+                       x, cin, w, bias, act, y, y_ld, c_store, up, add);
   else
     hipLaunchKernelGGL((conv_fwd_pipe_kernel<MT, NT, false>), grid, dim3(256), 0, st, H, W, tws, static_cast<int>(tiles),
-                       x, cin, w, bias, act, y, y_ld, c_store);
+                       x, cin, w, bias, act, y, y_ld, c_store, up, add);
 }
 
 // the pipelined kernel's tiles: W a multiple of TW = min(W, 64) in {16, 32, 64}
 inline bool pipe_fits(int W) { return W % 16 == 0 && (W >= 64 ? W % 64 == 0 : (W == 16 || W == 32)); }
 
-bool conv_pipe(int mt, int nt, int B, int H, int W, const uint16_t* x, int cin, const uint16_t* w,
-               const float* bias, int act, void* y, bool y_fp32, int y_ld, int c_store, int c_out, float waves,
-               hipStream_t st) {
+bool conv_pipe(int mt, int nt, int B, int H, int W, const uint16_t* x, int cin, int up, const uint16_t* w,
+               const float* bias, int act, const uint16_t* add, void* y, bool y_fp32, int y_ld, int c_store,
+               int c_out, float waves, hipStream_t st) {
   if (!pipe_fits(W) || c_out % (32 * nt)) return false;
   // BF16 results leave in 16-byte pieces: every channel stored, whole
   // 8-channel groups per row, 16-byte aligned rows
   if (!y_fp32 && (c_store != c_out || y_ld % 8 || (reinterpret_cast<uintptr_t>(y) & 15))) return false;
 #define QNN_PIPE(M, N)                                                                                   \
   if (mt == M && nt == N) {                                                                              \
-    conv_pipe_launch<M, N>(B, H, W, x, cin, w, bias, act, y, y_fp32, y_ld, c_store, c_out, waves, st); \
+    conv_pipe_launch<M, N>(B, H, W, x, cin, up, w, bias, act, add, y, y_fp32, y_ld, c_store, c_out, waves, st); \
     return true;                                                                                         \
   }
   QNN_PIPE(1, 1) QNN_PIPE(1, 2) QNN_PIPE(2, 1) QNN_PIPE(2, 2)
 #undef QNN_PIPE
   return false;
+}
+
+// Tile shape of the pipelined kernel for a layer: 256-pixel tiles x 64
+// channels when that gives two or more blocks per CU, else 128-pixel tiles;
+// the layers with the fewest pixels split the channels finest.
+void pipe_shape(int B, int H, int W, int c_out, int& m, int& n) {
+  const int TW = W < 64 ? W : 64;
+  auto blocks = [&](int mt, int nt) {
+    const int TH = 128 * mt / TW;
+    return static_cast<int64_t>(B) * (W / TW) * ((H + TH - 1) / TH) * (c_out / (32 * nt));
+  };
+  const int nt = (c_out % 64 == 0) ? 2 : 1;
+  m = 1;
+  n = 1;
+  if (blocks(2, nt) >= 512) m = 2, n = nt;
+  else if (blocks(1, nt) >= 256) n = nt;
 }
 
 __global__ void to_bf16_kernel(int64_t n, const float* __restrict__ x, uint16_t* __restrict__ y) {
@@ -1170,21 +1198,11 @@ int qnn_conv3x3_fwd(int32_t B, int32_t H, int32_t W, const uint16_t* x, int32_t 
   if (P64 * (c_in > y_ld ? c_in : y_ld) >= (int64_t{1} << 31)) return bad("conv3x3_fwd: tensor too large");
   const int P = static_cast<int>(P64);
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  // The pipelined kernel, where the tiles fit: 256-pixel tiles x 64
-  // channels when that gives two or more blocks per CU, else 128-pixel
-  // tiles; the layers with the fewest pixels split the channels finest.
-  // Otherwise the pixel-list kernel below.
+  // the pipelined kernel where its tiles fit, else the pixel-list kernel
   if (pipe_fits(W)) {
-    const int TW = W < 64 ? W : 64;
-    auto blocks = [&](int mt, int nt) {
-      const int TH = 128 * mt / TW;
-      return static_cast<int64_t>(B) * (W / TW) * ((H + TH - 1) / TH) * (c_out / (32 * nt));
-    };
-    const int nt = (c_out % 64 == 0) ? 2 : 1;
-    int m = 1, n = 1;
-    if (blocks(2, nt) >= 512) m = 2, n = nt;
-    else if (blocks(1, nt) >= 256) n = nt;
-    if (conv_pipe(m, n, B, H, W, x, c_in, w, bias, act, y, y_fp32 != 0, y_ld, c_store, c_out, 1.0f, st))
+    int m, n;
+    pipe_shape(B, H, W, c_out, m, n);
+    if (conv_pipe(m, n, B, H, W, x, c_in, 0, w, bias, act, nullptr, y, y_fp32 != 0, y_ld, c_store, c_out, 1.0f, st))
       return launched("conv3x3_fwd");
   }
   const int nt = (c_out % 64 == 0) ? 2 : 1;
@@ -1199,12 +1217,34 @@ int qnn_conv3x3_fwd(int32_t B, int32_t H, int32_t W, const uint16_t* x, int32_t 
   return launched("conv3x3_fwd");
 }
 
+int qnn_conv3x3_fwd_fused(int32_t B, int32_t H, int32_t W, const uint16_t* x, int32_t c_in, int32_t up,
+                          const uint16_t* w, const float* bias, int32_t c_out, int32_t act, const uint16_t* add,
+                          uint16_t* y, int32_t y_ld, void* hip_stream) {
+  if (B < 1 || H < 1 || W < 1 || !x || !w || !y) return bad("conv3x3_fwd_fused: bad size or null pointer");
+  if (c_in < 16 || c_in % 16 || c_out < 32 || c_out % 32) return bad("conv3x3_fwd_fused: c_in % 16, c_out % 32");
+  if (act != QNN_ACT_NONE && act != QNN_ACT_LEAKY) return bad("conv3x3_fwd_fused: unknown activation");
+  if (up != 0 && up != 1) return bad("conv3x3_fwd_fused: up must be 0 or 1");
+  if (up && ((H | W) & 1)) return bad("conv3x3_fwd_fused: an upsampled input needs even H and W");
+  if (!pipe_fits(W)) return bad("conv3x3_fwd_fused: W must be 16, 32 or a multiple of 64");
+  if (y_ld < c_out || y_ld % 8) return bad("conv3x3_fwd_fused: y_ld must be >= c_out and a multiple of 8");
+  if (!a16(x) || !a16(w) || !a16(y) || (add && !a16(add)))
+    return bad("conv3x3_fwd_fused: tensors must be 16-byte aligned");
+  const int64_t P64 = static_cast<int64_t>(B) * H * W;
+  if (P64 * (c_in > y_ld ? c_in : y_ld) >= (int64_t{1} << 31)) return bad("conv3x3_fwd_fused: tensor too large");
+  int m, n;
+  pipe_shape(B, H, W, c_out, m, n);
+  if (!conv_pipe(m, n, B, H, W, x, c_in, up, w, bias, act, add, y, false, y_ld, c_out, c_out, 1.0f,
+                 static_cast<hipStream_t>(hip_stream)))
+    return bad("conv3x3_fwd_fused: shape not supported");
+  return launched("conv3x3_fwd_fused");
+}
+
 #ifdef QNN_TUNE_HOOK
 // geometry sweeps only (not part of the library's interface)
 int qnn_conv3x3_fwd_cfg(int32_t B, int32_t H, int32_t W, const uint16_t* x, int32_t c_in, const uint16_t* w,
                         const float* bias, int32_t c_out, int32_t act, void* y, int32_t y_fp32, int32_t y_ld,
                         int32_t c_store, int32_t mt, int32_t nt, float waves, void* hip_stream) {
-  if (!conv_pipe(mt, nt, B, H, W, x, c_in, w, bias, act, y, y_fp32 != 0, y_ld, c_store, c_out, waves,
+  if (!conv_pipe(mt, nt, B, H, W, x, c_in, 0, w, bias, act, nullptr, y, y_fp32 != 0, y_ld, c_store, c_out, waves,
                  static_cast<hipStream_t>(hip_stream)))
     return bad("conv3x3_fwd_cfg: geometry not supported");
   return launched("conv3x3_fwd_cfg");

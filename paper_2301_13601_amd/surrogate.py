@@ -201,8 +201,13 @@ class UNet:
                                 s.c_out, self.stream)
         return y
 
-    def forward_packed(self, B: int, H: int, W: int):
-        """Run the network on self.act["x"]; returns the FP32 output [P][8] (6 channels used)."""
+    def forward_packed(self, B: int, H: int, W: int, fused: bool = False):
+        """Run the network on self.act["x"]; returns the FP32 output [P][8]
+        (6 channels used). fused: each decoder level's upsampling and skip
+        addition run inside its first convolution (qnn_conv3x3_fwd_fused,
+        bitwise the same result) wherever that kernel's tile widths fit; the
+        upsampled and pre-addition tensors are then not stored, so training,
+        whose backward pass reads them, runs unfused."""
         A, S = self.act, self.by_name
         st = self.stream
         x = A["x"]
@@ -218,10 +223,15 @@ class UNet:
             x = self._conv(S[f"b{k}"], x, B, H, W)
         up_c = LEVELS[3]
         for l in (3, 2, 1, 0):
-            qnn.qnn_upsample2(B, H >> (l + 1), W >> (l + 1), up_c, x, A[f"u{l}"], st)
-            d = self._conv(S[f"d{l}a"], A[f"u{l}"], B, H, W)
-            n = B * (H >> l) * (W >> l) * LEVELS[l]
-            qnn.qnn_add(n, d, A[f"e{l}"], A[f"h{l}"], st)
+            s, w_l = S[f"d{l}a"], W >> l
+            if fused and (w_l in (16, 32) or w_l % 64 == 0):
+                qnn.qnn_conv3x3_fwd_fused(B, H >> l, w_l, x, s.c_in, 1, self.w(s), self.b(s), s.c_out, s.act,
+                                          A[f"e{l}"], A[f"h{l}"], s.c_out, st)
+            else:
+                qnn.qnn_upsample2(B, H >> (l + 1), W >> (l + 1), up_c, x, A[f"u{l}"], st)
+                d = self._conv(s, A[f"u{l}"], B, H, W)
+                n = B * (H >> l) * (W >> l) * LEVELS[l]
+                qnn.qnn_add(n, d, A[f"e{l}"], A[f"h{l}"], st)
             x = self._conv(S[f"d{l}"], A[f"h{l}"], B, H, W)
             up_c = LEVELS[l]
         return self._conv(S["out"], x, B, H, W, fp32=True)
@@ -241,7 +251,7 @@ class UNet:
         for c0 in range(0, B, chunk):
             c1 = min(B, c0 + chunk)
             self.pack(c1 - c0, H, W, q[c0:c1], None, n[c0:c1], None)
-            y = self.forward_packed(c1 - c0, H, W)
+            y = self.forward_packed(c1 - c0, H, W, fused=True)
             qnn.qnn_unpack_output(c1 - c0, H, W, y, OUT_LD, self.scale, out_q[c0:c1], self.stream)
 
     # -- backward ----------------------------------------------------------------
@@ -309,7 +319,7 @@ class UNet:
     def eval_error(self, q, idx_q, n, idx_n, target, idx_t, B, H, W):
         """Per-sample relative field errors |pred - target| / |target|."""
         self.pack(B, H, W, q, idx_q, n, idx_n)
-        y = self.forward_packed(B, H, W)
+        y = self.forward_packed(B, H, W, fused=True)
         qnn.qnn_rel_l2(B, H, W, y, OUT_LD, target, idx_t, self.scale, None, OUT_CH, self.loss, self.per_sample,
                        self.lwork, self.stream)
         return self.per_sample.cpu().numpy().copy()

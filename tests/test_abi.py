@@ -111,3 +111,21 @@ def test_conv_rejects_misaligned_operands_without_a_device(qla):
     for x, w in [(0x1002, 0x2000), (0x1000, 0x2008)]:
         assert conv(1, 16, 16, x, 16, w, None, 32, 0, 0x3000, 1, 32, 32, None) == -1
         assert "aligned" in qla.qla_last_error()
+
+
+def test_fused_conv_rejects_what_it_cannot_run_without_a_device(qla):
+    L = ctypes.CDLL(qla.LIB_PATH)
+    f = L.qnn_conv3x3_fwd_fused
+    i, v = ctypes.c_int32, ctypes.c_void_p
+    f.argtypes = [i, i, i, v, i, i, v, v, i, i, v, v, i, v]
+    X, Wt, Y = 0x10000, 0x20000, 0x30000
+    ok = dict(B=1, H=32, W=64, x=X, ci=32, up=1, w=Wt, bias=None, co=32, act=0, add=None, y=Y, ld=32)
+
+    def call(**kw):
+        a = dict(ok, **kw)
+        return f(a["B"], a["H"], a["W"], a["x"], a["ci"], a["up"], a["w"], a["bias"], a["co"], a["act"],
+                 a["add"], a["y"], a["ld"], None)
+
+    for bad in [dict(W=48), dict(H=31), dict(up=2), dict(ld=36), dict(ld=16), dict(y=Y + 2),
+                dict(add=0x40008), dict(co=48), dict(ci=24), dict(act=3)]:
+        assert call(**bad) == -1, bad

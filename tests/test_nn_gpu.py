@@ -81,6 +81,33 @@ def test_conv_forward_partial_store(env, W):
     assert np.all(gotb[..., 6:] == 7.0)
 
 
+@pytest.mark.parametrize("B,H,W,ci,co", [(2, 32, 64, 64, 32), (3, 16, 16, 128, 128), (2, 20, 32, 32, 64),
+                                         (16, 64, 128, 128, 64)])
+@pytest.mark.parametrize("up", [0, 1])
+@pytest.mark.parametrize("with_add", [False, True])
+def test_conv_fused_is_bitwise_the_separate_steps(env, B, H, W, ci, co, up, with_add):
+    torch, qnn = env
+    h, w_ = (H // 2, W // 2) if up else (H, W)
+    x, _ = bf(torch, rnd(30, (B, h, w_, ci)))
+    w, _ = bf(torch, rnd(31, (co, 9, ci), 1 / np.sqrt(9 * ci)))
+    bias = torch.tensor(rnd(32, co).astype(np.float32)).cuda()
+    e, _ = bf(torch, rnd(33, (B, H, W, co))) if with_add else (None, None)
+    # the separate steps
+    xin = x
+    if up:
+        xin = torch.empty((B, H, W, ci), dtype=torch.bfloat16, device="cuda")
+        qnn.qnn_upsample2(B, h, w_, ci, x, xin)
+    d = torch.empty((B, H, W, co), dtype=torch.bfloat16, device="cuda")
+    qnn.qnn_conv3x3_fwd(B, H, W, xin, ci, w, bias, co, 1, d, 0, co, co)
+    want = d
+    if with_add:
+        want = torch.empty_like(d)
+        qnn.qnn_add(d.numel(), d, e, want)
+    got = torch.full((B, H, W, co), 3.0, dtype=torch.bfloat16, device="cuda")
+    qnn.qnn_conv3x3_fwd_fused(B, H, W, x, ci, up, w, bias, co, 1, e, got, co)
+    assert torch.equal(got.view(torch.int16), want.view(torch.int16))
+
+
 @pytest.mark.parametrize("B,H,W,ci,co", [(2, 16, 16, 16, 32), (1, 6, 10, 64, 32), (2, 2, 2, 128, 128),
                                          (4, 32, 64, 32, 64)])
 def test_conv_data_gradient(env, B, H, W, ci, co):
@@ -290,6 +317,26 @@ def test_compare(env, m):
     A, Bn = a.cpu().numpy().astype(np.float64), b.cpu().numpy().astype(np.float64)
     np.testing.assert_allclose(rel.cpu().numpy(), np.linalg.norm(A - Bn, axis=1) / np.linalg.norm(Bn, axis=1), rtol=1e-12)
     np.testing.assert_allclose(en.cpu().numpy(), np.abs((A ** 2).sum(1) - (Bn ** 2).sum(1)) / (Bn ** 2).sum(1), rtol=1e-10)
+
+
+@pytest.mark.parametrize("H,W", [(64, 128), (32, 64)])
+def test_network_forward_fused_is_bitwise_unfused(env, H, W):
+    """Inference folds each decoder level's upsampling and skip addition
+    into its first convolution where the tile widths fit (at W = 64 the
+    8-wide level stays unfused)."""
+    torch, qnn = env
+    from paper_2301_13601_amd import surrogate as S
+
+    net = S.UNet(seed=5)
+    B = 2
+    net._buffers(B, H, W)
+    xin = rnd(24, (B, H, W, 48))
+    xin[..., 33:] = 0
+    xt, _ = bf(torch, xin)
+    net.act["x"].copy_(xt.view(-1))
+    a = net.forward_packed(B, H, W).clone()
+    b = net.forward_packed(B, H, W, fused=True).clone()
+    assert torch.equal(a, b)
 
 
 def test_whole_network_forward_and_gradients(env):

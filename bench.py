@@ -300,15 +300,92 @@ def sweep_workload(args) -> dict:
     }
 
 
+def unet_workload(args) -> dict:
+    """Inference throughput of the surrogate network (the U-net of the
+    sweep, random-init weights: the cost does not depend on their values).
+
+    --unet-lattices lattices of 1024 x 1024 from the batched scene family
+    (seed 5) are packed, run through the network and unpacked; one "step"
+    is one such pass over the whole batch. value = pixels/s; the roofline
+    is the BF16 matrix-core peak, with 2 x (multiply-accumulates per pixel)
+    flops per pixel. The CPU baseline is the FP64 oracle network on one
+    --cpu-unet-side square sample."""
+    import torch
+    from paper_2301_13601_amd import scenes, surrogate as S
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    L, B = 1024, args.unet_lattices
+    specs = scenes.batch_instance_specs(B, seed=5, sides=(L,))
+    scs = [scenes.scene_from_spec(sp, steps=0) for sp in specs]
+    q = torch.as_tensor(np.stack([s.q.astype(np.float32) for s in scs])).to(dev)
+    n = torch.as_tensor(np.stack([s.n.astype(np.float32) for s in scs])).to(dev)
+    out = torch.empty_like(q)
+    net = S.UNet(seed=0)
+    for _ in range(args.warmup):
+        net.predict(q, n, out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(net.stream)
+    for _ in range(args.steps):
+        net.predict(q, n, out)
+    e1.record(net.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sec = e0.elapsed_time(e1) / 1e3 / args.steps
+    pixels = B * L * L
+    flop = 2.0 * S.macs_per_pixel() * pixels
+    rec = {
+        "metric": "surrogate inference pixels/s",
+        "value": pixels / sec,
+        "unit": "pixels/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec * 1e3,
+        "wall_s": wall,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16 x bf16 -> f32",
+        "data": "synthetic (batched scene family, random-init weights)",
+        "config": {"workload": f"unet_forward: {B} lattices of {L}x{L}, one network pass each (pack, "
+                               "U-net 32/64/128/128 with fused decoder steps, unpack)",
+                   "macs_per_pixel": S.macs_per_pixel(), "seconds_per_pixel": sec / pixels},
+        "roofline": {"bound": "mfma", "achieved": flop / sec / 1e12, "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": flop / sec / 1e12 / 2500.0, "traffic": None,
+                     "kernel": "whole network pass (conv_fwd_pipe_kernel: ~90 % of it)"},
+    }
+    if not args.no_cpu_baseline:
+        from oracle import nn_oracle as NO
+        from threadpoolctl import threadpool_info
+        side = args.cpu_unet_side
+        rng = np.random.default_rng(7)
+        x = rng.standard_normal((1, side, side, 48))
+        x[..., 33:] = 0
+        p = net.p.cpu().numpy().astype(np.float64)
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+        t0 = time.perf_counter()
+        NO.unet_forward(p, x, bf16=True)
+        dt = time.perf_counter() - t0
+        rec["cpu_baseline"] = {"value": side * side / dt, "unit": "pixels/s", "cores": threads, "kind": "oracle",
+                               "sample": f"one {side}x{side} sample through the FP64 oracle network "
+                                         f"(numpy, BLAS threads), {dt:.1f} s"}
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="cylinder_4096",
-                    choices=["cylinder_4096", "single_256", "batch_64", "sweep"])
+                    choices=["cylinder_4096", "single_256", "batch_64", "sweep", "unet_forward"])
     ap.add_argument("--train-steps", type=int, default=5000, help="sweep workload: network training steps")
     ap.add_argument("--sweep-lattices", type=int, default=16, help="sweep workload: lattices of 1024 x 1024")
+    ap.add_argument("--unet-lattices", type=int, default=16, help="unet_forward workload: lattices of 1024 x 1024")
+    ap.add_argument("--cpu-unet-side", type=int, default=1024, help="unet_forward: side of the oracle's sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="batch_64: keep the library's default launch geometry instead of the autotuned one")
@@ -337,6 +414,9 @@ def main():
 
     if args.workload == "sweep":
         print(json.dumps(sweep_workload(args)), flush=True)
+        return
+    if args.workload == "unet_forward":
+        print(json.dumps(unet_workload(args)), flush=True)
         return
 
     sc, desc = make_workload(args.workload, args.steps)

@@ -499,99 +499,148 @@ __global__ void __launch_bounds__(256) wgrad_kernel(int P, int H, int W, const u
   }
 }
 
-// Weight gradient, staged: a block owns 32 output channels x 128 columns k
-// of dW (one 32 x 32 MFMA tile per wave) and a range of pixels, taken 64 at
-// a time. Each chunk of dy (64 pixels x 32 channels) and of the tap-shifted
-// inputs (64 pixels x 128 columns) is read from memory in 16-byte pieces
-// and written to LDS transposed (pixel index fastest), so that every MFMA
-// operand -- eight consecutive pixels of one channel or column -- is one
-// 16-byte LDS read. Needs 16-byte aligned x and dy.
-constexpr int kWgChunk = 64;                 // pixels per staged chunk
-constexpr int kWgStride = kWgChunk + 8;      // LDS row stride (elements), 16-byte multiple
+// Weight gradient, staged: a block owns 32*A output channels x 128 columns k
+// of dW (per wave A 32 x 32 MFMA tiles sharing one B operand) and a range of
+// pixels, taken 128 at a time. Each thread loads a group of 8 pixels x 8
+// channels of dy or of the tap-shifted input (eight 16-byte loads), turns it
+// into 8 channels x 8 pixels with byte permutes, and writes it to LDS as 16-
+// byte rows, pixel index fastest, so that every MFMA operand (eight
+// consecutive pixels of one channel or column) is one 16-byte LDS read. The
+// next chunk's loads are in flight during the current chunk's MFMAs. Needs
+// 16-byte aligned x and dy and W % 8 == 0 (a group then lies in one image
+// row); the block's pixel range is a multiple of 128.
+constexpr int kWtChunk = 128;                 // pixels per staged chunk
+constexpr int kWtStride = kWtChunk + 8;       // LDS row stride (elements): rows 272 bytes apart
 
+template <int A>
 __global__ void __launch_bounds__(256) wgrad_lds_kernel(int P, int H, int W, const uint16_t* __restrict__ x,
                                                         int cin, const uint16_t* __restrict__ dy, int cout,
-                                                        float* __restrict__ part, float* __restrict__ bpart) {
-  __shared__ __attribute__((aligned(16))) uint16_t dyT[32 * kWgStride];
-  __shared__ __attribute__((aligned(16))) uint16_t xT[128 * kWgStride];
+                                                        int pps, float* __restrict__ part,
+                                                        float* __restrict__ bpart) {
+  __shared__ __attribute__((aligned(16))) uint16_t dyT[32 * A * kWtStride];
+  __shared__ __attribute__((aligned(16))) uint16_t xT[128 * kWtStride];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int tid = threadIdx.x;
-  const int co0 = blockIdx.x * 32;
+  const int co0 = blockIdx.x * 32 * A;
   const int kb0 = blockIdx.y * 128;
   const int split = blockIdx.z;
   const int K = 9 * cin;
-  const int HW = H * W;
-  f32x16 acc;
-#pragma unroll
-  for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
-  float bsum = 0.0f;
-  const int pbeg = split * kWgradPixelsPerBlock;
-  const int pend = min(P, pbeg + kWgradPixelsPerBlock);
+  const int pbeg = split * pps;
+  const int pend = min(P, pbeg + pps);
   const int half = (lane >> 5) * 8;
-  for (int pc = pbeg; pc < pend; pc += kWgChunk) {
-    // dy chunk: thread -> (pixel, 8 channels)
-    {
-      const int px = tid >> 2, c8 = (tid & 3) * 8;
-      const int pp = pc + px;
-      uint4 v = make_uint4(0, 0, 0, 0);
-      if (pp < pend) v = *reinterpret_cast<const uint4*>(dy + static_cast<int64_t>(pp) * cout + co0 + c8);
-      const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+  // this thread's groups: pixels 8 pg .. 8 pg + 7 of every chunk; input
+  // columns kb0 + 8 kc .. + 7 (one tap, 8 channels); for the first 64 A
+  // threads also dy channels co0 + 8 kc .. + 7
+  const int pg = tid & 15, kc = tid >> 4;
+  const int k = kb0 + 8 * kc;
+  const bool kvalid = k < K;
+  const int tap = kvalid ? k / cin : 0;
+  const int ci = k - tap * cin;
+  const int ty = tap / 3 - 1, tx = tap % 3 - 1;
+  const bool dgrp = tid < 64 * A;
+  // image, row and column of the group's first pixel in the next chunk
+  int gb, gy, gx;
+  {
+    const int p = pbeg + 8 * pg;
+    const int HW = H * W;
+    gb = p / HW;
+    gy = (p - gb * HW) / W;
+    gx = p - gb * HW - gy * W;
+  }
+  u32x4 xr[8], dr[8];
+  auto fetch = [&](int pc) {
+    const int p = pc + 8 * pg;
+    const bool live = p < pend;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        dyT[(c8 + 2 * j) * kWgStride + px] = static_cast<uint16_t>(w4[j] & 0xffffu);
-        dyT[(c8 + 2 * j + 1) * kWgStride + px] = static_cast<uint16_t>(w4[j] >> 16);
+    for (int i = 0; i < 8; ++i) xr[i] = u32x4{0, 0, 0, 0};
+    if (live && kvalid) {
+      int sy = gy + ty;
+      sy = sy < 0 ? sy + H : (sy >= H ? sy - H : sy);
+      const int rowbase = (gb * H + sy) * W;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        int sx = gx + i + tx;
+        sx = sx < 0 ? sx + W : (sx >= W ? sx - W : sx);
+        // element offsets fit 31 bits (checked on the host)
+        xr[i] = *reinterpret_cast<const u32x4*>(x + (rowbase + sx) * cin + ci);
       }
     }
-    // tap-shifted input chunk: unit -> (pixel, 8 columns k)
+    if (dgrp) {
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      const int u = tid + 256 * m;
-      const int px = u >> 4, kg = (u & 15) * 8;
-      const int k = kb0 + kg;
-      const int pp = pc + px;
-      uint4 v = make_uint4(0, 0, 0, 0);
-      if (pp < pend && k < K) {
-        const int t = k / cin, ci = k - (k / cin) * cin;
-        const int b = pp / HW;
-        const int rem = pp - b * HW;
-        const int yy = rem / W, xx = rem - (rem / W) * W;
-        const int64_t src = static_cast<int64_t>(b) * HW + static_cast<int64_t>(wrapi(yy + t / 3 - 1, H)) * W +
-                            wrapi(xx + t % 3 - 1, W);
-        v = *reinterpret_cast<const uint4*>(x + src * cin + ci);
-      }
-      const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        xT[(kg + 2 * j) * kWgStride + px] = static_cast<uint16_t>(w4[j] & 0xffffu);
-        xT[(kg + 2 * j + 1) * kWgStride + px] = static_cast<uint16_t>(w4[j] >> 16);
+      for (int i = 0; i < 8; ++i)
+        dr[i] = live ? *reinterpret_cast<const u32x4*>(dy + (p + i) * cout + co0 + 8 * kc) : u32x4{0, 0, 0, 0};
+    }
+    // advance the group by one chunk
+    gx += kWtChunk;
+    while (gx >= W) {
+      gx -= W;
+      if (++gy == H) {
+        gy = 0;
+        ++gb;
       }
     }
+  };
+  // 8 pixels x 8 channels (one 16-byte row per pixel) -> 8 channels x 8
+  // pixels: word w of channel row j holds pixels 2w (low half) and 2w + 1
+  auto put = [&](const u32x4 (&g)[8], uint16_t* dst) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const uint32_t sel = (j & 1) ? 0x07060302u : 0x05040100u;
+      u32x4 o;
+#pragma unroll
+      for (int w = 0; w < 4; ++w) o[w] = __builtin_amdgcn_perm(g[2 * w + 1][j >> 1], g[2 * w][j >> 1], sel);
+      *reinterpret_cast<u32x4*>(dst + j * kWtStride) = o;
+    }
+  };
+
+  f32x16 acc[A];
+#pragma unroll
+  for (int a = 0; a < A; ++a)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[a][r] = 0.0f;
+  float bsum[A];
+#pragma unroll
+  for (int a = 0; a < A; ++a) bsum[a] = 0.0f;
+  const bool want_bias = bpart && blockIdx.y == 0 && wave == 0;
+  if (pbeg < pend) fetch(pbeg);
+  for (int pc = pbeg; pc < pend; pc += kWtChunk) {
+    __syncthreads();      // every wave is done with the previous chunk
+    put(xr, xT + (8 * kc) * kWtStride + 8 * pg);
+    if (dgrp) put(dr, dyT + (8 * kc) * kWtStride + 8 * pg);
     __syncthreads();
+    if (pc + kWtChunk < pend) fetch(pc + kWtChunk);
 #pragma unroll
-    for (int s = 0; s < kWgChunk / 16; ++s) {
-      const bf16x8 a = *reinterpret_cast<const bf16x8*>(dyT + (lane & 31) * kWgStride + 16 * s + half);
-      const bf16x8 bb = *reinterpret_cast<const bf16x8*>(xT + (32 * wave + (lane & 31)) * kWgStride + 16 * s + half);
-      if (wave == 0) {
+    for (int s = 0; s < kWtChunk / 16; ++s) {
+      const u32x4 braw = *reinterpret_cast<const u32x4*>(xT + (32 * wave + (lane & 31)) * kWtStride + 16 * s + half);
 #pragma unroll
-        for (int j = 0; j < 8; ++j) bsum += static_cast<float>(a[j]);
+      for (int a = 0; a < A; ++a) {
+        const u32x4 araw = *reinterpret_cast<const u32x4*>(dyT + (32 * a + (lane & 31)) * kWtStride + 16 * s + half);
+        if (want_bias) {
+#pragma unroll
+          for (int w = 0; w < 4; ++w)
+            bsum[a] += bf2f(static_cast<uint16_t>(araw[w])) + bf2f(static_cast<uint16_t>(araw[w] >> 16));
+        }
+        acc[a] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, araw),
+                                                         __builtin_bit_cast(bf16x8, braw), acc[a], 0, 0, 0);
       }
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bb, acc, 0, 0, 0);
     }
-    __syncthreads();
   }
   const int kcol = kb0 + 32 * wave + (lane & 31);
-  if (kcol < K) {
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int row = (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);     // co within the tile
-      part[(static_cast<int64_t>(split) * cout + co0 + row) * K + kcol] = acc[r];
+  for (int a = 0; a < A; ++a) {
+    if (kcol < K) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);     // co within the tile
+        part[(static_cast<int64_t>(split) * cout + co0 + 32 * a + row) * K + kcol] = acc[a][r];
+      }
     }
-  }
-  if (bpart && blockIdx.y == 0 && wave == 0) {
-    // lanes l and l + 32 hold the two pixel halves of channel l
-    const float tot = bsum + __shfl_xor(bsum, 32);
-    if (lane < 32) bpart[static_cast<int64_t>(split) * cout + co0 + lane] = tot;
+    if (want_bias) {
+      // lanes l and l + 32 hold the two pixel halves of channel l
+      const float tot = bsum[a] + __shfl_xor(bsum[a], 32);
+      if (lane < 32) bpart[static_cast<int64_t>(split) * cout + co0 + 32 * a + lane] = tot;
+    }
   }
 }
 
@@ -1140,6 +1189,22 @@ bool conv_pipe(int mt, int nt, int B, int H, int W, const uint16_t* x, int cin, 
 // Tile shape of the pipelined kernel for a layer: 256-pixel tiles x 64
 // channels when that gives two or more blocks per CU, else 128-pixel tiles;
 // the layers with the fewest pixels split the channels finest.
+// Weight-gradient geometry of the staged kernel: a = 32-channel output tiles
+// per block (2 when c_out allows), and the pixel range of a block (pps, a
+// multiple of the 128-pixel chunk) chosen so that about 1024 blocks cover
+// the chip; nsplit ranges (each leaves one partial dW in the workspace).
+void wgrad_split(int P, int c_in, int c_out, int& a, int& nsplit, int& pps) {
+  a = (c_out % 64 == 0) ? 2 : 1;
+  const int64_t blocks_xy = static_cast<int64_t>(c_out / (32 * a)) * ((9 * c_in + 127) / 128);
+  int64_t want = (1024 + blocks_xy - 1) / blocks_xy;
+  const int64_t chunks = (P + kWtChunk - 1) / kWtChunk;
+  if (want > chunks) want = chunks;
+  if (want < 1) want = 1;
+  const int64_t per = (P + want - 1) / want;
+  pps = static_cast<int>((per + kWtChunk - 1) / kWtChunk * kWtChunk);
+  nsplit = static_cast<int>((P + pps - 1) / pps);
+}
+
 void pipe_shape(int B, int H, int W, int c_out, int& m, int& n) {
   const int TW = W < 64 ? W : 64;
   auto blocks = [&](int mt, int nt) {
@@ -1260,8 +1325,12 @@ int qnn_conv3x3_flip(const uint16_t* w, int32_t c_out, int32_t c_in, uint16_t* w
 
 int64_t qnn_wgrad_work_floats(int32_t B, int32_t H, int32_t W, int32_t c_in, int32_t c_out) {
   const int64_t P = static_cast<int64_t>(B) * H * W;
-  const int64_t nsplit = (P + kWgradPixelsPerBlock - 1) / kWgradPixelsPerBlock;
-  return nsplit * c_out * (9 * static_cast<int64_t>(c_in) + 1);
+  if (P < 1 || P >= (int64_t{1} << 31) || c_in < 1 || c_out < 32) return 0;
+  const int64_t old_split = (P + kWgradPixelsPerBlock - 1) / kWgradPixelsPerBlock;
+  int a, nsplit, pps;
+  wgrad_split(static_cast<int>(P), c_in, c_out, a, nsplit, pps);
+  const int64_t most = nsplit > old_split ? nsplit : old_split;
+  return most * c_out * (9 * static_cast<int64_t>(c_in) + 1);
 }
 
 int qnn_conv3x3_wgrad(int32_t B, int32_t H, int32_t W, const uint16_t* x, int32_t c_in, const uint16_t* dy,
@@ -1271,18 +1340,28 @@ int qnn_conv3x3_wgrad(int32_t B, int32_t H, int32_t W, const uint16_t* x, int32_
   const int64_t P64 = static_cast<int64_t>(B) * H * W;
   if (P64 * (c_in > c_out ? c_in : c_out) >= (int64_t{1} << 31)) return bad("conv3x3_wgrad: tensor too large");
   const int P = static_cast<int>(P64);
-  const int nsplit = (P + kWgradPixelsPerBlock - 1) / kWgradPixelsPerBlock;
   const int K = 9 * c_in;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  int nsplit;
   float* part = work;
-  float* bpart = work + static_cast<int64_t>(nsplit) * c_out * K;
-  if (a16(x) && a16(dy)) {
-    dim3 g2(c_out / 32, (K + 127) / 128, nsplit);
-    hipLaunchKernelGGL(wgrad_lds_kernel, g2, dim3(256), 0, st, P, H, W, x, c_in, dy, c_out, part, dbias ? bpart : nullptr);
-  } else if (W % 16 == 0)
-    hipLaunchKernelGGL((wgrad_kernel<true>), dim3(c_out / 32, (K + 31) / 32, nsplit), dim3(256), 0, st, P, H, W, x, c_in, dy, c_out, part, dbias ? bpart : nullptr);
-  else
-    hipLaunchKernelGGL((wgrad_kernel<false>), dim3(c_out / 32, (K + 31) / 32, nsplit), dim3(256), 0, st, P, H, W, x, c_in, dy, c_out, part, dbias ? bpart : nullptr);
+  float* bpart;
+  if (a16(x) && a16(dy) && W % 8 == 0) {
+    int a, pps;
+    wgrad_split(P, c_in, c_out, a, nsplit, pps);
+    bpart = work + static_cast<int64_t>(nsplit) * c_out * K;
+    dim3 g(c_out / (32 * a), (K + 127) / 128, nsplit);
+    if (a == 2)
+      hipLaunchKernelGGL((wgrad_lds_kernel<2>), g, dim3(256), 0, st, P, H, W, x, c_in, dy, c_out, pps, part, dbias ? bpart : nullptr);
+    else
+      hipLaunchKernelGGL((wgrad_lds_kernel<1>), g, dim3(256), 0, st, P, H, W, x, c_in, dy, c_out, pps, part, dbias ? bpart : nullptr);
+  } else {
+    nsplit = (P + kWgradPixelsPerBlock - 1) / kWgradPixelsPerBlock;
+    bpart = work + static_cast<int64_t>(nsplit) * c_out * K;
+    if (W % 16 == 0)
+      hipLaunchKernelGGL((wgrad_kernel<true>), dim3(c_out / 32, (K + 31) / 32, nsplit), dim3(256), 0, st, P, H, W, x, c_in, dy, c_out, part, dbias ? bpart : nullptr);
+    else
+      hipLaunchKernelGGL((wgrad_kernel<false>), dim3(c_out / 32, (K + 31) / 32, nsplit), dim3(256), 0, st, P, H, W, x, c_in, dy, c_out, part, dbias ? bpart : nullptr);
+  }
   const int64_t n = static_cast<int64_t>(c_out) * K;
   hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(grid_for(n)), dim3(256), 0, st, part, nsplit, n, dw);
   if (dbias) hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(grid_for(c_out)), dim3(256), 0, st, bpart, nsplit, static_cast<int64_t>(c_out), dbias);

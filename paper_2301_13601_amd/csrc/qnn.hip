@@ -644,6 +644,26 @@ __global__ void __launch_bounds__(256) wgrad_lds_kernel(int P, int H, int W, con
   }
 }
 
+// First pass of the partial-sum reduction, in place: part holds nsplit
+// slices of n floats; slice g (< G) becomes the sum of slices g, g + G,
+// g + 2G, ... (in that order), element by element. Each element of a group
+// is read and written by one thread only. n % 4 == 0, 16-byte aligned.
+__global__ void wgrad_fold_kernel(float* __restrict__ part, int nsplit, int G, int64_t n4) {
+  const int g = blockIdx.y;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n4;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    float4 s = reinterpret_cast<const float4*>(part + static_cast<int64_t>(g) * 4 * n4)[i];
+    for (int k = g + G; k < nsplit; k += G) {
+      const float4 v = reinterpret_cast<const float4*>(part + static_cast<int64_t>(k) * 4 * n4)[i];
+      s.x += v.x;
+      s.y += v.y;
+      s.z += v.z;
+      s.w += v.w;
+    }
+    reinterpret_cast<float4*>(part + static_cast<int64_t>(g) * 4 * n4)[i] = s;
+  }
+}
+
 __global__ void wgrad_reduce_kernel(const float* __restrict__ part, int nsplit, int64_t n,
                                     float* __restrict__ out) {
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
@@ -1362,9 +1382,26 @@ int qnn_conv3x3_wgrad(int32_t B, int32_t H, int32_t W, const uint16_t* x, int32_
     else
       hipLaunchKernelGGL((wgrad_kernel<false>), dim3(c_out / 32, (K + 31) / 32, nsplit), dim3(256), 0, st, P, H, W, x, c_in, dy, c_out, part, dbias ? bpart : nullptr);
   }
+  // fold the partial sums: groups of splits in parallel (in place), then
+  // the group sums; a fixed order, so the result is the same on every call
   const int64_t n = static_cast<int64_t>(c_out) * K;
-  hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(grid_for(n)), dim3(256), 0, st, part, nsplit, n, dw);
-  if (dbias) hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(grid_for(c_out)), dim3(256), 0, st, bpart, nsplit, static_cast<int64_t>(c_out), dbias);
+  const int G = nsplit < 16 ? nsplit : 16;
+  if (G < nsplit && a16(work)) {
+    const int64_t n4 = n / 4;
+    const int gx = static_cast<int>(std::min<int64_t>((n4 + 255) / 256, 1024));
+    hipLaunchKernelGGL(wgrad_fold_kernel, dim3(gx, G), dim3(256), 0, st, part, nsplit, G, n4);
+    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(grid_for(n)), dim3(256), 0, st, part, G, n, dw);
+  } else {
+    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(grid_for(n)), dim3(256), 0, st, part, nsplit, n, dw);
+  }
+  if (dbias) {
+    if (G < nsplit && a16(work)) {
+      hipLaunchKernelGGL(wgrad_fold_kernel, dim3(1, G), dim3(256), 0, st, bpart, nsplit, G, static_cast<int64_t>(c_out / 4));
+      hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(grid_for(c_out)), dim3(256), 0, st, bpart, G, static_cast<int64_t>(c_out), dbias);
+    } else {
+      hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(grid_for(c_out)), dim3(256), 0, st, bpart, nsplit, static_cast<int64_t>(c_out), dbias);
+    }
+  }
   return launched("conv3x3_wgrad");
 }
 

@@ -308,7 +308,8 @@ def unet_workload(args) -> dict:
     (seed 5) are packed, run through the network and unpacked; one "step"
     is one such pass over the whole batch. value = pixels/s; the roofline
     is the BF16 matrix-core peak, with 2 x (multiply-accumulates per pixel)
-    flops per pixel. The CPU baseline is the FP64 oracle network on one
+    flops per pixel. Also times training steps (batch 16 x 256^2) beside
+    the headline. The CPU baseline is the FP64 oracle network on one
     --cpu-unet-side square sample."""
     import torch
     from paper_2301_13601_amd import scenes, surrogate as S
@@ -357,6 +358,22 @@ def unet_workload(args) -> dict:
                      "frac": flop / sec / 1e12 / 2500.0, "traffic": None,
                      "kernel": "whole network pass (conv_fwd_pipe_kernel: ~90 % of it)"},
     }
+    # training steps (forward, relative-L2 loss, backward, Adam) at batch 16
+    # x 256^2 on pairs the library generates; flops per step: forward + data
+    # gradient (every layer but the first) + weight gradient
+    data = S.generate(64, seed=11, L=256, K=256, snaps=3)
+    S.train(net, data, steps=3, batch=16, lr=1e-3, seed=1, log_every=0)
+    torch.cuda.synchronize()
+    tsteps = max(10, args.steps)
+    t0 = time.perf_counter()
+    S.train(net, data, steps=tsteps, batch=16, lr=1e-3, seed=2, log_every=0)
+    torch.cuda.synchronize()
+    tstep = (time.perf_counter() - t0) / tsteps
+    macs = sum(sp.n_w / 4 ** sp.level * (2 if sp.name == "e0a" else 3) for sp in S.layer_specs())
+    tflop = 2.0 * macs * 16 * 256 * 256
+    rec["training"] = {"batch": 16, "side": 256, "steps": tsteps, "ms_per_step": tstep * 1e3,
+                       "macs_per_pixel": macs, "tflops": tflop / tstep / 1e12,
+                       "note": "wall clock per step, host loop included"}
     if not args.no_cpu_baseline:
         from oracle import nn_oracle as NO
         from threadpoolctl import threadpool_info
@@ -378,8 +395,9 @@ def unet_workload(args) -> dict:
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20000)
-    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default 20000; sweep 4096; unet_forward 20 passes)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed steps first (default 100; unet_forward 3)")
     ap.add_argument("--workload", default="cylinder_4096",
                     choices=["cylinder_4096", "single_256", "batch_64", "sweep", "unet_forward"])
     ap.add_argument("--train-steps", type=int, default=5000, help="sweep workload: network training steps")
@@ -398,6 +416,10 @@ def main():
     ap.add_argument("--counters", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_MIB"),
                     help="summarise rocprofv3 counter CSVs into the committed traffic record and exit")
     args = ap.parse_args()
+    if args.steps is None:
+        args.steps = {"sweep": 4096, "unet_forward": 20}.get(args.workload, 20000)
+    if args.warmup is None:
+        args.warmup = 3 if args.workload == "unet_forward" else 100
 
     if args.counters:
         rec = summarize_counters(args.counters[0], args.counters[1], int(args.counters[2]), TRAFFIC_FILE)

@@ -81,9 +81,14 @@ int qnn_conv3x3_flip(const uint16_t *w, int32_t c_out, int32_t c_in, uint16_t *w
  *   dw[co][t][ci] = sum_p dy[p][co] * x[p + offset(t)][ci]      (FP32)
  *   dbias[co]     = sum_p dy[p][co]                               (FP32, if non-NULL)
  *   x BF16 [P][c_in], dy BF16 [P][c_out]; c_in a multiple of 16, c_out a
- *   multiple of 32 (any H, W; W a multiple of 16 takes a faster path).
- *   work FP32 scratch of qnn_wgrad_work_floats(...) floats.
- * Deterministic: pixel chunks reduce in a fixed order.
+ *   multiple of 32; P * max(c_in, c_out) < 2^31 (QNN_EINVAL otherwise).
+ *   Any H, W; with x and dy 16-byte aligned and W a multiple of 8 the
+ *   staged MFMA kernel runs, otherwise a slower one reading 2-byte elements.
+ *   work FP32 scratch of qnn_wgrad_work_floats(...) floats (0 for sizes the
+ *   call would reject), 16-byte aligned for the fastest reduction; it holds
+ *   one partial dW per pixel range until the call's kernels have run.
+ * Deterministic: the pixel ranges' partial sums are folded in a fixed order,
+ * so repeated calls give bitwise equal results.
  */
 int64_t qnn_wgrad_work_floats(int32_t B, int32_t H, int32_t W, int32_t c_in, int32_t c_out);
 int qnn_conv3x3_wgrad(int32_t B, int32_t H, int32_t W, const uint16_t *x, int32_t c_in,

@@ -136,7 +136,7 @@ def make_workload(name: str, steps: int):
     return sc, desc
 
 
-def cpu_baseline(sc, sample_steps: int, sample_n: int):
+def cpu_baseline(sc, sample_steps: int, sample_n: int, pot_mode: str = "eq28", v_form: str = "printed"):
     """The FP64 oracle on the host cores, on a sample of the workload: the
     same scene generator at sample_n x sample_n for sample_steps steps."""
     from oracle import oracle as O
@@ -150,7 +150,7 @@ def cpu_baseline(sc, sample_steps: int, sample_n: int):
     q32 = q.astype(np.float32).astype(np.float64)
     threads = O.threads(0)
     t0 = time.perf_counter()
-    O.run(n32, q32, sc.delta, sample_steps, sc.pot_mode, "phys")
+    O.run(n32, q32, sc.delta, sample_steps, pot_mode, "phys", v_form=v_form)
     dt = time.perf_counter() - t0
     rate = sample_n * sample_n * sample_steps / dt
     return {"value": rate, "unit": "site-updates/s", "cores": threads, "kind": "oracle",
@@ -404,6 +404,10 @@ def main():
     ap.add_argument("--sweep-lattices", type=int, default=16, help="sweep workload: lattices of 1024 x 1024")
     ap.add_argument("--unet-lattices", type=int, default=16, help="unet_forward workload: lattices of 1024 x 1024")
     ap.add_argument("--cpu-unet-side", type=int, default=1024, help="unet_forward: side of the oracle's sample")
+    ap.add_argument("--pot-mode", choices=["eq28", "eq23"], default="eq28",
+                    help="placement of the potentials: Eq. (28) (default) or Eq. (23)")
+    ap.add_argument("--v-form", choices=["printed", "skew"], default="printed",
+                    help="potentials as printed (default) or their skew-symmetric form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="batch_64: keep the library's default launch geometry instead of the autotuned one")
@@ -442,6 +446,10 @@ def main():
         return
 
     sc, desc = make_workload(args.workload, args.steps)
+    if args.pot_mode != "eq28":
+        desc = desc.replace("Eq.(28) potentials", "Eq.(23) potentials")
+    if args.v_form != "printed":
+        desc = desc.replace(" potentials", " skew-symmetric potentials", 1)
     batch = isinstance(sc, list)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -450,10 +458,11 @@ def main():
     def make_sim(pol="both"):
         if batch:
             return qla.Batch([s.n.astype(np.float32) for s in sc], [s.q.astype(np.float32) for s in sc],
-                             [s.delta for s in sc], "eq28", "phys", device="cuda:0", stream=stream)
+                             [s.delta for s in sc], args.pot_mode, "phys", device="cuda:0", stream=stream,
+                             v_form=args.v_form)
         n32, q32 = sc.as_f32()
-        return qla.Simulation(n32, q32, sc.delta, sc.pot_mode, "phys", device="cuda:0", stream=stream,
-                              polarisation=pol)
+        return qla.Simulation(n32, q32, sc.delta, args.pot_mode, "phys", device="cuda:0", stream=stream,
+                              polarisation=pol, v_form=args.v_form)
 
     sim = make_sim()
     sites = sim.sites if batch else sc.nx * sc.ny
@@ -525,7 +534,9 @@ def main():
     # one launch advances spp steps: spp site-updates per site, 60 B each
     algo_bytes = spp * sites * ALGO_BYTES_PER_SITE
     achieved = algo_bytes / avg_launch_s / 1e9
-    traffic = measured_traffic("all") if args.workload == "cylinder_4096" else None
+    # the committed counters were taken on the default kernel instance
+    default_kernel = args.pot_mode == "eq28" and args.v_form == "printed"
+    traffic = measured_traffic("all") if args.workload == "cylinder_4096" and default_kernel else None
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "kernel": "qla_step_kernel", "avg_launch_us": avg_launch_s * 1e6, "steps_per_launch": spp,
@@ -556,11 +567,12 @@ def main():
     sim.close()
     if args.polarised_steps > 0 and not batch and is_tm_only(sc.q):
         out["polarised"] = time_polarised(make_sim, stream, sites, args.polarised_steps, args.warmup,
-                                          measured_traffic("tm") if args.workload == "cylinder_4096" else None)
+                                          measured_traffic("tm") if args.workload == "cylinder_4096" and default_kernel
+                                          else None)
     if not args.no_cpu_baseline:
         first = sc[0] if batch else sc
         sample_n = min(args.cpu_sample_n, first.nx)
-        out["cpu_baseline"] = cpu_baseline(first, args.cpu_sample_steps, sample_n)
+        out["cpu_baseline"] = cpu_baseline(first, args.cpu_sample_steps, sample_n, args.pot_mode, args.v_form)
     print(json.dumps(out), flush=True)
 
 

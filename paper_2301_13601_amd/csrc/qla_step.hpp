@@ -319,6 +319,9 @@ enum { kCoefCompute = 0, kCoefExport = 1, kCoefImport = 2 };
 // V_Y pairs of beta_1, beta_3 (8 rows); cx the collision pair of n_y and the
 // V_X pairs of beta_0, beta_2 (6 rows); fy, fx the wave-uniform flags that say
 // whether the row has any index difference.
+// Eq. (23) pairs also keep in LDS what the row at lag 4 needs after U_Y:
+// cxo, fxo point at that row's V_X pairs and flag in the cx ring, and q14
+// at the wave's four row slots of (q1, q4).
 template <int C>
 struct CoefIO {
   float* cy;   // rows of kWave * C floats, numbered by RingMap::cy
@@ -326,6 +329,9 @@ struct CoefIO {
   int* fy;
   int* fx;
   int lane;
+  const float* cxo = nullptr;
+  const int* fxo = nullptr;
+  float* q14 = nullptr;   // [4 slots][q1, q4][kWave * C]
 };
 
 // Rows of the two-step LDS ring that a field triple uses, packed: the
@@ -364,6 +370,9 @@ __device__ __forceinline__ void process_row(Pipe<C>& p, const StepArgs& g, const
   constexpr bool VEC = O::VEC, WIDE = O::WIDE, POT = O::POT, TE = O::TE, TM = O::TM;
   constexpr int MODE = O::MODE;
   constexpr bool IMPORT = CMODE == kCoefImport;
+  // Eq. (23) in a two-step pair: the lag-4 row's (q1, q4) and V_X pairs
+  // come from LDS (the cx ring and the wave's q14 slots)
+  constexpr bool LDSROW = MODE == 0 && CMODE != kCoefCompute;
 
   // ---- coefficients of row R (Eq. (24), (25)) -----------------------------
   float u[3][C];
@@ -632,14 +641,44 @@ __device__ __forceinline__ void process_row(Pipe<C>& p, const StepArgs& g, const
     // U_Y; q1, q4 are the x-sweep values kept for this row (the skew V_X
     // also rotates q2, which the y sweep has moved on, so it uses b2).
     constexpr int sl = (SLOT - 4) & 3;
+    if constexpr (LDSROW) {
+      // the two-step pair keeps these in LDS (registers are spent)
 #pragma unroll
-    for (int k = 0; k < C; ++k) {
-      o1[k] = p.q14[sl][0][k];
-      o4[k] = p.q14[sl][1][k];
-    }
-    if constexpr (POT) {
-      if (p.fx[sl]) vx_apply(p.vx[sl][0], p.vx[sl][1], p.vx[sl][2], p.vx[sl][3], o1, b2, o4, a5);
-      vy_apply(std::integral_constant<int, 4>{});
+      for (int k = 0; k < C; ++k) {
+        const int x = io.lane * C + k;
+        o1[k] = io.q14[(sl * 2 + 0) * (kWave * C) + x];
+        o4[k] = io.q14[(sl * 2 + 1) * (kWave * C) + x];
+      }
+      if constexpr (POT) {
+        if (*io.fxo != 0) {
+          float c00[C], c01[C], c20[C], c21[C];
+#pragma unroll
+          for (int k = 0; k < C; ++k) {
+            const int x = io.lane * C + k;
+            c00[k] = c01[k] = c20[k] = c21[k] = 0.0f;
+            if constexpr (TE) {
+              c00[k] = io.cxo[RingMap<O>::cx(2) * (kWave * C) + x];
+              c01[k] = io.cxo[RingMap<O>::cx(3) * (kWave * C) + x];
+            }
+            if constexpr (TM) {
+              c20[k] = io.cxo[RingMap<O>::cx(4) * (kWave * C) + x];
+              c21[k] = io.cxo[RingMap<O>::cx(5) * (kWave * C) + x];
+            }
+          }
+          vx_apply(c00, c01, c20, c21, o1, b2, o4, a5);
+        }
+        vy_apply(std::integral_constant<int, 4>{});
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < C; ++k) {
+        o1[k] = p.q14[sl][0][k];
+        o4[k] = p.q14[sl][1][k];
+      }
+      if constexpr (POT) {
+        if (p.fx[sl]) vx_apply(p.vx[sl][0], p.vx[sl][1], p.vx[sl][2], p.vx[sl][3], o1, b2, o4, a5);
+        vy_apply(std::integral_constant<int, 4>{});
+      }
     }
   }
   if constexpr (EMIT) {
@@ -686,14 +725,21 @@ __device__ __forceinline__ void process_row(Pipe<C>& p, const StepArgs& g, const
       p.th[SLOT][3][k] = sc[2][k];
     }
   }
-  if constexpr (MODE == 0 || EMIT) {
+  if constexpr (LDSROW) {
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+      const int x = io.lane * C + k;
+      if constexpr (TE) io.q14[(SLOT * 2 + 0) * (kWave * C) + x] = p.q[1][k];
+      if constexpr (TM) io.q14[(SLOT * 2 + 1) * (kWave * C) + x] = p.q[4][k];
+    }
+  } else if constexpr (MODE == 0 || EMIT) {
 #pragma unroll
     for (int k = 0; k < C; ++k) {
       if constexpr (TE) p.q14[SLOT][0][k] = p.q[1][k];
       if constexpr (TM) p.q14[SLOT][1][k] = p.q[4][k];
     }
   }
-  if constexpr (MODE == 0) {
+  if constexpr (MODE == 0 && !LDSROW) {
     if constexpr (POT) {
       p.fx[SLOT] = fx;
 #pragma unroll
@@ -902,11 +948,16 @@ __device__ __forceinline__ void march(const StepArgs& g, const uint32_t (&xo)[C]
 template <int C, class O>
 struct Ring {
   using M = RingMap<O>;
+  // cx rows kept: the consumer reads a row's four iterations after the
+  // producer wrote it, and with Eq. (23) once more four iterations later
+  static constexpr int NR = O::MODE == 0 ? 10 : 6;
   float q[2][M::NQ][kWave * C];    // the emitted row (live planes)
   float cy[2][M::NCY][kWave * C];  // its collision (n_x, n_z) and V_Y coefficients
-  float cx[6][M::NCX][kWave * C];  // collision (n_y) and V_X coefficients, by row
+  float cx[NR][M::NCX][kWave * C]; // collision (n_y) and V_X coefficients, by row
+  // Eq. (23): each wave's four row slots of (q1, q4)
+  float q14[O::MODE == 0 ? 2 * 4 * 2 * kWave * C : 1];
   int fy[2];
-  int fx[6];
+  int fx[NR];
 };
 
 template <int C, class O, int DIR>
@@ -921,7 +972,25 @@ __device__ __forceinline__ void march2(const StepArgs& g, const uint32_t (&xo)[C
   const int64_t nx64 = g.nx;
   const int iters = ((seg_h + 16) + 3) & ~3;
   float unused[6][C];
+  constexpr int NR = Ring<C, O>::NR;
+  // Eq. (23): this wave's (q1, q4) row slots start at zero, like the
+  // registers of a one-step pipeline
+  float* const q14 = O::MODE == 0 ? ring.q14 + (producer ? 0 : 4 * 2 * kWave * C) : nullptr;
+  if constexpr (O::MODE == 0) {
+    for (int e = lane; e < 4 * 2 * kWave * C; e += kWave) q14[e] = 0.0f;
+  }
   if (producer) {
+    if constexpr (O::MODE == 0) {
+      // the lag-4 rows of its first four iterations (ahead of the halo)
+      // read slots nobody has written yet: zero, as the consumer makes them
+      for (int sl = NR - 4; sl < NR; ++sl) {
+#pragma unroll
+        for (int c = 0; c < M::NCX; ++c)
+#pragma unroll
+          for (int k = 0; k < C; ++k) ring.cx[sl][c][lane * C + k] = 0.0f;
+        if (lane == 0) ring.fx[sl] = 0;
+      }
+    }
     {
       const float* q0r = g.qin + wrap_index(RA, g.ny) * nx64;
       const float* q1r = g.qin + wrap_index(RA + DIR, g.ny) * nx64;
@@ -935,7 +1004,7 @@ __device__ __forceinline__ void march2(const StepArgs& g, const uint32_t (&xo)[C
     }
     int rq = wrap_index(RA + 2 * DIR, g.ny);
     int rn = wrap_index(RA + 3 * DIR, g.ny);
-    int r6 = 0;   // iteration mod 6
+    int r6 = 0;   // iteration mod NR
     for (int i = 0; i < iters; i += 4) {
 #define QLA_ITER_A(S)                                                                          \
   {                                                                                            \
@@ -965,7 +1034,9 @@ __device__ __forceinline__ void march2(const StepArgs& g, const uint32_t (&xo)[C
     }                                                                                          \
     if (lane == 0) ring.fy[(S) & 1] = p.fy[S] ? 1 : 0;                                         \
     {                                                                                          \
-      const CoefIO<C> io{&ring.cy[(S) & 1][0][0], &ring.cx[r6][0][0], &ring.fy[(S) & 1], &ring.fx[r6], lane}; \
+      const int ro = r6 >= 4 ? r6 - 4 : r6 + NR - 4;   /* the row at lag 4 */                 \
+      const CoefIO<C> io{&ring.cy[(S) & 1][0][0], &ring.cx[r6][0][0], &ring.fy[(S) & 1], &ring.fx[r6], lane, \
+                         &ring.cx[ro][0][0], &ring.fx[ro], q14};                                    \
       process_row<C, O, DIR, S, true, 8, kCoefExport>(p, g, so, edge_lane, i + S, seg_h, y0, e, io); \
     }                                                                                          \
     _Pragma("unroll") for (int c = 0; c < 6; ++c) {                                            \
@@ -975,7 +1046,7 @@ __device__ __forceinline__ void march2(const StepArgs& g, const uint32_t (&xo)[C
     advance<C, O, true>(p, qld, nld);                                                          \
     rq = next_row<DIR>(rq, g.ny);                                                              \
     rn = next_row<DIR>(rn, g.ny);                                                              \
-    r6 = r6 == 5 ? 0 : r6 + 1;                                                                 \
+    r6 = r6 == NR - 1 ? 0 : r6 + 1;                                                            \
     __syncthreads();                                                                           \
   }
       QLA_ITER_A(0)
@@ -987,8 +1058,9 @@ __device__ __forceinline__ void march2(const StepArgs& g, const uint32_t (&xo)[C
     __syncthreads();     // the consumer's last row
   } else {
     // slots the consumer reads before the producer has written them (its
-    // first four rows, which only reach halo rows) start at zero
-    for (int sl = 2; sl < 6; ++sl) {
+    // first four rows, and with Eq. (23) the lag-4 rows of its first eight,
+    // which only reach halo rows) start at zero
+    for (int sl = O::MODE == 0 ? NR - 8 : NR - 4; sl < NR; ++sl) {
 #pragma unroll
       for (int c = 0; c < M::NCX; ++c)
 #pragma unroll
@@ -996,7 +1068,7 @@ __device__ __forceinline__ void march2(const StepArgs& g, const uint32_t (&xo)[C
       if (lane == 0) ring.fx[sl] = 0;
     }
     __syncthreads();     // the producer's first row
-    int r6 = 2;          // (iteration - 4) mod 6
+    int r6 = NR - 4;     // (iteration - 4) mod NR
     for (int i = 0; i < iters; i += 4) {
 #define QLA_ITER_B(S)                                                                          \
   {                                                                                            \
@@ -1005,10 +1077,12 @@ __device__ __forceinline__ void march2(const StepArgs& g, const uint32_t (&xo)[C
       _Pragma("unroll") for (int k = 0; k < C; ++k) p.q[c][k] = ring.q[(S) & 1][M::q(c)][lane * C + k]; \
     }                                                                                          \
     {                                                                                          \
-      const CoefIO<C> io{&ring.cy[(S) & 1][0][0], &ring.cx[r6][0][0], &ring.fy[(S) & 1], &ring.fx[r6], lane}; \
+      const int ro = r6 >= 4 ? r6 - 4 : r6 + NR - 4;   /* the row at lag 4 */                 \
+      const CoefIO<C> io{&ring.cy[(S) & 1][0][0], &ring.cx[r6][0][0], &ring.fy[(S) & 1], &ring.fx[r6], lane, \
+                         &ring.cx[ro][0][0], &ring.fx[ro], q14};                                    \
       process_row<C, O, DIR, S, false, 12, kCoefImport>(p, g, so, edge_lane, i + S, seg_h, y0, unused, io); \
     }                                                                                          \
-    r6 = r6 == 5 ? 0 : r6 + 1;                                                                 \
+    r6 = r6 == NR - 1 ? 0 : r6 + 1;                                                            \
     __syncthreads();                                                                           \
   }
       QLA_ITER_B(0)

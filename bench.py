@@ -400,7 +400,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=None, help="untimed steps first (default 100; unet_forward 3)")
     ap.add_argument("--workload", default="cylinder_4096",
                     choices=["cylinder_4096", "single_256", "batch_64", "sweep", "unet_forward"])
-    ap.add_argument("--train-steps", type=int, default=5000, help="sweep workload: network training steps")
+    ap.add_argument("--train-steps", type=int, default=20000, help="sweep workload: network training steps")
     ap.add_argument("--sweep-lattices", type=int, default=16, help="sweep workload: lattices of 1024 x 1024")
     ap.add_argument("--unet-lattices", type=int, default=16, help="unet_forward workload: lattices of 1024 x 1024")
     ap.add_argument("--cpu-unet-side", type=int, default=1024, help="unet_forward: side of the oracle's sample")

@@ -128,7 +128,11 @@ def test_conv_data_gradient(env, B, H, W, ci, co):
 
 
 @pytest.mark.parametrize("B,H,W,ci,co", [(2, 16, 32, 16, 32), (1, 32, 32, 32, 64), (2, 4, 4, 128, 128),
-                                         (1, 2, 2, 128, 128), (3, 7, 5, 16, 32)])
+                                         (1, 2, 2, 128, 128), (3, 7, 5, 16, 32),
+                                         # staged kernel: W = 24 (groups advance over several rows
+                                         # per chunk), 720 pixels (a partial last chunk), many
+                                         # pixel ranges, c_out = 96 (one 32-channel tile per block)
+                                         (3, 10, 24, 48, 32), (4, 64, 64, 32, 64), (2, 16, 32, 16, 96)])
 def test_conv_weight_gradient(env, B, H, W, ci, co):
     torch, qnn = env
     x, xr = bf(torch, rnd(8, (B, H, W, ci)))

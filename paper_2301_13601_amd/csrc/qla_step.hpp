@@ -1181,6 +1181,9 @@ __global__ void __launch_bounds__(256) qla_step_kernel(BatchArgs ba) {
   if constexpr (STEPS == 2) {
     __shared__ Ring<C, O> ring;
     const bool producer = wave == 0;
+    // the producer is on the pair's critical path (it also computes the
+    // row coefficients): let its instructions issue first on a shared SIMD
+    if (producer) __builtin_amdgcn_s_setprio(2);
     if (seg & 1)
       march2<C, O, +1>(g, xo, so, edge_lane, y0, seg_h, producer, lane, ring);
     else

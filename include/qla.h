@@ -123,8 +123,9 @@ typedef struct qla_ctx qla_ctx;   /* opaque */
  *                    about equal height across the batch, the height picked
  *                    by simulating the block schedule; qla_get_launch then
  *                    reports the tallest)
- *   waves_per_block  1..4 waves (vertically adjacent segments) per block
- *                    (default 1)
+ *   waves_per_block  1..4 waves (vertically adjacent segments) per block of
+ *                    a one-step launch (default 1); a two-step block is
+ *                    always one producer/consumer pair of waves
  *   graph_steps      steps per replayed HIP graph (rounded up to a multiple
  *                    of 2 * steps_per_pass); 1 launches every pass on its
  *                    own (default 32)

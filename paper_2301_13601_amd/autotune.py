@@ -24,7 +24,7 @@ DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "qla_autotune.js
 
 def _key(arch: str, pot_mode: str, beta_scale: str, shapes: Sequence[Tuple[int, int]]) -> str:
     h = hashlib.sha256(json.dumps(sorted(shapes)).encode()).hexdigest()[:16]
-    return f"{arch}|{pot_mode}|{beta_scale}|n{len(shapes)}|{h}|spp12"
+    return f"{arch}|{pot_mode}|{beta_scale}|n{len(shapes)}|{h}|spp12w"
 
 
 def candidates(default_seg: int, max_ny: int, steps_per_pass: int = 1) -> List[Dict[str, int]]:
@@ -36,8 +36,11 @@ def candidates(default_seg: int, max_ny: int, steps_per_pass: int = 1) -> List[D
         if 8 <= s <= max(8, max_ny + 3):
             segs.add(s)
     out = []
+    # a two-step block is always one producer/consumer pair: waves_per_block
+    # only shapes one-step launches
+    wpbs = (1, 2) if steps_per_pass == 1 else (1,)
     for s in sorted(segs):
-        for wpb in (1, 2):
+        for wpb in wpbs:
             out.append({"seg_rows": s, "waves_per_block": wpb, "graph_steps": 32,
                         "steps_per_pass": steps_per_pass})
     out.append({"seg_rows": default_seg, "waves_per_block": 1, "graph_steps": 1,

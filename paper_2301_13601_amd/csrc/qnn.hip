@@ -1154,21 +1154,25 @@ template <int MT, int NT>
 void conv_pipe_launch(int B, int H, int W, const uint16_t* x, int cin, int up, const uint16_t* w, const float* bias,
                       int act, const uint16_t* add, void* y, bool y_fp32, int y_ld, int c_store, int c_out,
                       float waves, hipStream_t st) {
-  static int resident_per_cu[2] = {0, 0};
-  static int cus = 0;
-  if (cus == 0) {
-    int dev = 0;
+  // compute units of the device and resident blocks per CU of the two
+  // instances, queried once (thread-safe static initialisation)
+  static const int cus = [] {
+    int dev = 0, n = 0;
     (void)hipGetDevice(&dev);
-    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (cus < 1) cus = 1;
-  }
-  int& res = resident_per_cu[y_fp32 ? 1 : 0];
-  if (res == 0) {
+    (void)hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev);
+    return n > 0 ? n : 1;
+  }();
+  static const int res_bf16 = [] {
     int n = 0;
-    if (y_fp32) (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, conv_fwd_pipe_kernel<MT, NT, true>, 256, 0);
-    else (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, conv_fwd_pipe_kernel<MT, NT, false>, 256, 0);
-    res = n > 0 ? n : 1;
-  }
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, conv_fwd_pipe_kernel<MT, NT, false>, 256, 0);
+    return n > 0 ? n : 1;
+  }();
+  static const int res_fp32 = [] {
+    int n = 0;
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, conv_fwd_pipe_kernel<MT, NT, true>, 256, 0);
+    return n > 0 ? n : 1;
+  }();
+  const int res = y_fp32 ? res_fp32 : res_bf16;
   const int TW = W < 64 ? W : 64;
   const int tws = TW == 64 ? 6 : (TW == 32 ? 5 : 4);
   const int TH = PipeConv<MT, NT>::kPix / TW;

@@ -1056,26 +1056,40 @@ __global__ void rel_l2_final_kernel(int B, int nb, double* __restrict__ work, do
   }
 }
 
+// One thread per pixel: the gradient of its 6 channels, zeros in the rest of
+// the d_ld-channel row (16-byte pieces when VEC: d_ld % 8 == 0, aligned).
+template <bool VEC>
 __global__ void rel_l2_grad_kernel(int B, int H, int W, int nb, const float* __restrict__ pred, int pred_ld,
                                    const float* __restrict__ target, const int32_t* __restrict__ idx_t,
                                    const float* __restrict__ scale, const double* __restrict__ work,
                                    uint16_t* __restrict__ dpred, int d_ld) {
   const int64_t HW = static_cast<int64_t>(H) * W;
-  const int64_t total = B * HW * d_ld;
-  QNN_GRID_STRIDE(i, total) {
-    const int c = static_cast<int>(i % d_ld);
-    const int64_t p = i / d_ld;
+  const int64_t total = B * HW;
+  QNN_GRID_STRIDE(p, total) {
     const int b = static_cast<int>(p / HW);
     const int64_t s = p - b * HW;
-    float g = 0.0f;
-    if (c < 6) {
-      const double den = work[2 * static_cast<int64_t>(B) * nb + 2 * b + 1];
-      const double inv = 1.0 / static_cast<double>(scale ? scale[b] : 1.0f);
-      const double t = static_cast<double>(target[((idx_t ? idx_t[b] : b) * 6 + c) * HW + s]) * inv;
+    const double den = work[2 * static_cast<int64_t>(B) * nb + 2 * b + 1];
+    const double inv = 1.0 / static_cast<double>(scale ? scale[b] : 1.0f);
+    const float* tb = target + static_cast<int64_t>(idx_t ? idx_t[b] : b) * 6 * HW + s;
+    uint16_t gv[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const double t = static_cast<double>(tb[c * HW]) * inv;
       const double d = static_cast<double>(pred[p * pred_ld + c]) - t;
-      g = den > 0.0 ? static_cast<float>(2.0 * d / (den * B)) : 0.0f;
+      gv[c] = f2bf(den > 0.0 ? static_cast<float>(2.0 * d / (den * B)) : 0.0f);
     }
-    dpred[i] = f2bf(g);
+    uint16_t* row = dpred + p * d_ld;
+    if constexpr (VEC) {
+      const u32x4 first = {static_cast<uint32_t>(gv[0]) | (static_cast<uint32_t>(gv[1]) << 16),
+                           static_cast<uint32_t>(gv[2]) | (static_cast<uint32_t>(gv[3]) << 16),
+                           static_cast<uint32_t>(gv[4]) | (static_cast<uint32_t>(gv[5]) << 16), 0u};
+      *reinterpret_cast<u32x4*>(row) = first;
+      for (int c = 8; c < d_ld; c += 8) *reinterpret_cast<u32x4*>(row + c) = u32x4{0u, 0u, 0u, 0u};
+    } else {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) row[c] = gv[c];
+      for (int c = 6; c < d_ld; ++c) row[c] = 0;
+    }
   }
 }
 
@@ -1516,8 +1530,11 @@ int qnn_rel_l2(int32_t B, int32_t H, int32_t W, const float* pred, int32_t pred_
   hipLaunchKernelGGL(rel_l2_partial_kernel, dim3(nb, B), dim3(256), 0, st, H, W, pred, pred_ld, target, idx_t, scale, work);
   hipLaunchKernelGGL(rel_l2_final_kernel, dim3(1), dim3(256), 0, st, B, nb, work, loss_out, per_sample);
   if (dpred) {
-    const int64_t total = static_cast<int64_t>(B) * H * W * d_ld;
-    hipLaunchKernelGGL(rel_l2_grad_kernel, dim3(grid_for(total)), dim3(256), 0, st, B, H, W, nb, pred, pred_ld, target, idx_t, scale, work, dpred, d_ld);
+    const int64_t pixels = static_cast<int64_t>(B) * H * W;
+    if (d_ld % 8 == 0 && a16(dpred))
+      hipLaunchKernelGGL((rel_l2_grad_kernel<true>), dim3(grid_for(pixels)), dim3(256), 0, st, B, H, W, nb, pred, pred_ld, target, idx_t, scale, work, dpred, d_ld);
+    else
+      hipLaunchKernelGGL((rel_l2_grad_kernel<false>), dim3(grid_for(pixels)), dim3(256), 0, st, B, H, W, nb, pred, pred_ld, target, idx_t, scale, work, dpred, d_ld);
   }
   return launched("rel_l2");
 }

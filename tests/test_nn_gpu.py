@@ -267,18 +267,19 @@ def test_absmax_large_and_zero_samples(env):
     np.testing.assert_array_equal(scale.cpu().numpy(), want.astype(np.float32))
 
 
-def test_relative_l2_loss_and_gradient(env):
+@pytest.mark.parametrize("pred_ld,d_ld", [(32, 32), (8, 32), (8, 6)])
+def test_relative_l2_loss_and_gradient(env, pred_ld, d_ld):
     torch, qnn = env
     B, H, W = 3, 16, 16
-    pred = torch.tensor(rnd(15, (B, H, W, 32)).astype(np.float32)).cuda()
+    pred = torch.tensor(rnd(15, (B, H, W, pred_ld)).astype(np.float32)).cuda()
     tgt = torch.tensor(rnd(16, (4, 6, H, W)).astype(np.float32)).cuda()
     idx = torch.tensor([3, 1, 0], dtype=torch.int32).cuda()
     scale = torch.tensor([2.0, 0.5, 1.0], dtype=torch.float32).cuda()
     loss = torch.zeros(1, dtype=torch.float64, device="cuda")
     per = torch.zeros(B, dtype=torch.float64, device="cuda")
     work = torch.zeros(64 * B, dtype=torch.float64, device="cuda")
-    d = torch.empty((B, H, W, 32), dtype=torch.bfloat16, device="cuda")
-    qnn.qnn_rel_l2(B, H, W, pred, 32, tgt, idx, scale, d, 32, loss, per, work)
+    d = torch.full((B, H, W, d_ld), 5.0, dtype=torch.bfloat16, device="cuda")
+    qnn.qnn_rel_l2(B, H, W, pred, pred_ld, tgt, idx, scale, d, d_ld, loss, per, work)
     p = pred.cpu().numpy().astype(np.float64)[..., :6]
     t = (tgt.cpu().numpy().astype(np.float64)[[3, 1, 0]] / np.array([2.0, 0.5, 1.0])[:, None, None, None])
     t = t.transpose(0, 2, 3, 1)

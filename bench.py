@@ -411,7 +411,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="batch_64: keep the library's default launch geometry instead of the autotuned one")
-    ap.add_argument("--cpu-sample-steps", type=int, default=6)
+    ap.add_argument("--cpu-sample-steps", type=int, default=18,
+                    help="oracle steps of the CPU baseline (about 10 s on 16 host threads at 4096^2)")
     ap.add_argument("--cpu-sample-n", type=int, default=4096)
     ap.add_argument("--polarised-steps", type=int, default=2000,
                     help="steps of the polarised (E_z triple) kernel timed after the headline run; 0 skips")

@@ -41,11 +41,16 @@ enum { QNN_ACT_NONE = 0, QNN_ACT_LEAKY = 1 };   /* leaky ReLU, negative slope 1/
  *   y      [B*H*W][y_ld], BF16 (y_fp32 = 0) or FP32 (y_fp32 = 1); channels
  *          >= c_store are not written (c_store <= c_out, c_store <= y_ld)
  * MFMA (32x32x16 BF16) implicit GEMM: M = B*H*W pixels, N = c_out,
- * K = 9*c_in; FP32 accumulation, input channels summed 16 at a time in
- * increasing order, the nine taps in order within each 16. B*H*W*max(c_in,
- * y_ld) must stay below 2^31 (QNN_EINVAL otherwise). Fastest for W = 16,
- * 32 or a multiple of 64 and, with BF16 output, c_store = c_out, y_ld a
- * multiple of 8 and y 16-byte aligned.
+ * K = 9*c_in; FP32 accumulation of 16-channel MFMA products. B*H*W*max(c_in,
+ * y_ld) must stay below 2^31 (QNN_EINVAL otherwise). The tiled kernels run
+ * for W a multiple of 16 with c_in = 32 or 48 and c_out = 32, or with c_in =
+ * 32 or 64, c_out = 64 and 256 or more tiles of 256 pixels, and otherwise
+ * for W = 16, 32 or a multiple of 64; they sum the input channels 16 at a
+ * time in increasing order, the nine taps in order within each 16, and give
+ * bitwise the same result as each other. Other widths take a per-pixel
+ * kernel that sums taps outer, channels inner (the last bits may differ).
+ * All are fastest with BF16 output when c_store = c_out, y_ld is a multiple
+ * of 8 and y is 16-byte aligned (else the per-pixel kernel runs).
  */
 int qnn_conv3x3_fwd(int32_t B, int32_t H, int32_t W, const uint16_t *x, int32_t c_in,
                     const uint16_t *w, const float *bias, int32_t c_out, int32_t act,

@@ -149,6 +149,118 @@ struct PipeConv {
   static constexpr int kSmem = kStage > kOut ? kStage : kOut;
 };
 
+// The end of a tile in the persistent convolution kernels: bias, activation
+// and the store of the block's 128*MT pixels x 32*NT channels from n0 (wave
+// w holds tile pixels (w*MT + mt)*32 .. +31), leaving acc zeroed. BF16
+// results (every channel stored, 16-byte aligned rows) pass through LDS as
+// [pixel][channel] rows from E (which may alias the staged operands: every
+// wave is waited for first) and leave as 16 bytes (8 channels of one pixel)
+// per lane, plus the skip input when given (`add`, or with ADD_REGS the
+// caller's registers add_regs[k] holding piece k of the lane's stores);
+// FP32 results are stored from the accumulators, channels below c_store
+// only.
+template <int MT, int NT, bool OUT_FP32, bool ADD_REGS = false>
+__device__ __forceinline__ void tile_epilogue(f32x16 (&acc)[MT][NT], uint16_t* E0, int tile, int tiles_x, int tiles_y,
+                                              int tw_shift, int TH, int H, int W, int n0,
+                                              const float* __restrict__ bias, int act, void* __restrict__ y, int y_ld,
+                                              int c_store, const uint16_t* __restrict__ add,
+                                              const u32x4* add_regs = nullptr) {
+  constexpr int kERow = 32 * NT + 8;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int TW = 1 << tw_shift;
+  const int tx0 = (tile % tiles_x) << tw_shift;
+  const int t2 = tile / tiles_x;
+  const int ty0 = (t2 % tiles_y) * TH;
+  const int b = t2 / tiles_y;
+  if constexpr (!OUT_FP32) {
+    __syncthreads();    // every wave is done with the staged operands
+    uint16_t* const E = E0 + wave * (32 * MT) * kERow;
+    const bool leaky = act == QNN_ACT_LEAKY;
+#pragma unroll
+    for (int jn = 0; jn < NT; ++jn) {
+      const int cl = jn * 32 + (lane & 31);
+      const float bsum = bias ? bias[n0 + cl] : 0.0f;
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+#pragma unroll
+        for (int r = 0; r < 16; r += 2) {
+          const int m = mt * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);   // rows m, m + 1
+          f32x2 v = {acc[mt][jn][r] + bsum, acc[mt][jn][r + 1] + bsum};
+          acc[mt][jn][r] = 0.0f;
+          acc[mt][jn][r + 1] = 0.0f;
+          if (leaky) {
+            // the leaky ReLU as max(v, v / 8)
+            v[0] = fmaxf(v[0], kLeakySlope * v[0]);
+            v[1] = fmaxf(v[1], kLeakySlope * v[1]);
+          }
+          // round to nearest even (the hardware conversion); the pair is
+          // taken apart as one 32-bit word (indexing the BF16 vector
+          // itself miscompiles: the second element is lost)
+          const uint32_t pk = __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
+          E[m * kERow + cl] = static_cast<uint16_t>(pk);
+          E[(m + 1) * kERow + cl] = static_cast<uint16_t>(pk >> 16);
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 2 * MT * NT; ++k) {
+      const int q = lane + 64 * k;
+      const int pm = q / (4 * NT), g = q % (4 * NT);
+      const int j = wave * 32 * MT + pm;
+      const int oy = ty0 + (j >> tw_shift);
+      if (oy < H) {
+        const int o = ((b * H + oy) * W + tx0 + (j & (TW - 1))) * y_ld + n0 + g * 8;
+        u32x4 v = *reinterpret_cast<const u32x4*>(E + pm * kERow + g * 8);
+        if (ADD_REGS || add) {
+          // the stored BF16 result plus the skip input, rounded once more
+          const u32x4 e = ADD_REGS ? add_regs[k] : *reinterpret_cast<const u32x4*>(add + o);
+#pragma unroll
+          for (int h = 0; h < 4; ++h) {
+            const float lo = bf2f(static_cast<uint16_t>(v[h])) + bf2f(static_cast<uint16_t>(e[h]));
+            const float hi = bf2f(static_cast<uint16_t>(v[h] >> 16)) + bf2f(static_cast<uint16_t>(e[h] >> 16));
+            v[h] = static_cast<uint32_t>(f2bf(lo)) | (static_cast<uint32_t>(f2bf(hi)) << 16);
+          }
+        }
+        *reinterpret_cast<u32x4*>(static_cast<uint16_t*>(y) + o) = v;
+      }
+    }
+  } else {
+    // result r of a lane is tile pixel (wave * MT + mt) * 32 + m, m = 8 (r / 4)
+    // + 4 (lane / 32) + r % 4; the 16 pixels m < 16, and the 16 pixels
+    // m >= 16, lie contiguous in one image row (TW >= 16), so each half
+    // needs one (wave-uniform) row check and one base offset
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+#pragma unroll
+      for (int hf = 0; hf < 2; ++hf) {
+        const int j0 = (wave * MT + mt) * 32 + hf * 16;
+        const int oy = ty0 + (j0 >> tw_shift);
+        const int o0 = (b * H + oy) * W + tx0 + (j0 & (TW - 1)) + (lane >> 5) * 4;
+        const bool row_in = oy < H;
+#pragma unroll
+        for (int jn = 0; jn < NT; ++jn) {
+          const int col = n0 + jn * 32 + (lane & 31);
+          const bool live = row_in && col < c_store;
+          const float bsum = (bias && col < c_store) ? bias[col] : 0.0f;
+#pragma unroll
+          for (int rr = 0; rr < 8; ++rr) {
+            const int r = hf * 8 + rr;
+            float v = acc[mt][jn][r] + bsum;
+            acc[mt][jn][r] = 0.0f;
+            if (!live) continue;
+            if (act == QNN_ACT_LEAKY) v = v > 0.0f ? v : kLeakySlope * v;
+            // (r / 4) * 8 + r % 4 - 16 hf, for r = 8 hf + rr
+            const int o = (o0 + (rr >> 2) * 8 + (rr & 3)) * y_ld + col;
+            static_cast<float*>(y)[o] = v;
+          }
+        }
+      }
+    }
+  }
+}
+
 template <int MT, int NT, bool OUT_FP32>
 __global__ void __launch_bounds__(256) conv_fwd_pipe_kernel(int H, int W, int tw_shift, int tiles,
                                                             const uint16_t* __restrict__ x, int cin,
@@ -281,111 +393,323 @@ __global__ void __launch_bounds__(256) conv_fwd_pipe_kernel(int H, int W, int tw
         for (int jn = 0; jn < NT; ++jn)
           acc[mt][jn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[mt], bv[jn], acc[mt][jn], 0, 0, 0);
     }
-    if (!OUT_FP32 && chunk == nchunks - 1) {
-      // BF16 output (every channel stored, 16-byte aligned rows): each wave
-      // writes its results to LDS as [pixel][channel] and stores 16 bytes
-      // (8 channels of one pixel) per lane
-      const int tx0 = (tile % tiles_x) << tw_shift;
-      const int t2 = tile / tiles_x;
-      const int ty0 = (t2 % tiles_y) * TH;
-      const int b = t2 / tiles_y;
-      __syncthreads();    // every wave is done with the staged operands
-      uint16_t* const E = smem + wave * (32 * MT) * PC::kERow;
-      const bool leaky = act == QNN_ACT_LEAKY;
-#pragma unroll
-      for (int jn = 0; jn < NT; ++jn) {
-        const int cl = jn * 32 + (lane & 31);
-        const float bsum = bias ? bias[n0 + cl] : 0.0f;
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-#pragma unroll
-          for (int r = 0; r < 16; r += 2) {
-            const int m = mt * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);   // rows m, m + 1
-            f32x2 v = {acc[mt][jn][r] + bsum, acc[mt][jn][r + 1] + bsum};
-            acc[mt][jn][r] = 0.0f;
-            acc[mt][jn][r + 1] = 0.0f;
-            if (leaky) {
-              // the leaky ReLU as max(v, v / 8)
-              v[0] = fmaxf(v[0], kLeakySlope * v[0]);
-              v[1] = fmaxf(v[1], kLeakySlope * v[1]);
-            }
-            // round to nearest even (the hardware conversion); the pair is
-            // taken apart as one 32-bit word (indexing the BF16 vector
-            // itself miscompiles: the second element is lost)
-            const uint32_t pk = __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
-            E[m * PC::kERow + cl] = static_cast<uint16_t>(pk);
-            E[(m + 1) * PC::kERow + cl] = static_cast<uint16_t>(pk >> 16);
-          }
-        }
-      }
-      __syncthreads();
-#pragma unroll
-      for (int k = 0; k < 2 * MT * NT; ++k) {
-        const int q = lane + 64 * k;
-        const int pm = q / (4 * NT), g = q % (4 * NT);
-        const int j = wave * 32 * MT + pm;
-        const int oy = ty0 + (j >> tw_shift);
-        if (oy < H) {
-          const int o = ((b * H + oy) * W + tx0 + (j & (TW - 1))) * y_ld + n0 + g * 8;
-          u32x4 v = *reinterpret_cast<const u32x4*>(E + pm * PC::kERow + g * 8);
-          if (add) {
-            // the stored BF16 result plus the skip input, rounded once more
-            const u32x4 e = *reinterpret_cast<const u32x4*>(add + o);
-#pragma unroll
-            for (int h = 0; h < 4; ++h) {
-              const float lo = bf2f(static_cast<uint16_t>(v[h])) + bf2f(static_cast<uint16_t>(e[h]));
-              const float hi = bf2f(static_cast<uint16_t>(v[h] >> 16)) + bf2f(static_cast<uint16_t>(e[h] >> 16));
-              v[h] = static_cast<uint32_t>(f2bf(lo)) | (static_cast<uint32_t>(f2bf(hi)) << 16);
-            }
-          }
-          *reinterpret_cast<u32x4*>(static_cast<uint16_t*>(y) + o) = v;
-        }
-      }
-    } else if (OUT_FP32 && chunk == nchunks - 1) {
-      const int tx0 = (tile % tiles_x) << tw_shift;
-      const int t2 = tile / tiles_x;
-      const int ty0 = (t2 % tiles_y) * TH;
-      const int b = t2 / tiles_y;
-      // result r of a lane is tile pixel (wave * MT + mt) * 32 + m, m = 8 (r / 4)
-      // + 4 (lane / 32) + r % 4; the 16 pixels m < 16, and the 16 pixels
-      // m >= 16, lie contiguous in one image row (TW >= 16), so each half
-      // needs one (wave-uniform) row check and one base offset
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-#pragma unroll
-        for (int hf = 0; hf < 2; ++hf) {
-          const int j0 = (wave * MT + mt) * 32 + hf * 16;
-          const int oy = ty0 + (j0 >> tw_shift);
-          const int o0 = (b * H + oy) * W + tx0 + (j0 & (TW - 1)) + (lane >> 5) * 4;
-          const bool row_in = oy < H;
-#pragma unroll
-          for (int jn = 0; jn < NT; ++jn) {
-            const int col = n0 + jn * 32 + (lane & 31);
-            const bool live = row_in && col < c_store;
-            const float bsum = (bias && col < c_store) ? bias[col] : 0.0f;
-#pragma unroll
-            for (int rr = 0; rr < 8; ++rr) {
-              const int r = hf * 8 + rr;
-              float v = acc[mt][jn][r] + bsum;
-              acc[mt][jn][r] = 0.0f;
-              if (!live) continue;
-              if (act == QNN_ACT_LEAKY) v = v > 0.0f ? v : kLeakySlope * v;
-              // (r / 4) * 8 + r % 4 - 16 hf, for r = 8 hf + rr
-              const int o = (o0 + (rr >> 2) * 8 + (rr & 3)) * y_ld + col;
-              if constexpr (OUT_FP32)
-                static_cast<float*>(y)[o] = v;
-              else
-                static_cast<uint16_t*>(y)[o] = f2bf(v);
-            }
-          }
-        }
-      }
-    }
+    if (chunk == nchunks - 1)
+      tile_epilogue<MT, NT, OUT_FP32>(acc, smem, tile, tiles_x, tiles_y, tw_shift, TH, H, W, n0, bias, act, y, y_ld,
+                                      c_store, add);
     tile = ntile;
     chunk = nchunk;
   }
 }
 #undef QNN_PIPE_FETCH
+
+// ---------------------------------------------------------------------------
+// Forward 3x3 circular convolution with resident weights, for the layers
+// whose weights fit in LDS beside one tile: 16*KC input channels (KC in
+// {2, 3, 4}), 32*NT output channels a block (NT in {1, 2}), tiles of 256
+// pixels (TH x TW, TW in {16, 32}). The block's weights are staged once and
+// stay; each step stages a whole tile with all its input channels, loaded
+// into registers during the previous tile's MFMAs. The only memory traffic
+// of a step is then the tile itself, in one batch of loads two to four
+// times as large as a step of the pipelined kernel has in flight, with a
+// fraction of its barriers: these layers are bound by the bytes a CU keeps
+// in flight, not by the matrix cores. The MFMAs run in the pipelined
+// kernel's order (16-channel chunks outer, taps inner), so the results are
+// bitwise the same.
+// ---------------------------------------------------------------------------
+template <int KC, int NT>
+struct ResConv {
+  static constexpr int kCin = 16 * KC;
+  static constexpr int kParts = 2 * KC;              // 16-byte pieces per staged row
+  static constexpr int kRow = 16 * KC + 8;           // LDS elements per row: an odd multiple of 16 bytes
+  // pieces are dealt to lanes in groups of kGroup rows x 2 pieces (KC = 3) or
+  // kGroup rows x 1 piece, which puts every eight consecutive lanes on eight
+  // distinct 16-byte bank groups
+  static constexpr int kGroup = KC == 3 ? 4 : 8;
+  static constexpr int kMaxIn = 10 * 34;             // staged pixels for TW = 32 (TW = 16: 18 * 18)
+  static constexpr int kInItems = ((kMaxIn + kGroup - 1) / kGroup * kGroup * kParts + 255) / 256;
+  static constexpr int kWRows = 9 * 32 * NT;
+  static constexpr int kIn = kMaxIn * kRow;
+  static constexpr int kOut = 4 * 64 * (32 * NT + 8);   // the epilogue's [pixel][channel] rows
+  static constexpr int kSmem = kWRows * kRow + (kIn > kOut ? kIn : kOut);
+};
+
+template <int KC, int NT, bool OUT_FP32>
+__global__ void __launch_bounds__(256) conv_fwd_res_kernel(int H, int W, int tw_shift, int tiles,
+                                                           const uint16_t* __restrict__ x,
+                                                           const uint16_t* __restrict__ w,
+                                                           const float* __restrict__ bias, int act,
+                                                           void* __restrict__ y, int y_ld, int c_store,
+                                                           const uint16_t* __restrict__ add) {
+  using RC = ResConv<KC, NT>;
+  constexpr int cin = RC::kCin;
+  __shared__ __attribute__((aligned(16))) uint16_t smem[RC::kSmem];
+  uint16_t* const lw = smem;                         // [co * 9 + tap][cin], resident
+  uint16_t* const lin = smem + RC::kWRows * RC::kRow;   // staged tile; then the epilogue's rows
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int TW = 1 << tw_shift;
+  const int TH = 256 >> tw_shift;
+  const int TWp = TW + 2;
+  const int nstaged = (TH + 2) * TWp;
+  const int tiles_x = W >> tw_shift;
+  const int tiles_y = (H + TH - 1) / TH;
+  const int n0 = blockIdx.y * 32 * NT;
+  const int kh = (lane >> 5) * 8;
+  const bool tall = TH > H;    // rows of a tile may wrap more than once
+
+  // this thread's staging pieces, fixed for the whole kernel: piece i is
+  // part (i / G) % parts of staged row G (i / (G parts)) + i % G (G rows per
+  // group; with KC = 3 the parts pair up within eight lanes), packed as tile
+  // row << 16 | column << 4 | part; a negative LDS offset marks a piece past
+  // the end
+  int in_p[RC::kInItems], in_d[RC::kInItems];
+#pragma unroll
+  for (int k = 0; k < RC::kInItems; ++k) {
+    const int i = threadIdx.x + 256 * k;
+    const int pi = (i / (RC::kGroup * RC::kParts)) * RC::kGroup + i % RC::kGroup;
+    const int part = (i / RC::kGroup) % RC::kParts;
+    const int r = pi / TWp;
+    in_p[k] = (r << 16) | ((pi - r * TWp) << 4) | part;
+    in_d[k] = pi < nstaged ? pi * RC::kRow + part * 8 : -1;
+  }
+  // this lane's A rows (tile pixels 64 * wave + 32 * mt + lane % 32) and B
+  // row (output channel lane % 32 of each 32-channel group)
+  int a_off[2];
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt) {
+    const int j = (wave * 2 + mt) * 32 + (lane & 31);
+    a_off[mt] = ((j >> tw_shift) * TWp + (j & (TW - 1))) * RC::kRow + kh;
+  }
+  const int b_off = (lane & 31) * 9 * RC::kRow + kh;
+
+  u32x4 sin[RC::kInItems];
+  auto fetch = [&](int t) {
+    const int tx0 = (t % tiles_x) << tw_shift;
+    const int t2 = t / tiles_x;
+    const int ty0 = (t2 % tiles_y) * TH;
+    const int img = (t2 / tiles_y) * H;
+#pragma unroll
+    for (int k = 0; k < RC::kInItems; ++k) {
+      if (in_d[k] >= 0) {
+        int yy = ty0 - 1 + (in_p[k] >> 16);
+        if (tall)
+          yy = (yy + H) % H;
+        else
+          yy = yy < 0 ? yy + H : (yy >= H ? yy - H : yy);
+        int xx = tx0 - 1 + ((in_p[k] >> 4) & 0xfff);
+        xx = xx < 0 ? xx + W : (xx >= W ? xx - W : xx);
+        // element offsets fit 31 bits (checked on the host)
+        sin[k] = *reinterpret_cast<const u32x4*>(x + ((img + yy) * W + xx) * cin + (in_p[k] & 15) * 8);
+      }
+    }
+  };
+
+  int tile = blockIdx.x;   // the grid never exceeds the tile count
+  fetch(tile);
+  // the block's weights, rows (co, tap) contiguous in memory
+  for (int i = threadIdx.x; i < RC::kWRows * RC::kParts; i += 256) {
+    const int row = i / RC::kParts, part = i - row * RC::kParts;
+    *reinterpret_cast<u32x4*>(lw + row * RC::kRow + part * 8) =
+        *reinterpret_cast<const u32x4*>(w + (n0 * 9 + row) * cin + part * 8);
+  }
+  f32x16 acc[2][NT];
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+    for (int jn = 0; jn < NT; ++jn)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[mt][jn][r] = 0.0f;
+
+  for (; tile < tiles; tile += gridDim.x) {
+    __syncthreads();      // every wave is done with the previous tile's LDS
+#pragma unroll
+    for (int k = 0; k < RC::kInItems; ++k)
+      if (in_d[k] >= 0) *reinterpret_cast<u32x4*>(lin + in_d[k]) = sin[k];
+    __syncthreads();
+    if (tile + static_cast<int>(gridDim.x) < tiles) fetch(tile + gridDim.x);
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc) {
+#pragma unroll
+      for (int tap = 0; tap < 9; ++tap) {
+        const int dy = tap / 3, dx = tap % 3;   // offsets +1 into the staged tile
+        bf16x8 a[2], bv[NT];
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+          a[mt] = *reinterpret_cast<const bf16x8*>(lin + a_off[mt] + (dy * TWp + dx) * RC::kRow + kc * 16);
+#pragma unroll
+        for (int jn = 0; jn < NT; ++jn)
+          bv[jn] = *reinterpret_cast<const bf16x8*>(lw + b_off + (jn * 32 * 9 + tap) * RC::kRow + kc * 16);
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+          for (int jn = 0; jn < NT; ++jn)
+            acc[mt][jn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[mt], bv[jn], acc[mt][jn], 0, 0, 0);
+      }
+    }
+    tile_epilogue<2, NT, OUT_FP32>(acc, lin, tile, tiles_x, tiles_y, tw_shift, TH, H, W, n0, bias, act, y, y_ld,
+                                   c_store, add);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Forward 3x3 circular convolution of a nearest-neighbour upsampled input,
+// plus an optional skip input: y = act(bias + conv3x3(up2(x), w)) + add, for
+// 64 input channels (x at half resolution) and 32 output channels a block,
+// tiles of 256 output pixels (TH x TW, TW in {16, 32}). Tile rows and
+// columns start at even coordinates, so the tile reads the fixed
+// half-resolution window (TH/2 + 2) x (TW/2 + 2), staged once per tile
+// instead of once per output pixel it feeds (a quarter of the bytes); the
+// tap offsets into that window depend on the lane only. The weights stay
+// in LDS, and each step loads the next tile's window and skip input into
+// registers during the current tile's MFMAs, the skip input in the pieces
+// the epilogue stores. Bitwise the same as the pipelined kernel with the
+// upsampling folded in (same MFMA operands, same order).
+// ---------------------------------------------------------------------------
+struct UpConv {
+  static constexpr int kCin = 64;
+  static constexpr int kParts = 8;                     // 16-byte pieces per staged row
+  static constexpr int kRow = kCin + 8;                // an odd multiple of 16 bytes
+  static constexpr int kMaxIn = 6 * 18;                // TW = 32: 6 x 18 (TW = 16: 10 x 10)
+  static constexpr int kInItems = ((kMaxIn + 7) / 8 * 8 * kParts + 255) / 256;
+  static constexpr int kWRows = 9 * 32;
+  static constexpr int kIn = kMaxIn * kRow;
+  static constexpr int kOut = 4 * 64 * 40;
+  static constexpr int kSmem = kWRows * kRow + (kIn > kOut ? kIn : kOut);
+};
+
+template <bool ADD>
+__global__ void __launch_bounds__(256) conv_fwd_up_kernel(int H, int W, int tw_shift, int tiles,
+                                                          const uint16_t* __restrict__ x,
+                                                          const uint16_t* __restrict__ w,
+                                                          const float* __restrict__ bias, int act,
+                                                          uint16_t* __restrict__ y, int y_ld,
+                                                          const uint16_t* __restrict__ add) {
+  using UC = UpConv;
+  constexpr int cin = UC::kCin;
+  __shared__ __attribute__((aligned(16))) uint16_t smem[UC::kSmem];
+  uint16_t* const lw = smem;                           // [co * 9 + tap][cin], resident
+  uint16_t* const lin = smem + UC::kWRows * UC::kRow;  // staged window; then the epilogue's rows
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int TW = 1 << tw_shift;
+  const int TH = 256 >> tw_shift;
+  const int Hh = H >> 1, Wh = W >> 1;                  // the input's size
+  const int SW = TW / 2 + 2;                           // staged window: (TH/2 + 2) x SW
+  const int nstaged = (TH / 2 + 2) * SW;
+  const int tiles_x = W >> tw_shift;
+  const int tiles_y = (H + TH - 1) / TH;
+  const int n0 = blockIdx.y * 32;
+  const int kh = (lane >> 5) * 8;
+  const bool tall = TH / 2 + 2 > Hh;   // window rows may wrap more than once
+
+  // staging pieces: piece i is part (i / 8) % 8 of window row 8 (i / 64) +
+  // i % 8 (eight consecutive lanes on eight rows 144 bytes apart: distinct
+  // bank groups), packed as row << 16 | column << 4 | part
+  int in_p[UC::kInItems], in_d[UC::kInItems];
+#pragma unroll
+  for (int k = 0; k < UC::kInItems; ++k) {
+    const int i = threadIdx.x + 256 * k;
+    const int pi = (i >> 6) * 8 + (i & 7), part = (i >> 3) & 7;
+    const int r = pi / SW;
+    in_p[k] = (r << 16) | ((pi - r * SW) << 4) | part;
+    in_d[k] = pi < nstaged ? pi * UC::kRow + part * 8 : -1;
+  }
+  // this lane's A rows: tile pixel (r, c) reads, for tap (dy, dx), the
+  // window element (((r + dy) >> 1) + 1, ((c + dx) >> 1) + 1)
+  int a_row[2][3], a_col[2][3];
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt) {
+    const int j = (wave * 2 + mt) * 32 + (lane & 31);
+    const int r = j >> tw_shift, c = j & (TW - 1);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      a_row[mt][d] = (((r + d - 1) >> 1) + 1) * SW * UC::kRow;
+      a_col[mt][d] = (((c + d - 1) >> 1) + 1) * UC::kRow + kh;
+    }
+  }
+  const int b_off = (lane & 31) * 9 * UC::kRow + kh;
+
+  u32x4 sin[UC::kInItems];
+  u32x4 sadd[ADD ? 4 : 1];
+  auto fetch = [&](int t) {
+    const int tx0 = (t % tiles_x) << tw_shift;
+    const int t2 = t / tiles_x;
+    const int ty0 = (t2 % tiles_y) * TH;
+    const int b = t2 / tiles_y;
+#pragma unroll
+    for (int k = 0; k < UC::kInItems; ++k) {
+      if (in_d[k] >= 0) {
+        int hy = (ty0 >> 1) - 1 + (in_p[k] >> 16);
+        if (tall)
+          hy = (hy + Hh) % Hh;
+        else
+          hy = hy < 0 ? hy + Hh : (hy >= Hh ? hy - Hh : hy);
+        int hx = (tx0 >> 1) - 1 + ((in_p[k] >> 4) & 0xfff);
+        hx = hx < 0 ? hx + Wh : (hx >= Wh ? hx - Wh : hx);
+        // element offsets fit 31 bits (checked on the host)
+        sin[k] = *reinterpret_cast<const u32x4*>(x + ((b * Hh + hy) * Wh + hx) * cin + (in_p[k] & 15) * 8);
+      }
+    }
+    if constexpr (ADD) {
+      // the skip input in the epilogue's store pieces: piece k of a lane is
+      // channels 8 (q % 4) .. +7 of tile pixel 64 wave + q / 4, q = lane + 64 k
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int q = lane + 64 * k;
+        const int j = wave * 64 + (q >> 2);
+        const int oy = ty0 + (j >> tw_shift);
+        if (oy < H)
+          sadd[k] = *reinterpret_cast<const u32x4*>(
+              add + ((b * H + oy) * W + tx0 + (j & (TW - 1))) * y_ld + n0 + (q & 3) * 8);
+      }
+    }
+  };
+
+  int tile = blockIdx.x;   // the grid never exceeds the tile count
+  fetch(tile);
+  for (int i = threadIdx.x; i < UC::kWRows * UC::kParts; i += 256) {
+    const int row = i / UC::kParts, part = i - row * UC::kParts;
+    *reinterpret_cast<u32x4*>(lw + row * UC::kRow + part * 8) =
+        *reinterpret_cast<const u32x4*>(w + (n0 * 9 + row) * cin + part * 8);
+  }
+  f32x16 acc[2][1];
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[mt][0][r] = 0.0f;
+
+  for (; tile < tiles; tile += gridDim.x) {
+    __syncthreads();      // every wave is done with the previous tile's LDS
+#pragma unroll
+    for (int k = 0; k < UC::kInItems; ++k)
+      if (in_d[k] >= 0) *reinterpret_cast<u32x4*>(lin + in_d[k]) = sin[k];
+    u32x4 cadd[ADD ? 4 : 1];
+    if constexpr (ADD) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) cadd[k] = sadd[k];
+    }
+    __syncthreads();
+    if (tile + static_cast<int>(gridDim.x) < tiles) fetch(tile + gridDim.x);
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) {
+#pragma unroll
+      for (int tap = 0; tap < 9; ++tap) {
+        const int dy = tap / 3, dx = tap % 3;
+        bf16x8 a[2];
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+          a[mt] = *reinterpret_cast<const bf16x8*>(lin + a_row[mt][dy] + a_col[mt][dx] + kc * 16);
+        const bf16x8 bv = *reinterpret_cast<const bf16x8*>(lw + b_off + tap * UC::kRow + kc * 16);
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+          acc[mt][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[mt], bv, acc[mt][0], 0, 0, 0);
+      }
+    }
+    // (BF16 results store every channel: no c_store)
+    tile_epilogue<2, 1, false, ADD>(acc, lin, tile, tiles_x, tiles_y, tw_shift, TH, H, W, n0, bias, act, y, y_ld, 0,
+                                    nullptr, cadd);
+  }
+}
 
 __global__ void flip_kernel(const uint16_t* __restrict__ w, int cout, int cin, uint16_t* __restrict__ wt) {
   const int64_t n = static_cast<int64_t>(cout) * 9 * cin;
@@ -1224,6 +1548,105 @@ bool conv_pipe(int mt, int nt, int B, int H, int W, const uint16_t* x, int cin, 
   return false;
 }
 
+// The resident-weight kernel (16*KC input channels, 32*NT output channels
+// a block): tiles of TW = tw columns (32, or 16) x 256 / tw rows, grid.x
+// persistent blocks as many as stay resident at once (times `waves`, capped
+// by the tile count).
+template <int KC, int NT>
+void conv_res_launch(int B, int H, int W, const uint16_t* x, const uint16_t* w, const float* bias, int act,
+                     const uint16_t* add, void* y, bool y_fp32, int y_ld, int c_store, int c_out, int tw,
+                     float waves, hipStream_t st) {
+  static const int cus = [] {
+    int dev = 0, n = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev);
+    return n > 0 ? n : 1;
+  }();
+  static const int res_bf16 = [] {
+    int n = 0;
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, conv_fwd_res_kernel<KC, NT, false>, 256, 0);
+    return n > 0 ? n : 1;
+  }();
+  static const int res_fp32 = [] {
+    int n = 0;
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, conv_fwd_res_kernel<KC, NT, true>, 256, 0);
+    return n > 0 ? n : 1;
+  }();
+  const int res = y_fp32 ? res_fp32 : res_bf16;
+  const int tws = tw == 32 ? 5 : 4;
+  const int TH = 256 / tw;
+  const int64_t tiles = static_cast<int64_t>(B) * (W / tw) * ((H + TH - 1) / TH);
+  const int gy = c_out / (32 * NT);
+  int64_t gx = static_cast<int64_t>(waves * cus * res / gy);
+  if (gx < 1) gx = 1;
+  if (gx > tiles) gx = tiles;
+  dim3 grid(static_cast<unsigned>(gx), gy);
+  if (y_fp32)
+    hipLaunchKernelGGL((conv_fwd_res_kernel<KC, NT, true>), grid, dim3(256), 0, st, H, W, tws,
+                       static_cast<int>(tiles), x, w, bias, act, y, y_ld, c_store, add);
+  else
+    hipLaunchKernelGGL((conv_fwd_res_kernel<KC, NT, false>), grid, dim3(256), 0, st, H, W, tws,
+                       static_cast<int>(tiles), x, w, bias, act, y, y_ld, c_store, add);
+}
+
+// the resident-weight kernel where it applies: 32 or 48 input channels with
+// 32-channel blocks (nt = 1), 32 or 64 with 64-channel blocks (nt = 2), W a
+// multiple of the tile width tw (32 or 16), and BF16 results leaving in
+// 16-byte pieces as in the pipelined kernel
+bool conv_res(int B, int H, int W, const uint16_t* x, int cin, const uint16_t* w, const float* bias, int act,
+              const uint16_t* add, void* y, bool y_fp32, int y_ld, int c_store, int c_out, int nt, int tw,
+              float waves, hipStream_t st) {
+  if ((tw != 16 && tw != 32) || W % tw || (nt != 1 && nt != 2) || c_out % (32 * nt)) return false;
+  if (!y_fp32 && (c_store != c_out || y_ld % 8 || (reinterpret_cast<uintptr_t>(y) & 15))) return false;
+#define QNN_RES(C, N)                                                                                             \
+  if (cin == 16 * (C) && nt == (N)) {                                                                            \
+    conv_res_launch<C, N>(B, H, W, x, w, bias, act, add, y, y_fp32, y_ld, c_store, c_out, tw, waves, st);        \
+    return true;                                                                                                  \
+  }
+  QNN_RES(2, 1) QNN_RES(3, 1) QNN_RES(2, 2) QNN_RES(4, 2)
+#undef QNN_RES
+  return false;
+}
+
+// The upsampling kernel (64 input channels at half resolution, BF16 out):
+// tiles of tw columns (32, or 16) x 256 / tw rows, grid.x persistent blocks
+// as many as stay resident at once (capped by the tile count).
+bool conv_up(int B, int H, int W, const uint16_t* x, int cin, const uint16_t* w, const float* bias, int act,
+             const uint16_t* add, uint16_t* y, int y_ld, int c_out, int tw, float waves, hipStream_t st) {
+  if ((tw != 16 && tw != 32) || W % tw || (H & 1) || cin != UpConv::kCin || c_out % 32 || y_ld % 8) return false;
+  static const int cus = [] {
+    int dev = 0, n = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev);
+    return n > 0 ? n : 1;
+  }();
+  static const int res_add = [] {
+    int n = 0;
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, conv_fwd_up_kernel<true>, 256, 0);
+    return n > 0 ? n : 1;
+  }();
+  static const int res_plain = [] {
+    int n = 0;
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, conv_fwd_up_kernel<false>, 256, 0);
+    return n > 0 ? n : 1;
+  }();
+  const int tws = tw == 32 ? 5 : 4;
+  const int TH = 256 / tw;
+  const int64_t tiles = static_cast<int64_t>(B) * (W / tw) * ((H + TH - 1) / TH);
+  const int gy = c_out / 32;
+  int64_t gx = static_cast<int64_t>(waves * cus * (add ? res_add : res_plain) / gy);
+  if (gx < 1) gx = 1;
+  if (gx > tiles) gx = tiles;
+  dim3 grid(static_cast<unsigned>(gx), gy);
+  if (add)
+    hipLaunchKernelGGL((conv_fwd_up_kernel<true>), grid, dim3(256), 0, st, H, W, tws, static_cast<int>(tiles), x, w,
+                       bias, act, y, y_ld, add);
+  else
+    hipLaunchKernelGGL((conv_fwd_up_kernel<false>), grid, dim3(256), 0, st, H, W, tws, static_cast<int>(tiles), x, w,
+                       bias, act, y, y_ld, add);
+  return true;
+}
+
 // Tile shape of the pipelined kernel for a layer: 256-pixel tiles x 64
 // channels when that gives two or more blocks per CU, else 128-pixel tiles;
 // the layers with the fewest pixels split the channels finest.
@@ -1301,7 +1724,19 @@ int qnn_conv3x3_fwd(int32_t B, int32_t H, int32_t W, const uint16_t* x, int32_t 
   if (P64 * (c_in > y_ld ? c_in : y_ld) >= (int64_t{1} << 31)) return bad("conv3x3_fwd: tensor too large");
   const int P = static_cast<int>(P64);
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  // the pipelined kernel where its tiles fit, else the pixel-list kernel
+  // the resident-weight kernel for the layers whose weights fit in LDS
+  // (with 64 output channels only for grids of a tile per CU or more: it
+  // keeps fewer blocks resident), else the pipelined kernel where its tiles
+  // fit, else the pixel-list kernel
+  {
+    const int tw = W % 32 == 0 ? 32 : 16;
+    const int64_t tiles = static_cast<int64_t>(B) * (W / tw) * ((H + 256 / tw - 1) / (256 / tw));
+    const bool narrow = c_out == 32;
+    const bool wide = c_out == 64 && (c_in == 32 || c_in == 64) && tiles >= 256;
+    if ((narrow || wide) && conv_res(B, H, W, x, c_in, w, bias, act, nullptr, y, y_fp32 != 0, y_ld, c_store, c_out,
+                                     c_in == 64 ? 2 : 1, tw, 1.0f, st))
+      return launched("conv3x3_fwd");
+  }
   if (pipe_fits(W)) {
     int m, n;
     pipe_shape(B, H, W, c_out, m, n);
@@ -1334,10 +1769,15 @@ int qnn_conv3x3_fwd_fused(int32_t B, int32_t H, int32_t W, const uint16_t* x, in
     return bad("conv3x3_fwd_fused: tensors must be 16-byte aligned");
   const int64_t P64 = static_cast<int64_t>(B) * H * W;
   if (P64 * (c_in > y_ld ? c_in : y_ld) >= (int64_t{1} << 31)) return bad("conv3x3_fwd_fused: tensor too large");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  // the upsampling kernel for 64 -> 32 channels (16-wide tiles: the skip
+  // input's rows are read in shorter runs but the window is smaller), else
+  // the pipelined kernel
+  if (up && c_out == 32 && conv_up(B, H, W, x, c_in, w, bias, act, add, y, y_ld, c_out, 16, 1.0f, st))
+    return launched("conv3x3_fwd_fused");
   int m, n;
   pipe_shape(B, H, W, c_out, m, n);
-  if (!conv_pipe(m, n, B, H, W, x, c_in, up, w, bias, act, add, y, false, y_ld, c_out, c_out, 1.0f,
-                 static_cast<hipStream_t>(hip_stream)))
+  if (!conv_pipe(m, n, B, H, W, x, c_in, up, w, bias, act, add, y, false, y_ld, c_out, c_out, 1.0f, st))
     return bad("conv3x3_fwd_fused: shape not supported");
   return launched("conv3x3_fwd_fused");
 }
@@ -1351,6 +1791,23 @@ int qnn_conv3x3_fwd_cfg(int32_t B, int32_t H, int32_t W, const uint16_t* x, int3
                  static_cast<hipStream_t>(hip_stream)))
     return bad("conv3x3_fwd_cfg: geometry not supported");
   return launched("conv3x3_fwd_cfg");
+}
+
+int qnn_conv3x3_fwd_res_cfg(int32_t B, int32_t H, int32_t W, const uint16_t* x, int32_t c_in, const uint16_t* w,
+                            const float* bias, int32_t c_out, int32_t act, void* y, int32_t y_fp32, int32_t y_ld,
+                            int32_t c_store, int32_t nt, int32_t tw, float waves, void* hip_stream) {
+  if (!conv_res(B, H, W, x, c_in, w, bias, act, nullptr, y, y_fp32 != 0, y_ld, c_store, c_out, nt, tw, waves,
+                static_cast<hipStream_t>(hip_stream)))
+    return bad("conv3x3_fwd_res_cfg: geometry not supported");
+  return launched("conv3x3_fwd_res_cfg");
+}
+
+int qnn_conv3x3_fwd_up_cfg(int32_t B, int32_t H, int32_t W, const uint16_t* x, int32_t c_in, const uint16_t* w,
+                           const float* bias, int32_t c_out, int32_t act, const uint16_t* add, uint16_t* y,
+                           int32_t y_ld, int32_t tw, float waves, void* hip_stream) {
+  if (!conv_up(B, H, W, x, c_in, w, bias, act, add, y, y_ld, c_out, tw, waves, static_cast<hipStream_t>(hip_stream)))
+    return bad("conv3x3_fwd_up_cfg: geometry not supported");
+  return launched("conv3x3_fwd_up_cfg");
 }
 #endif
 

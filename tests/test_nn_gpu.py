@@ -41,7 +41,15 @@ def rnd(seed, shape, scale=1.0):
                                          # channels)
                                          (64, 15, 64, 48, 32), (600, 7, 16, 32, 128), (2, 256, 128, 128, 128),
                                          (512, 3, 32, 64, 64), (600, 1, 16, 16, 32), (2, 168, 192, 32, 96),
-                                         (16, 32, 32, 128, 128), (3, 20, 64, 16, 64)])
+                                         (16, 32, 32, 128, 128), (3, 20, 64, 16, 64),
+                                         # resident-weight kernel (32 or 48 -> 32 channels, W a
+                                         # multiple of 16): 32- and 16-wide tiles, partial and
+                                         # over-tall tiles, more tiles than resident blocks
+                                         (64, 64, 64, 32, 32), (48, 64, 64, 48, 32), (3, 20, 48, 32, 32),
+                                         (2, 5, 96, 48, 32),
+                                         # and for 64 output channels (256 tiles or more): two
+                                         # 32-channel blocks a tile, or one 64-channel block
+                                         (24, 48, 64, 32, 64), (16, 64, 80, 64, 64)])
 @pytest.mark.parametrize("act", [0, 1])
 def test_conv_forward(env, B, H, W, ci, co, act):
     torch, qnn = env
@@ -82,7 +90,16 @@ def test_conv_forward_partial_store(env, W):
 
 
 @pytest.mark.parametrize("B,H,W,ci,co", [(2, 32, 64, 64, 32), (3, 16, 16, 128, 128), (2, 20, 32, 32, 64),
-                                         (16, 64, 128, 128, 64)])
+                                         (16, 64, 128, 128, 64),
+                                         # the separate convolution on the resident-weight kernel,
+                                         # the fused one on the pipelined kernel
+                                         (4, 24, 64, 32, 32), (2, 40, 32, 48, 32), (40, 32, 64, 32, 32),
+                                         # 64 -> 32 channels upsampled: the half-resolution window
+                                         # kernel (window taller than the input, more tiles than
+                                         # resident blocks)
+                                         (3, 6, 32, 64, 32), (5, 2, 16, 64, 32), (24, 64, 128, 64, 32),
+                                         # 64 output channels: resident-weight kernel vs pipelined
+                                         (24, 48, 64, 32, 64), (16, 64, 64, 64, 64)])
 @pytest.mark.parametrize("up", [0, 1])
 @pytest.mark.parametrize("with_add", [False, True])
 def test_conv_fused_is_bitwise_the_separate_steps(env, B, H, W, ci, co, up, with_add):

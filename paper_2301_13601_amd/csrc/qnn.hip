@@ -157,8 +157,8 @@ struct PipeConv {
 // wave is waited for first) and leave as 16 bytes (8 channels of one pixel)
 // per lane, plus the skip input when given (`add`, or with ADD_REGS the
 // caller's registers add_regs[k] holding piece k of the lane's stores);
-// FP32 results are stored from the accumulators, channels below c_store
-// only.
+// FP32 results pass through E too, 32 pixels of a wave at a time, and only
+// channels below c_store are stored.
 template <int MT, int NT, bool OUT_FP32, bool ADD_REGS = false>
 __device__ __forceinline__ void tile_epilogue(f32x16 (&acc)[MT][NT], uint16_t* E0, int tile, int tiles_x, int tiles_y,
                                               int tw_shift, int TH, int H, int W, int n0,
@@ -227,35 +227,35 @@ __device__ __forceinline__ void tile_epilogue(f32x16 (&acc)[MT][NT], uint16_t* E
       }
     }
   } else {
-    // result r of a lane is tile pixel (wave * MT + mt) * 32 + m, m = 8 (r / 4)
-    // + 4 (lane / 32) + r % 4; the 16 pixels m < 16, and the 16 pixels
-    // m >= 16, lie contiguous in one image row (TW >= 16), so each half
-    // needs one (wave-uniform) row check and one base offset
+    // FP32 results, one 32-pixel half of the wave's pixels at a time: the
+    // wave writes them to its rows of E as [pixel][channel] (rows of 32 NT +
+    // 4 floats), then stores the channels n0 .. c_store - 1 of each pixel,
+    // consecutive lanes on consecutive elements
+    constexpr int kFRow = 32 * NT + 4;
+    float* const E = reinterpret_cast<float*>(E0) + wave * 32 * kFRow;
+    const int cnt = c_store - n0 < 32 * NT ? c_store - n0 : 32 * NT;   // channels stored (may be <= 0)
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
+      __syncthreads();    // the staged operands, or the previous half's rows, are free
 #pragma unroll
-      for (int hf = 0; hf < 2; ++hf) {
-        const int j0 = (wave * MT + mt) * 32 + hf * 16;
-        const int oy = ty0 + (j0 >> tw_shift);
-        const int o0 = (b * H + oy) * W + tx0 + (j0 & (TW - 1)) + (lane >> 5) * 4;
-        const bool row_in = oy < H;
+      for (int jn = 0; jn < NT; ++jn) {
+        const int cl = jn * 32 + (lane & 31);
+        const float bsum = (bias && cl < cnt) ? bias[n0 + cl] : 0.0f;
 #pragma unroll
-        for (int jn = 0; jn < NT; ++jn) {
-          const int col = n0 + jn * 32 + (lane & 31);
-          const bool live = row_in && col < c_store;
-          const float bsum = (bias && col < c_store) ? bias[col] : 0.0f;
-#pragma unroll
-          for (int rr = 0; rr < 8; ++rr) {
-            const int r = hf * 8 + rr;
-            float v = acc[mt][jn][r] + bsum;
-            acc[mt][jn][r] = 0.0f;
-            if (!live) continue;
-            if (act == QNN_ACT_LEAKY) v = v > 0.0f ? v : kLeakySlope * v;
-            // (r / 4) * 8 + r % 4 - 16 hf, for r = 8 hf + rr
-            const int o = (o0 + (rr >> 2) * 8 + (rr & 3)) * y_ld + col;
-            static_cast<float*>(y)[o] = v;
-          }
+        for (int r = 0; r < 16; ++r) {
+          float v = acc[mt][jn][r] + bsum;
+          acc[mt][jn][r] = 0.0f;
+          if (act == QNN_ACT_LEAKY) v = v > 0.0f ? v : kLeakySlope * v;
+          E[((r >> 2) * 8 + (lane >> 5) * 4 + (r & 3)) * kFRow + cl] = v;
         }
+      }
+      __syncthreads();
+      for (int i = lane; i < 32 * cnt; i += 64) {
+        const int pm = i / cnt, c = i - pm * cnt;
+        const int j = (wave * MT + mt) * 32 + pm;
+        const int oy = ty0 + (j >> tw_shift);
+        if (oy < H)
+          static_cast<float*>(y)[((b * H + oy) * W + tx0 + (j & (TW - 1))) * y_ld + n0 + c] = E[pm * kFRow + c];
       }
     }
   }
@@ -271,6 +271,7 @@ __global__ void __launch_bounds__(256) conv_fwd_pipe_kernel(int H, int W, int tw
   using PC = PipeConv<MT, NT>;
   // staged input tile and weights; at the end of a tile, the waves' outputs
   __shared__ __attribute__((aligned(16))) uint16_t smem[PC::kSmem];
+  static_assert(PC::kSmem >= 4 * 32 * (32 * NT + 4) * 2, "FP32 epilogue rows exceed the staging area");
   uint16_t* const lin = smem;
   uint16_t* const lw = smem + PC::kMaxIn * kStageStride;
   const int lane = threadIdx.x & 63;
@@ -445,6 +446,8 @@ __global__ void __launch_bounds__(256) conv_fwd_res_kernel(int H, int W, int tw_
   __shared__ __attribute__((aligned(16))) uint16_t smem[RC::kSmem];
   uint16_t* const lw = smem;                         // [co * 9 + tap][cin], resident
   uint16_t* const lin = smem + RC::kWRows * RC::kRow;   // staged tile; then the epilogue's rows
+  static_assert(RC::kSmem - RC::kWRows * RC::kRow >= 4 * 32 * (32 * NT + 4) * 2,
+                "FP32 epilogue rows exceed the staging area");
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int TW = 1 << tw_shift;
@@ -1258,45 +1261,63 @@ __global__ void absmax_fix_kernel(int B, float* __restrict__ scale) {
 
 constexpr int kInCh = 48;
 
-// One thread per pixel: its 48 input channels (see qnn_pack_input) as six
-// 16-byte stores. dx, dy: the displacement reduced to [0, W) and [0, H).
-// Element offsets within a sample's planes fit 31 bits (checked on the host).
-__global__ void pack_input_kernel(int B, int H, int W, const float* __restrict__ q, const int32_t* __restrict__ idx_q,
-                                  const float* __restrict__ n, const int32_t* __restrict__ idx_n,
-                                  const float* __restrict__ scale, float n_shift, float n_scale, int dx, int dy,
-                                  uint16_t* __restrict__ x) {
+// One thread per pixel computes its 48 input channels (see qnn_pack_input).
+// dx, dy: the displacement reduced to [0, W) and [0, H). Element offsets
+// within a sample's planes fit 31 bits (checked on the host).
+__global__ void __launch_bounds__(256) pack_input_kernel(int B, int H, int W, const float* __restrict__ q,
+                                                         const int32_t* __restrict__ idx_q,
+                                                         const float* __restrict__ n,
+                                                         const int32_t* __restrict__ idx_n,
+                                                         const float* __restrict__ scale, float n_shift,
+                                                         float n_scale, int dx, int dy, uint16_t* __restrict__ x) {
+  // a block packs 256 consecutive pixels at a time: each thread computes
+  // its pixel's 48 channels into LDS, then the block stores the 24 KiB run
+  // in 16-byte pieces, consecutive lanes on consecutive pieces
+  __shared__ __attribute__((aligned(16))) uint16_t stage[256 * kInCh];
   const int HW = H * W;
   const int64_t total = static_cast<int64_t>(B) * HW;
-  QNN_GRID_STRIDE(p, total) {
-    const int b = static_cast<int>(p / HW);
-    const int s = static_cast<int>(p - static_cast<int64_t>(b) * HW);
-    const int yy = s / W, xx = s - (s / W) * W;
-    const float* qb = q + static_cast<int64_t>(idx_q ? idx_q[b] : b) * 6 * HW;
-    const float* nb = n + static_cast<int64_t>(idx_n ? idx_n[b] : b) * 3 * HW;
-    const float sc = scale[b];
-    // the four displaced source pixels, periodic
-    const int xm = xx >= dx ? xx - dx : xx - dx + W;
-    const int xp = xx + dx < W ? xx + dx : xx + dx - W;
-    const int ym = yy >= dy ? yy - dy : yy - dy + H;
-    const int yp = yy + dy < H ? yy + dy : yy + dy - H;
-    const int src[4] = {yy * W + xm, yy * W + xp, ym * W + xx, yp * W + xx};
-    float v[kInCh];
+  for (int64_t p0 = static_cast<int64_t>(blockIdx.x) * 256; p0 < total; p0 += static_cast<int64_t>(gridDim.x) * 256) {
+    const int64_t p = p0 + threadIdx.x;
+    __syncthreads();    // the previous run's stores have read the stage
+    if (p < total) {
+      const int b = static_cast<int>(p / HW);
+      const int s = static_cast<int>(p - static_cast<int64_t>(b) * HW);
+      const int yy = s / W, xx = s - (s / W) * W;
+      const float* qb = q + static_cast<int64_t>(idx_q ? idx_q[b] : b) * 6 * HW;
+      const float* nb = n + static_cast<int64_t>(idx_n ? idx_n[b] : b) * 3 * HW;
+      const float sc = scale[b];
+      // the four displaced source pixels, periodic
+      const int xm = xx >= dx ? xx - dx : xx - dx + W;
+      const int xp = xx + dx < W ? xx + dx : xx + dx - W;
+      const int ym = yy >= dy ? yy - dy : yy - dy + H;
+      const int yp = yy + dy < H ? yy + dy : yy + dy - H;
+      const int src[4] = {yy * W + xm, yy * W + xp, ym * W + xx, yp * W + xx};
+      float v[kInCh];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) v[c] = qb[c * HW + s] / sc;
+      for (int c = 0; c < 6; ++c) v[c] = qb[c * HW + s] / sc;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) v[6 + c] = (nb[c * HW + s] - n_shift) / n_scale;
+      for (int c = 0; c < 3; ++c) v[6 + c] = (nb[c * HW + s] - n_shift) / n_scale;
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
+      for (int k = 0; k < 4; ++k)
 #pragma unroll
-      for (int c = 0; c < 6; ++c) v[9 + 6 * k + c] = qb[c * HW + src[k]] / sc;
+        for (int c = 0; c < 6; ++c) v[9 + 6 * k + c] = qb[c * HW + src[k]] / sc;
 #pragma unroll
-    for (int c = 33; c < kInCh; ++c) v[c] = 0.0f;
+      for (int c = 33; c < kInCh; ++c) v[c] = 0.0f;
 #pragma unroll
-    for (int g = 0; g < kInCh / 8; ++g) {
-      float f[8];
+      for (int g = 0; g < kInCh / 8; ++g) {
+        float f[8];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) f[j] = v[8 * g + j];
-      st8(x + p * kInCh + 8 * g, f);
+        for (int j = 0; j < 8; ++j) f[j] = v[8 * g + j];
+        st8(stage + threadIdx.x * kInCh + 8 * g, f);
+      }
+    }
+    __syncthreads();
+    const int64_t pieces = (total - p0 < 256 ? total - p0 : 256) * (kInCh / 8);
+#pragma unroll
+    for (int k = 0; k < kInCh / 8; ++k) {
+      const int i = threadIdx.x + 256 * k;
+      if (i < pieces)
+        *reinterpret_cast<uint4*>(x + p0 * kInCh + 8 * i) = *reinterpret_cast<const uint4*>(stage + 8 * i);
     }
   }
 }

@@ -259,6 +259,29 @@ def test_pack_absmax_unpack(env):
     np.testing.assert_array_equal(out.cpu().numpy(), want.astype(np.float32))
 
 
+def test_pack_input_ragged_and_large(env):
+    """A pixel count that leaves a partial run of 256, and a batch large
+    enough that blocks pack several runs (rows sampled)."""
+    torch, qnn = env
+    for B, H, W, d, rows in ((3, 7, 45, 4, None), (5, 1024, 1024, 77, (0, 1, 76, 77, 500, 947, 1023))):
+        qn = rnd(40, (B, 6, H, W)).astype(np.float32)
+        nnp = (2 + rnd(41, (B, 3, H, W))).astype(np.float32)
+        q, nn = torch.tensor(qn).cuda(), torch.tensor(nnp).cuda()
+        scale = torch.empty(B, dtype=torch.float32, device="cuda")
+        qnn.qnn_absmax(B, H, W, q, None, scale)
+        x = torch.empty((B, H, W, 48), dtype=torch.bfloat16, device="cuda")
+        qnn.qnn_pack_input(B, H, W, q, None, nn, None, scale, 2.0, 1.0, d, x)
+        sc = scale.cpu().numpy()
+        sel = slice(None) if rows is None else list(rows)
+        xs = x[:, sel].float().cpu().numpy()
+        for b in range(B):
+            f = (qn[b] / np.float32(sc[b])).transpose(1, 2, 0)
+            want = np.concatenate([f, (nnp[b] - np.float32(2.0)).transpose(1, 2, 0), np.roll(f, d, axis=1),
+                                   np.roll(f, -d, axis=1), np.roll(f, d, axis=0), np.roll(f, -d, axis=0),
+                                   np.zeros((H, W, 15), np.float32)], axis=2)
+            np.testing.assert_array_equal(xs[b], N.bf16_round(want[sel]))
+
+
 def check_pack(xs, qn, nnp, want_scale, d):
     for b, (iq, inn) in enumerate(zip([4, 0, 2, 2], [1, 0, 2, 1])):
         f = (qn[iq] / np.float32(want_scale[b])).transpose(1, 2, 0)          # (H, W, 6)

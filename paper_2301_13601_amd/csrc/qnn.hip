@@ -557,8 +557,8 @@ __global__ void __launch_bounds__(256) conv_fwd_res_kernel(int H, int W, int tw_
 // ---------------------------------------------------------------------------
 // Forward 3x3 circular convolution of a nearest-neighbour upsampled input,
 // plus an optional skip input: y = act(bias + conv3x3(up2(x), w)) + add, for
-// 64 input channels (x at half resolution) and 32 output channels a block,
-// tiles of 256 output pixels (TH x TW, TW in {16, 32}). Tile rows and
+// 16*KC input channels (x at half resolution; KC in {4, 8}) and 32 output
+// channels a block, tiles of 256 output pixels (TH x TW, TW in {16, 32}). Tile rows and
 // columns start at even coordinates, so the tile reads the fixed
 // half-resolution window (TH/2 + 2) x (TW/2 + 2), staged once per tile
 // instead of once per output pixel it feeds (a quarter of the bytes); the
@@ -568,9 +568,10 @@ __global__ void __launch_bounds__(256) conv_fwd_res_kernel(int H, int W, int tw_
 // the epilogue stores. Bitwise the same as the pipelined kernel with the
 // upsampling folded in (same MFMA operands, same order).
 // ---------------------------------------------------------------------------
+template <int KC>
 struct UpConv {
-  static constexpr int kCin = 64;
-  static constexpr int kParts = 8;                     // 16-byte pieces per staged row
+  static constexpr int kCin = 16 * KC;
+  static constexpr int kParts = 2 * KC;                // 16-byte pieces per staged row
   static constexpr int kRow = kCin + 8;                // an odd multiple of 16 bytes
   static constexpr int kMaxIn = 6 * 18;                // TW = 32: 6 x 18 (TW = 16: 10 x 10)
   static constexpr int kInItems = ((kMaxIn + 7) / 8 * 8 * kParts + 255) / 256;
@@ -580,14 +581,14 @@ struct UpConv {
   static constexpr int kSmem = kWRows * kRow + (kIn > kOut ? kIn : kOut);
 };
 
-template <bool ADD>
+template <int KC, bool ADD>
 __global__ void __launch_bounds__(256) conv_fwd_up_kernel(int H, int W, int tw_shift, int tiles,
                                                           const uint16_t* __restrict__ x,
                                                           const uint16_t* __restrict__ w,
                                                           const float* __restrict__ bias, int act,
                                                           uint16_t* __restrict__ y, int y_ld,
                                                           const uint16_t* __restrict__ add) {
-  using UC = UpConv;
+  using UC = UpConv<KC>;
   constexpr int cin = UC::kCin;
   __shared__ __attribute__((aligned(16))) uint16_t smem[UC::kSmem];
   uint16_t* const lw = smem;                           // [co * 9 + tap][cin], resident
@@ -605,14 +606,15 @@ __global__ void __launch_bounds__(256) conv_fwd_up_kernel(int H, int W, int tw_s
   const int kh = (lane >> 5) * 8;
   const bool tall = TH / 2 + 2 > Hh;   // window rows may wrap more than once
 
-  // staging pieces: piece i is part (i / 8) % 8 of window row 8 (i / 64) +
-  // i % 8 (eight consecutive lanes on eight rows 144 bytes apart: distinct
-  // bank groups), packed as row << 16 | column << 4 | part
+  // staging pieces: piece i is part (i / 8) % parts of window row
+  // 8 (i / (8 parts)) + i % 8 (eight consecutive lanes on eight rows an odd
+  // number of 16-byte units apart: distinct bank groups), packed as row << 16
+  // | column << 4 | part
   int in_p[UC::kInItems], in_d[UC::kInItems];
 #pragma unroll
   for (int k = 0; k < UC::kInItems; ++k) {
     const int i = threadIdx.x + 256 * k;
-    const int pi = (i >> 6) * 8 + (i & 7), part = (i >> 3) & 7;
+    const int pi = (i / (8 * UC::kParts)) * 8 + (i & 7), part = (i >> 3) % UC::kParts;
     const int r = pi / SW;
     in_p[k] = (r << 16) | ((pi - r * SW) << 4) | part;
     in_d[k] = pi < nstaged ? pi * UC::kRow + part * 8 : -1;
@@ -694,7 +696,7 @@ __global__ void __launch_bounds__(256) conv_fwd_up_kernel(int H, int W, int tw_s
     __syncthreads();
     if (tile + static_cast<int>(gridDim.x) < tiles) fetch(tile + gridDim.x);
 #pragma unroll
-    for (int kc = 0; kc < 4; ++kc) {
+    for (int kc = 0; kc < KC; ++kc) {
 #pragma unroll
       for (int tap = 0; tap < 9; ++tap) {
         const int dy = tap / 3, dx = tap % 3;
@@ -1629,12 +1631,12 @@ bool conv_res(int B, int H, int W, const uint16_t* x, int cin, const uint16_t* w
   return false;
 }
 
-// The upsampling kernel (64 input channels at half resolution, BF16 out):
-// tiles of tw columns (32, or 16) x 256 / tw rows, grid.x persistent blocks
-// as many as stay resident at once (capped by the tile count).
-bool conv_up(int B, int H, int W, const uint16_t* x, int cin, const uint16_t* w, const float* bias, int act,
-             const uint16_t* add, uint16_t* y, int y_ld, int c_out, int tw, float waves, hipStream_t st) {
-  if ((tw != 16 && tw != 32) || W % tw || (H & 1) || cin != UpConv::kCin || c_out % 32 || y_ld % 8) return false;
+// The upsampling kernel (16*KC input channels at half resolution, BF16
+// out): tiles of tw columns (32, or 16) x 256 / tw rows, grid.x persistent
+// blocks as many as stay resident at once (capped by the tile count).
+template <int KC>
+void conv_up_launch(int B, int H, int W, const uint16_t* x, const uint16_t* w, const float* bias, int act,
+                    const uint16_t* add, uint16_t* y, int y_ld, int c_out, int tw, float waves, hipStream_t st) {
   static const int cus = [] {
     int dev = 0, n = 0;
     (void)hipGetDevice(&dev);
@@ -1643,12 +1645,12 @@ bool conv_up(int B, int H, int W, const uint16_t* x, int cin, const uint16_t* w,
   }();
   static const int res_add = [] {
     int n = 0;
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, conv_fwd_up_kernel<true>, 256, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, conv_fwd_up_kernel<KC, true>, 256, 0);
     return n > 0 ? n : 1;
   }();
   static const int res_plain = [] {
     int n = 0;
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, conv_fwd_up_kernel<false>, 256, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, conv_fwd_up_kernel<KC, false>, 256, 0);
     return n > 0 ? n : 1;
   }();
   const int tws = tw == 32 ? 5 : 4;
@@ -1660,11 +1662,22 @@ bool conv_up(int B, int H, int W, const uint16_t* x, int cin, const uint16_t* w,
   if (gx > tiles) gx = tiles;
   dim3 grid(static_cast<unsigned>(gx), gy);
   if (add)
-    hipLaunchKernelGGL((conv_fwd_up_kernel<true>), grid, dim3(256), 0, st, H, W, tws, static_cast<int>(tiles), x, w,
-                       bias, act, y, y_ld, add);
+    hipLaunchKernelGGL((conv_fwd_up_kernel<KC, true>), grid, dim3(256), 0, st, H, W, tws, static_cast<int>(tiles), x,
+                       w, bias, act, y, y_ld, add);
   else
-    hipLaunchKernelGGL((conv_fwd_up_kernel<false>), grid, dim3(256), 0, st, H, W, tws, static_cast<int>(tiles), x, w,
-                       bias, act, y, y_ld, add);
+    hipLaunchKernelGGL((conv_fwd_up_kernel<KC, false>), grid, dim3(256), 0, st, H, W, tws, static_cast<int>(tiles), x,
+                       w, bias, act, y, y_ld, add);
+}
+
+bool conv_up(int B, int H, int W, const uint16_t* x, int cin, const uint16_t* w, const float* bias, int act,
+             const uint16_t* add, uint16_t* y, int y_ld, int c_out, int tw, float waves, hipStream_t st) {
+  if ((tw != 16 && tw != 32) || W % tw || (H & 1) || c_out % 32 || y_ld % 8) return false;
+  if (cin == 64)
+    conv_up_launch<4>(B, H, W, x, w, bias, act, add, y, y_ld, c_out, tw, waves, st);
+  else if (cin == 128)
+    conv_up_launch<8>(B, H, W, x, w, bias, act, add, y, y_ld, c_out, tw, waves, st);
+  else
+    return false;
   return true;
 }
 
@@ -1791,10 +1804,13 @@ int qnn_conv3x3_fwd_fused(int32_t B, int32_t H, int32_t W, const uint16_t* x, in
   const int64_t P64 = static_cast<int64_t>(B) * H * W;
   if (P64 * (c_in > y_ld ? c_in : y_ld) >= (int64_t{1} << 31)) return bad("conv3x3_fwd_fused: tensor too large");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  // the upsampling kernel for 64 -> 32 channels (16-wide tiles: the skip
-  // input's rows are read in shorter runs but the window is smaller), else
-  // the pipelined kernel
-  if (up && c_out == 32 && conv_up(B, H, W, x, c_in, w, bias, act, add, y, y_ld, c_out, 16, 1.0f, st))
+  // the upsampling kernel for 64 -> 32 channels, and for 128 -> 64 on 2^20
+  // pixels or more (below that its one block per CU falls behind), with
+  // 16-wide tiles (the skip input's rows are read in shorter runs but the
+  // window is smaller); else the pipelined kernel
+  const bool up_narrow = c_in == 64 && c_out == 32;
+  const bool up_wide = c_in == 128 && c_out == 64 && P64 >= (int64_t{1} << 20);
+  if (up && (up_narrow || up_wide) && conv_up(B, H, W, x, c_in, w, bias, act, add, y, y_ld, c_out, 16, 1.0f, st))
     return launched("conv3x3_fwd_fused");
   int m, n;
   pipe_shape(B, H, W, c_out, m, n);

@@ -99,7 +99,9 @@ def test_conv_forward_partial_store(env, W):
                                          # resident blocks)
                                          (3, 6, 32, 64, 32), (5, 2, 16, 64, 32), (24, 64, 128, 64, 32),
                                          # 64 output channels: resident-weight kernel vs pipelined
-                                         (24, 48, 64, 32, 64), (16, 64, 64, 64, 64)])
+                                         (24, 48, 64, 32, 64), (16, 64, 64, 64, 64),
+                                         # 128 -> 64 upsampled on 2^20 pixels: the window kernel
+                                         (16, 256, 256, 128, 64)])
 @pytest.mark.parametrize("up", [0, 1])
 @pytest.mark.parametrize("with_add", [False, True])
 def test_conv_fused_is_bitwise_the_separate_steps(env, B, H, W, ci, co, up, with_add):

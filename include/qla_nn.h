@@ -90,8 +90,8 @@ int qnn_conv3x3_flip(const uint16_t *w, int32_t c_out, int32_t c_in, uint16_t *w
  *   Any H, W; with x and dy 16-byte aligned and W a multiple of 8 the
  *   staged MFMA kernel runs, otherwise a slower one reading 2-byte elements.
  *   work FP32 scratch of qnn_wgrad_work_floats(...) floats (0 for sizes the
- *   call would reject), 16-byte aligned for the fastest reduction; it holds
- *   one partial dW per pixel range until the call's kernels have run.
+ *   call would reject); it holds one partial dW (and dbias) per pixel range
+ *   until the call's kernels have run.
  * Deterministic: the pixel ranges' partial sums are folded in a fixed order,
  * so repeated calls give bitwise equal results.
  */

@@ -973,33 +973,41 @@ __global__ void __launch_bounds__(256) wgrad_lds_kernel(int P, int H, int W, con
   }
 }
 
-// First pass of the partial-sum reduction, in place: part holds nsplit
-// slices of n floats; slice g (< G) becomes the sum of slices g, g + G,
-// g + 2G, ... (in that order), element by element. Each element of a group
-// is read and written by one thread only. n % 4 == 0, 16-byte aligned.
-__global__ void wgrad_fold_kernel(float* __restrict__ part, int nsplit, int G, int64_t n4) {
-  const int g = blockIdx.y;
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n4;
-       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    float4 s = reinterpret_cast<const float4*>(part + static_cast<int64_t>(g) * 4 * n4)[i];
-    for (int k = g + G; k < nsplit; k += G) {
-      const float4 v = reinterpret_cast<const float4*>(part + static_cast<int64_t>(k) * 4 * n4)[i];
-      s.x += v.x;
-      s.y += v.y;
-      s.z += v.z;
-      s.w += v.w;
-    }
-    reinterpret_cast<float4*>(part + static_cast<int64_t>(g) * 4 * n4)[i] = s;
-  }
-}
-
-__global__ void wgrad_reduce_kernel(const float* __restrict__ part, int nsplit, int64_t n,
-                                    float* __restrict__ out) {
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
-       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+// The weight (and bias) gradient from the per-range partial sums, in one
+// pass and a fixed order. part holds nsplit slices of n floats (bpart
+// nsplit slices of nb); with G = min(nsplit, 16) groups, group g sums the
+// slices g, g + G, g + 2G, ... in that order, and the result is 0 plus the
+// groups in increasing g. A block owns 64 elements (weights first, then
+// bias): its four waves take four groups each, reading 64 consecutive
+// floats per load, and the first wave adds the groups up from LDS.
+__global__ void __launch_bounds__(256) wgrad_sum_kernel(const float* __restrict__ part,
+                                                        const float* __restrict__ bpart, int nsplit, int G,
+                                                        int64_t n, int nb, float* __restrict__ dw,
+                                                        float* __restrict__ dbias) {
+  __shared__ float gs[16][64];
+  const int e = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * 64 + e;
+  const bool live = i < n + nb;
+  const bool is_w = i < n;
+  const float* src = is_w ? part + i : bpart + (i - n);
+  const int64_t stride = is_w ? n : nb;
+  for (int g = w; g < G; g += 4) {
     float s = 0.0f;
-    for (int k = 0; k < nsplit; ++k) s += part[static_cast<int64_t>(k) * n + i];
-    out[i] = s;
+    if (live) {
+      s = src[static_cast<int64_t>(g) * stride];
+#pragma unroll 4
+      for (int k = g + G; k < nsplit; k += G) s += src[static_cast<int64_t>(k) * stride];
+    }
+    gs[g][e] = s;
+  }
+  __syncthreads();
+  if (w == 0 && live) {
+    float s = 0.0f;
+    for (int g = 0; g < G; ++g) s += gs[g][e];
+    if (is_w)
+      dw[i] = s;
+    else
+      dbias[i - n] = s;
   }
 }
 
@@ -1894,26 +1902,13 @@ int qnn_conv3x3_wgrad(int32_t B, int32_t H, int32_t W, const uint16_t* x, int32_
     else
       hipLaunchKernelGGL((wgrad_kernel<false>), dim3(c_out / 32, (K + 31) / 32, nsplit), dim3(256), 0, st, P, H, W, x, c_in, dy, c_out, part, dbias ? bpart : nullptr);
   }
-  // fold the partial sums: groups of splits in parallel (in place), then
-  // the group sums; a fixed order, so the result is the same on every call
+  // the partial sums, weights and bias in one pass (a fixed order, so the
+  // result is the same on every call)
   const int64_t n = static_cast<int64_t>(c_out) * K;
+  const int nb = dbias ? c_out : 0;
   const int G = nsplit < 16 ? nsplit : 16;
-  if (G < nsplit && a16(work)) {
-    const int64_t n4 = n / 4;
-    const int gx = static_cast<int>(std::min<int64_t>((n4 + 255) / 256, 1024));
-    hipLaunchKernelGGL(wgrad_fold_kernel, dim3(gx, G), dim3(256), 0, st, part, nsplit, G, n4);
-    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(grid_for(n)), dim3(256), 0, st, part, G, n, dw);
-  } else {
-    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(grid_for(n)), dim3(256), 0, st, part, nsplit, n, dw);
-  }
-  if (dbias) {
-    if (G < nsplit && a16(work)) {
-      hipLaunchKernelGGL(wgrad_fold_kernel, dim3(1, G), dim3(256), 0, st, bpart, nsplit, G, static_cast<int64_t>(c_out / 4));
-      hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(grid_for(c_out)), dim3(256), 0, st, bpart, G, static_cast<int64_t>(c_out), dbias);
-    } else {
-      hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(grid_for(c_out)), dim3(256), 0, st, bpart, nsplit, static_cast<int64_t>(c_out), dbias);
-    }
-  }
+  hipLaunchKernelGGL(wgrad_sum_kernel, dim3(static_cast<unsigned>((n + nb + 63) / 64)), dim3(256), 0, st, part, bpart,
+                     nsplit, G, n, nb, dw, dbias);
   return launched("conv3x3_wgrad");
 }
 

@@ -1694,12 +1694,17 @@ bool conv_up(int B, int H, int W, const uint16_t* x, int cin, const uint16_t* w,
 // the layers with the fewest pixels split the channels finest.
 // Weight-gradient geometry of the staged kernel: a = 32-channel output tiles
 // per block (2 when c_out allows), and the pixel range of a block (pps, a
-// multiple of the 128-pixel chunk) chosen so that about 1024 blocks cover
-// the chip; nsplit ranges (each leaves one partial dW in the workspace).
+// multiple of the 128-pixel chunk) chosen so that the blocks fill the chip
+// once: at most kWgradResident of them, the blocks both instances keep
+// resident on the 256 CUs of an MI355X (three each, bound by LDS). Past that
+// a second, partial round of blocks would take as long as the first. nsplit
+// ranges (each leaves one partial dW in the workspace).
+constexpr int64_t kWgradResident = 3 * 256;
+
 void wgrad_split(int P, int c_in, int c_out, int& a, int& nsplit, int& pps) {
   a = (c_out % 64 == 0) ? 2 : 1;
   const int64_t blocks_xy = static_cast<int64_t>(c_out / (32 * a)) * ((9 * c_in + 127) / 128);
-  int64_t want = (1024 + blocks_xy - 1) / blocks_xy;
+  int64_t want = kWgradResident / blocks_xy;
   const int64_t chunks = (P + kWtChunk - 1) / kWtChunk;
   if (want > chunks) want = chunks;
   if (want < 1) want = 1;

@@ -307,6 +307,15 @@ def test_absmax_large_and_zero_samples(env):
     want = np.abs(q.cpu().numpy()).reshape(B, -1).max(axis=1)
     want[1] = 1.0
     np.testing.assert_array_equal(scale.cpu().numpy(), want.astype(np.float32))
+    # an odd pixel count (6 H W not a multiple of 4) and an unaligned view:
+    # the 4-byte-load form
+    for B, H, W, off in ((3, 7, 9, 0), (2, 8, 8, 1)):
+        buf = torch.tensor(rnd(22, B * 6 * H * W + off).astype(np.float32)).cuda()
+        q = buf[off:].view(B, 6, H, W)
+        scale = torch.empty(B, dtype=torch.float32, device="cuda")
+        qnn.qnn_absmax(B, H, W, q, None, scale)
+        want = np.abs(q.cpu().numpy()).reshape(B, -1).max(axis=1)
+        np.testing.assert_array_equal(scale.cpu().numpy(), want.astype(np.float32))
 
 
 @pytest.mark.parametrize("pred_ld,d_ld", [(32, 32), (8, 32), (8, 6)])

@@ -1528,6 +1528,18 @@ __global__ void compare_final_kernel(int B, const double* __restrict__ work, dou
   en[b] = rr > 0.0 ? fabs(aa - rr) / rr : aa;
 }
 
+// compute units of the device the library first launched on, queried once
+// (thread-safe static initialisation)
+int cu_count() {
+  static const int cus = [] {
+    int dev = 0, n = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev);
+    return n > 0 ? n : 1;
+  }();
+  return cus;
+}
+
 // Launch of the pipelined forward kernel: grid.y channel groups of 32*NT;
 // grid.x persistent blocks, as many as stay resident at once (times
 // `waves`, capped by the tile count).
@@ -1535,14 +1547,9 @@ template <int MT, int NT>
 void conv_pipe_launch(int B, int H, int W, const uint16_t* x, int cin, int up, const uint16_t* w, const float* bias,
                       int act, const uint16_t* add, void* y, bool y_fp32, int y_ld, int c_store, int c_out,
                       float waves, hipStream_t st) {
-  // compute units of the device and resident blocks per CU of the two
-  // instances, queried once (thread-safe static initialisation)
-  static const int cus = [] {
-    int dev = 0, n = 0;
-    (void)hipGetDevice(&dev);
-    (void)hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev);
-    return n > 0 ? n : 1;
-  }();
+  // resident blocks per CU of the two instances, queried once (thread-safe
+  // static initialisation)
+  const int cus = cu_count();
   static const int res_bf16 = [] {
     int n = 0;
     (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, conv_fwd_pipe_kernel<MT, NT, false>, 256, 0);
@@ -1599,12 +1606,7 @@ template <int KC, int NT>
 void conv_res_launch(int B, int H, int W, const uint16_t* x, const uint16_t* w, const float* bias, int act,
                      const uint16_t* add, void* y, bool y_fp32, int y_ld, int c_store, int c_out, int tw,
                      float waves, hipStream_t st) {
-  static const int cus = [] {
-    int dev = 0, n = 0;
-    (void)hipGetDevice(&dev);
-    (void)hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev);
-    return n > 0 ? n : 1;
-  }();
+  const int cus = cu_count();
   static const int res_bf16 = [] {
     int n = 0;
     (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, conv_fwd_res_kernel<KC, NT, false>, 256, 0);
@@ -1657,12 +1659,7 @@ bool conv_res(int B, int H, int W, const uint16_t* x, int cin, const uint16_t* w
 template <int KC>
 void conv_up_launch(int B, int H, int W, const uint16_t* x, const uint16_t* w, const float* bias, int act,
                     const uint16_t* add, uint16_t* y, int y_ld, int c_out, int tw, float waves, hipStream_t st) {
-  static const int cus = [] {
-    int dev = 0, n = 0;
-    (void)hipGetDevice(&dev);
-    (void)hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev);
-    return n > 0 ? n : 1;
-  }();
+  const int cus = cu_count();
   static const int res_add = [] {
     int n = 0;
     (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, conv_fwd_up_kernel<KC, true>, 256, 0);

@@ -244,10 +244,14 @@ class UNet:
         qnn.qnn_pack_input(B, H, W, q, idx_q, n, idx_n, self.scale, N_SHIFT, N_SCALE, self.shift,
                            self.act["x"], self.stream)
 
-    def predict(self, q, n, out_q, chunk: int = 8):
+    def predict(self, q, n, out_q, chunk: int = 0):
         """out_q[b] = network(q[b], n[b]) for lattices q [B][6][H][W] (FP32),
-        in chunks of at most ``chunk`` lattices."""
+        in chunks of at most ``chunk`` lattices (0: as many as the kernels'
+        31-bit element offsets allow for the 48-channel input, at most 16;
+        fewer, smaller launches leave the deep layers' grids short)."""
         B, _, H, W = q.shape
+        if chunk <= 0:
+            chunk = max(1, min(16, ((1 << 31) - 1) // (IN_CH * H * W)))
         for c0 in range(0, B, chunk):
             c1 = min(B, c0 + chunk)
             self.pack(c1 - c0, H, W, q[c0:c1], None, n[c0:c1], None)

@@ -75,6 +75,23 @@ int qnn_conv3x3_fwd_fused(int32_t B, int32_t H, int32_t W, const uint16_t *x, in
                           int32_t act, const uint16_t *add, uint16_t *y, int32_t y_ld,
                           void *hip_stream);
 
+/*
+ * The network's output layer and the unpacking of its result in one pass,
+ * for inference:
+ *   q[b][c][y][x] = scale[b] * act(bias + conv3x3(x, w))[b, y, x, c],
+ *   c < n_planes
+ *   x      BF16 [B*H*W][c_in], c_in = 32 or 48, 16-byte aligned
+ *   w      BF16 [32][9][c_in] (c_out = 32), 16-byte aligned
+ *   bias   FP32 [32] or NULL; scale FP32 [B]
+ *   q      FP32 [B][n_planes][H][W], 1 <= n_planes <= 32
+ * W must be a multiple of 16 and B*H*W*c_in below 2^31; otherwise QNN_EINVAL
+ * (and nothing runs). Bitwise qnn_conv3x3_fwd with FP32 output followed by
+ * qnn_unpack_output (n_planes = 6), without the intermediate tensor.
+ */
+int qnn_conv3x3_fwd_planes(int32_t B, int32_t H, int32_t W, const uint16_t *x, int32_t c_in,
+                           const uint16_t *w, const float *bias, int32_t c_out, int32_t act,
+                           const float *scale, int32_t n_planes, float *q, void *hip_stream);
+
 /* wt = the weights of the adjoint convolution: wt[ci][8 - t][co] = w[co][t][ci]
  * (the data gradient of a circular 3x3 convolution is a 3x3 convolution of
  * the output gradient with the flipped, transposed kernel). */

@@ -261,6 +261,63 @@ __device__ __forceinline__ void tile_epilogue(f32x16 (&acc)[MT][NT], uint16_t* E
   }
 }
 
+// One 32-pixel half (mt) of a wave's results written as scaled FP32 planes
+// (see tile_epilogue_planes), leaving a zeroed.
+__device__ __forceinline__ void planes_half(f32x16& a, float* E, int mt, int MT, int tx0, int ty0, int b,
+                                            int tw_shift, int H, int W, float bsum, int act, float* __restrict__ q,
+                                            int nq, float sc) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int cl = lane & 31;
+  // the accumulators are read from a copy and cleared as one vector (element
+  // stores under the branches below put them in scratch memory)
+  const f32x16 av = a;
+  a = f32x16{};
+  __syncthreads();    // the staged operands, or the previous half's rows, are free
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    float v = av[r] + bsum;
+    if (act == QNN_ACT_LEAKY) v = v > 0.0f ? v : kLeakySlope * v;
+    if (cl < nq) E[cl * 33 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3)] = v;
+  }
+  __syncthreads();
+  const int j = (wave * MT + mt) * 32 + cl;
+  const int oy = ty0 + (j >> tw_shift);
+  if (oy < H) {
+    const int64_t pix = static_cast<int64_t>(oy) * W + tx0 + (j & ((1 << tw_shift) - 1));
+    for (int c = lane >> 5; c < nq; c += 2)
+      q[(static_cast<int64_t>(b) * nq + c) * H * W + pix] = E[c * 33 + cl] * sc;
+  }
+}
+
+// The end of a tile for results written as per-sample scaled FP32 planes
+// (32 output channels, n0 = 0): q[(b * nq + c) * H * W + pixel] = scale[b] *
+// act(bias + acc) for channels c < nq, leaving acc zeroed. Each half of a
+// wave's pixels passes through LDS as [channel][pixel] (rows of 33 floats
+// from E0), and each lane then stores one pixel of a plane: consecutive
+// lanes on consecutive pixels of one image row (TW >= 32: a half is one
+// row segment; TW = 16: two).
+template <int MT>
+__device__ __forceinline__ void tile_epilogue_planes(f32x16 (&acc)[MT][1], uint16_t* E0, int tile, int tiles_x,
+                                                     int tiles_y, int tw_shift, int TH, int H, int W,
+                                                     const float* __restrict__ bias, int act,
+                                                     float* __restrict__ q, int nq,
+                                                     const float* __restrict__ scale) {
+  static_assert(MT == 1 || MT == 2, "one or two halves");
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int tx0 = (tile % tiles_x) << tw_shift;
+  const int t2 = tile / tiles_x;
+  const int ty0 = (t2 % tiles_y) * TH;
+  const int b = t2 / tiles_y;
+  const float sc = scale[b];
+  float* const E = reinterpret_cast<float*>(E0) + wave * 32 * 33;
+  const int cl = lane & 31;
+  const float bsum = (bias && cl < nq) ? bias[cl] : 0.0f;
+  planes_half(acc[0][0], E, 0, MT, tx0, ty0, b, tw_shift, H, W, bsum, act, q, nq, sc);
+  if constexpr (MT == 2) planes_half(acc[1][0], E, 1, MT, tx0, ty0, b, tw_shift, H, W, bsum, act, q, nq, sc);
+}
+
 template <int MT, int NT, bool OUT_FP32>
 __global__ void __launch_bounds__(256) conv_fwd_pipe_kernel(int H, int W, int tw_shift, int tiles,
                                                             const uint16_t* __restrict__ x, int cin,
@@ -434,13 +491,15 @@ struct ResConv {
   static constexpr int kSmem = kWRows * kRow + (kIn > kOut ? kIn : kOut);
 };
 
-template <int KC, int NT, bool OUT_FP32>
+template <int KC, int NT, bool OUT_FP32, bool PLANES = false>
 __global__ void __launch_bounds__(256) conv_fwd_res_kernel(int H, int W, int tw_shift, int tiles,
                                                            const uint16_t* __restrict__ x,
                                                            const uint16_t* __restrict__ w,
                                                            const float* __restrict__ bias, int act,
                                                            void* __restrict__ y, int y_ld, int c_store,
-                                                           const uint16_t* __restrict__ add) {
+                                                           const uint16_t* __restrict__ add,
+                                                           const float* __restrict__ scale) {
+  static_assert(!PLANES || (NT == 1 && OUT_FP32), "planes: 32 output channels, FP32");
   using RC = ResConv<KC, NT>;
   constexpr int cin = RC::kCin;
   __shared__ __attribute__((aligned(16))) uint16_t smem[RC::kSmem];
@@ -549,8 +608,12 @@ __global__ void __launch_bounds__(256) conv_fwd_res_kernel(int H, int W, int tw_
             acc[mt][jn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[mt], bv[jn], acc[mt][jn], 0, 0, 0);
       }
     }
-    tile_epilogue<2, NT, OUT_FP32>(acc, lin, tile, tiles_x, tiles_y, tw_shift, TH, H, W, n0, bias, act, y, y_ld,
-                                   c_store, add);
+    if constexpr (PLANES)
+      tile_epilogue_planes<2>(acc, lin, tile, tiles_x, tiles_y, tw_shift, TH, H, W, bias, act,
+                              static_cast<float*>(y), c_store, scale);
+    else
+      tile_epilogue<2, NT, OUT_FP32>(acc, lin, tile, tiles_x, tiles_y, tw_shift, TH, H, W, n0, bias, act, y, y_ld,
+                                     c_store, add);
   }
 }
 
@@ -1628,10 +1691,30 @@ void conv_res_launch(int B, int H, int W, const uint16_t* x, const uint16_t* w, 
   dim3 grid(static_cast<unsigned>(gx), gy);
   if (y_fp32)
     hipLaunchKernelGGL((conv_fwd_res_kernel<KC, NT, true>), grid, dim3(256), 0, st, H, W, tws,
-                       static_cast<int>(tiles), x, w, bias, act, y, y_ld, c_store, add);
+                       static_cast<int>(tiles), x, w, bias, act, y, y_ld, c_store, add, nullptr);
   else
     hipLaunchKernelGGL((conv_fwd_res_kernel<KC, NT, false>), grid, dim3(256), 0, st, H, W, tws,
-                       static_cast<int>(tiles), x, w, bias, act, y, y_ld, c_store, add);
+                       static_cast<int>(tiles), x, w, bias, act, y, y_ld, c_store, add, nullptr);
+}
+
+// The resident-weight kernel writing nq scaled FP32 planes (32 output
+// channels), grid as above.
+template <int KC>
+void conv_res_planes_launch(int B, int H, int W, const uint16_t* x, const uint16_t* w, const float* bias, int act,
+                            const float* scale, int nq, float* q, int tw, hipStream_t st) {
+  const int cus = cu_count();
+  static const int res = [] {
+    int n = 0;
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, conv_fwd_res_kernel<KC, 1, true, true>, 256, 0);
+    return n > 0 ? n : 1;
+  }();
+  const int tws = tw == 32 ? 5 : 4;
+  const int TH = 256 / tw;
+  const int64_t tiles = static_cast<int64_t>(B) * (W / tw) * ((H + TH - 1) / TH);
+  int64_t gx = static_cast<int64_t>(cus) * res;
+  if (gx > tiles) gx = tiles;
+  hipLaunchKernelGGL((conv_fwd_res_kernel<KC, 1, true, true>), dim3(static_cast<unsigned>(gx), 1), dim3(256), 0, st,
+                     H, W, tws, static_cast<int>(tiles), x, w, bias, act, q, 0, nq, nullptr, scale);
 }
 
 // the resident-weight kernel where it applies: 32 or 48 input channels with
@@ -1839,6 +1922,26 @@ int qnn_conv3x3_fwd_fused(int32_t B, int32_t H, int32_t W, const uint16_t* x, in
   if (!conv_pipe(m, n, B, H, W, x, c_in, up, w, bias, act, add, y, false, y_ld, c_out, c_out, 1.0f, st))
     return bad("conv3x3_fwd_fused: shape not supported");
   return launched("conv3x3_fwd_fused");
+}
+
+int qnn_conv3x3_fwd_planes(int32_t B, int32_t H, int32_t W, const uint16_t* x, int32_t c_in, const uint16_t* w,
+                           const float* bias, int32_t c_out, int32_t act, const float* scale, int32_t n_planes,
+                           float* q, void* hip_stream) {
+  if (B < 1 || H < 1 || W < 1 || !x || !w || !scale || !q) return bad("conv3x3_fwd_planes: bad size or null pointer");
+  if ((c_in != 32 && c_in != 48) || c_out != 32) return bad("conv3x3_fwd_planes: c_in must be 32 or 48, c_out 32");
+  if (W % 16) return bad("conv3x3_fwd_planes: W must be a multiple of 16");
+  if (n_planes < 1 || n_planes > 32) return bad("conv3x3_fwd_planes: n_planes must be 1..32");
+  if (act != QNN_ACT_NONE && act != QNN_ACT_LEAKY) return bad("conv3x3_fwd_planes: unknown activation");
+  if (!a16(x) || !a16(w)) return bad("conv3x3_fwd_planes: x and w must be 16-byte aligned");
+  const int64_t P64 = static_cast<int64_t>(B) * H * W;
+  if (P64 * c_in >= (int64_t{1} << 31)) return bad("conv3x3_fwd_planes: tensor too large");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const int tw = W % 32 == 0 ? 32 : 16;
+  if (c_in == 32)
+    conv_res_planes_launch<2>(B, H, W, x, w, bias, act, scale, n_planes, q, tw, st);
+  else
+    conv_res_planes_launch<3>(B, H, W, x, w, bias, act, scale, n_planes, q, tw, st);
+  return launched("conv3x3_fwd_planes");
 }
 
 #ifdef QNN_TUNE_HOOK

@@ -16,6 +16,7 @@ _i32, _i64, _f32, _vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c
 _SIGNATURES = {
     "qnn_conv3x3_fwd": [_i32, _i32, _i32, _vp, _i32, _vp, _vp, _i32, _i32, _vp, _i32, _i32, _i32, _vp],
     "qnn_conv3x3_fwd_fused": [_i32, _i32, _i32, _vp, _i32, _i32, _vp, _vp, _i32, _i32, _vp, _vp, _i32, _vp],
+    "qnn_conv3x3_fwd_planes": [_i32, _i32, _i32, _vp, _i32, _vp, _vp, _i32, _i32, _vp, _i32, _vp, _vp],
     "qnn_conv3x3_flip": [_vp, _i32, _i32, _vp, _vp],
     "qnn_conv3x3_wgrad": [_i32, _i32, _i32, _vp, _i32, _vp, _i32, _vp, _vp, _vp, _vp],
     "qnn_leaky_bwd": [_i64, _vp, _vp, _vp, _vp],
@@ -75,6 +76,11 @@ def qnn_conv3x3_fwd(B, H, W, x, c_in, w, bias, c_out, act, y, y_fp32, y_ld, c_st
 def qnn_conv3x3_fwd_fused(B, H, W, x, c_in, up, w, bias, c_out, act, add, y, y_ld, stream=None):
     _call("qnn_conv3x3_fwd_fused", B, H, W, _p(x), c_in, int(up), _p(w), _p(bias), c_out, act, _p(add), _p(y),
           y_ld, _s(stream))
+
+
+def qnn_conv3x3_fwd_planes(B, H, W, x, c_in, w, bias, c_out, act, scale, n_planes, q, stream=None):
+    _call("qnn_conv3x3_fwd_planes", B, H, W, _p(x), c_in, _p(w), _p(bias), c_out, act, _p(scale), n_planes, _p(q),
+          _s(stream))
 
 
 def qnn_conv3x3_flip(w, c_out, c_in, wt, stream=None):

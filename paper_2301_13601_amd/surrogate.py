@@ -201,13 +201,16 @@ class UNet:
                                 s.c_out, self.stream)
         return y
 
-    def forward_packed(self, B: int, H: int, W: int, fused: bool = False):
+    def forward_packed(self, B: int, H: int, W: int, fused: bool = False, planes=None):
         """Run the network on self.act["x"]; returns the FP32 output [P][8]
         (6 channels used). fused: each decoder level's upsampling and skip
         addition run inside its first convolution (qnn_conv3x3_fwd_fused,
         bitwise the same result) wherever that kernel's tile widths fit; the
         upsampled and pre-addition tensors are then not stored, so training,
-        whose backward pass reads them, runs unfused."""
+        whose backward pass reads them, runs unfused. planes: an FP32 tensor
+        [B][6][H][W] that receives the unpacked, rescaled output directly
+        (qnn_conv3x3_fwd_planes, bitwise the FP32 output then
+        qnn_unpack_output); None is returned then."""
         A, S = self.act, self.by_name
         st = self.stream
         x = A["x"]
@@ -234,6 +237,11 @@ class UNet:
                 qnn.qnn_add(n, d, A[f"e{l}"], A[f"h{l}"], st)
             x = self._conv(S[f"d{l}"], A[f"h{l}"], B, H, W)
             up_c = LEVELS[l]
+        if planes is not None:
+            s = S["out"]
+            qnn.qnn_conv3x3_fwd_planes(B, H, W, x, s.c_in, self.w(s), self.b(s), s.c_out, s.act, self.scale, 6,
+                                       planes, st)
+            return None
         return self._conv(S["out"], x, B, H, W, fp32=True)
 
     def pack(self, B, H, W, q, idx_q, n, idx_n, train=False):
@@ -255,8 +263,7 @@ class UNet:
         for c0 in range(0, B, chunk):
             c1 = min(B, c0 + chunk)
             self.pack(c1 - c0, H, W, q[c0:c1], None, n[c0:c1], None)
-            y = self.forward_packed(c1 - c0, H, W, fused=True)
-            qnn.qnn_unpack_output(c1 - c0, H, W, y, OUT_LD, self.scale, out_q[c0:c1], self.stream)
+            self.forward_packed(c1 - c0, H, W, fused=True, planes=out_q[c0:c1])
 
     # -- backward ----------------------------------------------------------------
     def _conv_bwd(self, s: Conv, x_in, dy, B, H, W, dx=None):

@@ -129,3 +129,23 @@ def test_fused_conv_rejects_what_it_cannot_run_without_a_device(qla):
     for bad in [dict(W=48), dict(H=31), dict(up=2), dict(ld=36), dict(ld=16), dict(y=Y + 2),
                 dict(add=0x40008), dict(co=48), dict(ci=24), dict(act=3)]:
         assert call(**bad) == -1, bad
+
+
+def test_planes_conv_rejects_what_it_cannot_run_without_a_device(qla):
+    L = ctypes.CDLL(qla.LIB_PATH)
+    f = L.qnn_conv3x3_fwd_planes
+    i, v = ctypes.c_int32, ctypes.c_void_p
+    f.argtypes = [i, i, i, v, i, v, v, i, i, v, i, v, v]
+    X, Wt, S, Q = 0x10000, 0x20000, 0x30000, 0x40000
+    ok = dict(B=1, H=32, W=64, x=X, ci=32, w=Wt, bias=None, co=32, act=0, scale=S, nq=6, q=Q)
+
+    def call(**kw):
+        a = dict(ok, **kw)
+        return f(a["B"], a["H"], a["W"], a["x"], a["ci"], a["w"], a["bias"], a["co"], a["act"], a["scale"],
+                 a["nq"], a["q"], None)
+
+    for bad in [dict(W=24), dict(ci=64), dict(ci=16), dict(co=64), dict(nq=0), dict(nq=33), dict(act=2),
+                dict(x=X + 2), dict(w=Wt + 8), dict(scale=None), dict(q=None), dict(B=0),
+                dict(B=1 << 12, H=1024, W=1024)]:
+        assert call(**bad) == -1, bad
+        assert "conv3x3_fwd_planes" in qla.qla_last_error()

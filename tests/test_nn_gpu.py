@@ -127,6 +127,32 @@ def test_conv_fused_is_bitwise_the_separate_steps(env, B, H, W, ci, co, up, with
     assert torch.equal(got.view(torch.int16), want.view(torch.int16))
 
 
+@pytest.mark.parametrize("B,H,W,ci", [(2, 16, 32, 32), (3, 20, 48, 48), (2, 5, 64, 32), (40, 32, 64, 32)])
+@pytest.mark.parametrize("act", [0, 1])
+def test_conv_planes_is_bitwise_conv_then_unpack(env, B, H, W, ci, act):
+    """The output layer writing scaled planes: bitwise the FP32 convolution
+    followed by qnn_unpack_output (6 planes), and the plain product for all
+    32 (16- and 32-wide tiles, a tile taller than the image, many tiles)."""
+    torch, qnn = env
+    x, _ = bf(torch, rnd(50, (B, H, W, ci)))
+    w, _ = bf(torch, rnd(51, (32, 9, ci), 1 / np.sqrt(9 * ci)))
+    bias = torch.tensor(rnd(52, 32).astype(np.float32)).cuda()
+    scale = torch.tensor((0.5 + np.abs(rnd(53, B))).astype(np.float32)).cuda()
+    y = torch.empty((B, H, W, 8), dtype=torch.float32, device="cuda")
+    qnn.qnn_conv3x3_fwd(B, H, W, x, ci, w, bias, 32, act, y, 1, 8, 6)
+    want = torch.empty((B, 6, H, W), dtype=torch.float32, device="cuda")
+    qnn.qnn_unpack_output(B, H, W, y, 8, scale, want)
+    got = torch.full((B, 6, H, W), 3.0, dtype=torch.float32, device="cuda")
+    qnn.qnn_conv3x3_fwd_planes(B, H, W, x, ci, w, bias, 32, act, scale, 6, got)
+    assert torch.equal(got.view(torch.int32), want.view(torch.int32))
+    y32 = torch.empty((B, H, W, 32), dtype=torch.float32, device="cuda")
+    qnn.qnn_conv3x3_fwd(B, H, W, x, ci, w, bias, 32, act, y32, 1, 32, 32)
+    want32 = y32.permute(0, 3, 1, 2).contiguous() * scale[:, None, None, None]
+    got32 = torch.empty((B, 32, H, W), dtype=torch.float32, device="cuda")
+    qnn.qnn_conv3x3_fwd_planes(B, H, W, x, ci, w, bias, 32, act, scale, 32, got32)
+    assert torch.equal(got32.view(torch.int32), want32.view(torch.int32))
+
+
 @pytest.mark.parametrize("B,H,W,ci,co", [(2, 16, 16, 16, 32), (1, 6, 10, 64, 32), (2, 2, 2, 128, 128),
                                          (4, 32, 64, 32, 64)])
 def test_conv_data_gradient(env, B, H, W, ci, co):

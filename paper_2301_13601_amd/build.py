@@ -7,6 +7,7 @@ parallel, then link into one shared library.
 from __future__ import annotations
 
 import os
+import re
 import subprocess
 import sys
 import tempfile
@@ -34,20 +35,50 @@ FLAGS = [
 ]
 
 
+def spilled_kernels(remarks: str) -> list:
+    """Kernels that the compiler's resource-usage remarks show using scratch
+    memory (register spills or a private array the compiler could not keep
+    in registers): every kernel of the library is meant to need none, and
+    one that does runs several times slower."""
+    out, name = [], None
+    for line in remarks.splitlines():
+        m = re.search(r"Function Name: (\S+)", line)
+        if m:
+            name = m.group(1)
+            continue
+        m = re.search(r"ScratchSize \[bytes/lane\]: (\d+)", line)
+        if m and int(m.group(1)) > 0:
+            out.append((name, int(m.group(1))))
+    return out
+
+
 def build(verbose: bool = False, extra=()) -> str:
     with tempfile.TemporaryDirectory(prefix="qla_build_") as tmpd:
         objs, procs = [], []
         for src, name, defs in SOURCES:
             obj = os.path.join(tmpd, name + ".o")
-            cmd = [HIPCC, *FLAGS, *defs, *extra, "-I", INCLUDE, "-I", CSRC, "-c", os.path.join(CSRC, src),
-                   "-o", obj]
+            cmd = [HIPCC, *FLAGS, *defs, *extra, "-Rpass-analysis=kernel-resource-usage", "-I", INCLUDE, "-I",
+                   CSRC, "-c", os.path.join(CSRC, src), "-o", obj]
             if verbose:
                 print(" ".join(cmd), flush=True)
-            procs.append((name, subprocess.Popen(cmd)))
+            # the remarks go to a file (a pipe could fill while the compiler runs)
+            log = open(os.path.join(tmpd, name + ".log"), "w+")
+            procs.append((name, subprocess.Popen(cmd, stderr=log), log))
             objs.append(obj)
-        failed = [src for src, p in procs if p.wait() != 0]
+        failed, spills = [], []
+        for name, proc, log in procs:
+            rc = proc.wait()
+            log.seek(0)
+            text = log.read()
+            log.close()
+            if rc != 0:
+                failed.append(name)
+                sys.stderr.write("\n".join(l for l in text.splitlines() if "remark:" not in l) + "\n")
+            spills += spilled_kernels(text)
         if failed:
             raise RuntimeError(f"hipcc failed on {failed}")
+        if spills:
+            raise RuntimeError(f"kernels using scratch memory: {spills}")
         tmp = LIB + ".tmp"
         cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
         if verbose:

@@ -621,15 +621,15 @@ __global__ void __launch_bounds__(256) conv_fwd_res_kernel(int H, int W, int tw_
 // Forward 3x3 circular convolution of a nearest-neighbour upsampled input,
 // plus an optional skip input: y = act(bias + conv3x3(up2(x), w)) + add, for
 // 16*KC input channels (x at half resolution; KC in {4, 8}) and 32 output
-// channels a block, tiles of 256 output pixels (TH x TW, TW in {16, 32}). Tile rows and
-// columns start at even coordinates, so the tile reads the fixed
-// half-resolution window (TH/2 + 2) x (TW/2 + 2), staged once per tile
-// instead of once per output pixel it feeds (a quarter of the bytes); the
-// tap offsets into that window depend on the lane only. The weights stay
-// in LDS, and each step loads the next tile's window and skip input into
-// registers during the current tile's MFMAs, the skip input in the pieces
-// the epilogue stores. Bitwise the same as the pipelined kernel with the
-// upsampling folded in (same MFMA operands, same order).
+// channels a block, tiles of 256 output pixels (TH x TW, TW in {16, 32}).
+// Tile rows and columns start at even coordinates, so the tile reads the
+// fixed half-resolution window (TH/2 + 2) x (TW/2 + 2), staged once per
+// tile instead of once per output pixel it feeds (a quarter of the bytes);
+// the tap offsets into that window depend on the lane only. The weights
+// stay in LDS, and each step loads the next tile's window and skip input
+// into registers during the current tile's MFMAs, the skip input in the
+// pieces the epilogue stores. Bitwise the same as the pipelined kernel
+// with the upsampling folded in (same MFMA operands, same order).
 // ---------------------------------------------------------------------------
 template <int KC>
 struct UpConv {

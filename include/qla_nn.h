@@ -92,6 +92,22 @@ int qnn_conv3x3_fwd_planes(int32_t B, int32_t H, int32_t W, const uint16_t *x, i
                            const uint16_t *w, const float *bias, int32_t c_out, int32_t act,
                            const float *scale, int32_t n_planes, float *q, void *hip_stream);
 
+/*
+ * A convolution and the 2x2 average pooling of its result, for an encoder
+ * level in inference:
+ *   y     = act(bias + conv3x3(x, w))   BF16 [B*H*W][c_out]
+ *   pool  = avgpool2(y)                 BF16 [B*(H/2)*(W/2)][c_out]
+ * bitwise qnn_conv3x3_fwd (BF16, y_ld = c_store = c_out) followed by
+ * qnn_avgpool2; where the convolution runs on the resident-weight tiles
+ * (see qnn_conv3x3_fwd) the pooling is done as the tiles are stored, else the
+ * two calls are made in turn. H and W even; x, w, y and pool 16-byte aligned;
+ * c_in a multiple of 16, c_out of 32; B*H*W*max(c_in, c_out) below 2^31;
+ * otherwise QNN_EINVAL (and nothing runs).
+ */
+int qnn_conv3x3_fwd_pool(int32_t B, int32_t H, int32_t W, const uint16_t *x, int32_t c_in,
+                         const uint16_t *w, const float *bias, int32_t c_out, int32_t act,
+                         uint16_t *y, uint16_t *pool, void *hip_stream);
+
 /* wt = the weights of the adjoint convolution: wt[ci][8 - t][co] = w[co][t][ci]
  * (the data gradient of a circular 3x3 convolution is a 3x3 convolution of
  * the output gradient with the flipped, transposed kernel). */

@@ -159,12 +159,12 @@ struct PipeConv {
 // caller's registers add_regs[k] holding piece k of the lane's stores);
 // FP32 results pass through E too, 32 pixels of a wave at a time, and only
 // channels below c_store are stored.
-template <int MT, int NT, bool OUT_FP32, bool ADD_REGS = false>
+template <int MT, int NT, bool OUT_FP32, bool ADD_REGS = false, bool POOL = false>
 __device__ __forceinline__ void tile_epilogue(f32x16 (&acc)[MT][NT], uint16_t* E0, int tile, int tiles_x, int tiles_y,
                                               int tw_shift, int TH, int H, int W, int n0,
                                               const float* __restrict__ bias, int act, void* __restrict__ y, int y_ld,
                                               int c_store, const uint16_t* __restrict__ add,
-                                              const u32x4* add_regs = nullptr) {
+                                              const u32x4* add_regs = nullptr, uint16_t* __restrict__ pool = nullptr) {
   constexpr int kERow = 32 * NT + 8;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -224,6 +224,48 @@ __device__ __forceinline__ void tile_epilogue(f32x16 (&acc)[MT][NT], uint16_t* E
           }
         }
         *reinterpret_cast<u32x4*>(static_cast<uint16_t*>(y) + o) = v;
+      }
+    }
+    if constexpr (POOL) {
+      // 2x2 means of the stored results (no skip input), from the wave's rows
+      // of E: the wave's 64 pixels are 64 / TW whole tile rows starting at an
+      // even image row, i.e. 16 pooled pixels x 32 NT channels; each lane
+      // takes 8 channels of one pooled pixel, summed in the order of
+      // qnn_avgpool2 and rounded the same way. Pool rows are y_ld long.
+      static_assert(MT == 2, "whole tile rows per wave");
+      const int hw = TW >> 1;
+      const int r0 = ty0 + ((wave * 64) >> tw_shift);
+#pragma unroll
+      for (int k = 0; k < NT; ++k) {
+        const int q = lane + 64 * k;
+        const int pp = q / (4 * NT), g = q % (4 * NT);
+        const int pr = pp / hw, pc = pp - pr * hw;
+        if (r0 + 2 * pr < H) {
+          const uint16_t* e = E + (2 * pr * TW + 2 * pc) * kERow + g * 8;
+          const u32x4 v00 = *reinterpret_cast<const u32x4*>(e);
+          const u32x4 v01 = *reinterpret_cast<const u32x4*>(e + kERow);
+          const u32x4 v10 = *reinterpret_cast<const u32x4*>(e + TW * kERow);
+          const u32x4 v11 = *reinterpret_cast<const u32x4*>(e + (TW + 1) * kERow);
+          float f[8];
+#pragma unroll
+          for (int h = 0; h < 4; ++h) {
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+              const int sh = 16 * s;
+              f[2 * h + s] = 0.25f * (bf2f(static_cast<uint16_t>(v00[h] >> sh)) +
+                                      bf2f(static_cast<uint16_t>(v01[h] >> sh)) +
+                                      bf2f(static_cast<uint16_t>(v10[h] >> sh)) +
+                                      bf2f(static_cast<uint16_t>(v11[h] >> sh)));
+            }
+          }
+          u32x4 o;
+#pragma unroll
+          for (int h = 0; h < 4; ++h)
+            o[h] = static_cast<uint32_t>(f2bf(f[2 * h])) | (static_cast<uint32_t>(f2bf(f[2 * h + 1])) << 16);
+          const int64_t po = ((static_cast<int64_t>(b) * (H >> 1) + ((r0 >> 1) + pr)) * (W >> 1) +
+                              (tx0 >> 1) + pc) * y_ld + n0 + g * 8;
+          *reinterpret_cast<u32x4*>(pool + po) = o;
+        }
       }
     }
   } else {
@@ -491,15 +533,17 @@ struct ResConv {
   static constexpr int kSmem = kWRows * kRow + (kIn > kOut ? kIn : kOut);
 };
 
-template <int KC, int NT, bool OUT_FP32, bool PLANES = false>
+template <int KC, int NT, bool OUT_FP32, bool PLANES = false, bool POOL = false>
 __global__ void __launch_bounds__(256) conv_fwd_res_kernel(int H, int W, int tw_shift, int tiles,
                                                            const uint16_t* __restrict__ x,
                                                            const uint16_t* __restrict__ w,
                                                            const float* __restrict__ bias, int act,
                                                            void* __restrict__ y, int y_ld, int c_store,
                                                            const uint16_t* __restrict__ add,
-                                                           const float* __restrict__ scale) {
+                                                           const float* __restrict__ scale,
+                                                           uint16_t* __restrict__ pool) {
   static_assert(!PLANES || (NT == 1 && OUT_FP32), "planes: 32 output channels, FP32");
+  static_assert(!POOL || !OUT_FP32, "pooling: BF16 results");
   using RC = ResConv<KC, NT>;
   constexpr int cin = RC::kCin;
   __shared__ __attribute__((aligned(16))) uint16_t smem[RC::kSmem];
@@ -612,8 +656,8 @@ __global__ void __launch_bounds__(256) conv_fwd_res_kernel(int H, int W, int tw_
       tile_epilogue_planes<2>(acc, lin, tile, tiles_x, tiles_y, tw_shift, TH, H, W, bias, act,
                               static_cast<float*>(y), c_store, scale);
     else
-      tile_epilogue<2, NT, OUT_FP32>(acc, lin, tile, tiles_x, tiles_y, tw_shift, TH, H, W, n0, bias, act, y, y_ld,
-                                     c_store, add);
+      tile_epilogue<2, NT, OUT_FP32, false, POOL>(acc, lin, tile, tiles_x, tiles_y, tw_shift, TH, H, W, n0, bias, act,
+                                                  y, y_ld, c_store, add, nullptr, pool);
   }
 }
 
@@ -1668,7 +1712,7 @@ bool conv_pipe(int mt, int nt, int B, int H, int W, const uint16_t* x, int cin, 
 template <int KC, int NT>
 void conv_res_launch(int B, int H, int W, const uint16_t* x, const uint16_t* w, const float* bias, int act,
                      const uint16_t* add, void* y, bool y_fp32, int y_ld, int c_store, int c_out, int tw,
-                     float waves, hipStream_t st) {
+                     float waves, hipStream_t st, uint16_t* pool = nullptr) {
   const int cus = cu_count();
   static const int res_bf16 = [] {
     int n = 0;
@@ -1680,7 +1724,12 @@ void conv_res_launch(int B, int H, int W, const uint16_t* x, const uint16_t* w, 
     (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, conv_fwd_res_kernel<KC, NT, true>, 256, 0);
     return n > 0 ? n : 1;
   }();
-  const int res = y_fp32 ? res_fp32 : res_bf16;
+  static const int res_pool = [] {
+    int n = 0;
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, conv_fwd_res_kernel<KC, NT, false, false, true>, 256, 0);
+    return n > 0 ? n : 1;
+  }();
+  const int res = y_fp32 ? res_fp32 : (pool ? res_pool : res_bf16);
   const int tws = tw == 32 ? 5 : 4;
   const int TH = 256 / tw;
   const int64_t tiles = static_cast<int64_t>(B) * (W / tw) * ((H + TH - 1) / TH);
@@ -1691,10 +1740,13 @@ void conv_res_launch(int B, int H, int W, const uint16_t* x, const uint16_t* w, 
   dim3 grid(static_cast<unsigned>(gx), gy);
   if (y_fp32)
     hipLaunchKernelGGL((conv_fwd_res_kernel<KC, NT, true>), grid, dim3(256), 0, st, H, W, tws,
-                       static_cast<int>(tiles), x, w, bias, act, y, y_ld, c_store, add, nullptr);
+                       static_cast<int>(tiles), x, w, bias, act, y, y_ld, c_store, add, nullptr, nullptr);
+  else if (pool)
+    hipLaunchKernelGGL((conv_fwd_res_kernel<KC, NT, false, false, true>), grid, dim3(256), 0, st, H, W, tws,
+                       static_cast<int>(tiles), x, w, bias, act, y, y_ld, c_store, add, nullptr, pool);
   else
     hipLaunchKernelGGL((conv_fwd_res_kernel<KC, NT, false>), grid, dim3(256), 0, st, H, W, tws,
-                       static_cast<int>(tiles), x, w, bias, act, y, y_ld, c_store, add, nullptr);
+                       static_cast<int>(tiles), x, w, bias, act, y, y_ld, c_store, add, nullptr, nullptr);
 }
 
 // The resident-weight kernel writing nq scaled FP32 planes (32 output
@@ -1714,7 +1766,7 @@ void conv_res_planes_launch(int B, int H, int W, const uint16_t* x, const uint16
   int64_t gx = static_cast<int64_t>(cus) * res;
   if (gx > tiles) gx = tiles;
   hipLaunchKernelGGL((conv_fwd_res_kernel<KC, 1, true, true>), dim3(static_cast<unsigned>(gx), 1), dim3(256), 0, st,
-                     H, W, tws, static_cast<int>(tiles), x, w, bias, act, q, 0, nq, nullptr, scale);
+                     H, W, tws, static_cast<int>(tiles), x, w, bias, act, q, 0, nq, nullptr, scale, nullptr);
 }
 
 // the resident-weight kernel where it applies: 32 or 48 input channels with
@@ -1723,12 +1775,13 @@ void conv_res_planes_launch(int B, int H, int W, const uint16_t* x, const uint16
 // 16-byte pieces as in the pipelined kernel
 bool conv_res(int B, int H, int W, const uint16_t* x, int cin, const uint16_t* w, const float* bias, int act,
               const uint16_t* add, void* y, bool y_fp32, int y_ld, int c_store, int c_out, int nt, int tw,
-              float waves, hipStream_t st) {
+              float waves, hipStream_t st, uint16_t* pool = nullptr) {
   if ((tw != 16 && tw != 32) || W % tw || (nt != 1 && nt != 2) || c_out % (32 * nt)) return false;
   if (!y_fp32 && (c_store != c_out || y_ld % 8 || (reinterpret_cast<uintptr_t>(y) & 15))) return false;
+  if (pool && (y_fp32 || add || (H & 1) || (W & 1) || (reinterpret_cast<uintptr_t>(pool) & 15))) return false;
 #define QNN_RES(C, N)                                                                                             \
   if (cin == 16 * (C) && nt == (N)) {                                                                            \
-    conv_res_launch<C, N>(B, H, W, x, w, bias, act, add, y, y_fp32, y_ld, c_store, c_out, tw, waves, st);        \
+    conv_res_launch<C, N>(B, H, W, x, w, bias, act, add, y, y_fp32, y_ld, c_store, c_out, tw, waves, st, pool);  \
     return true;                                                                                                  \
   }
   QNN_RES(2, 1) QNN_RES(3, 1) QNN_RES(2, 2) QNN_RES(4, 2)
@@ -1942,6 +1995,33 @@ int qnn_conv3x3_fwd_planes(int32_t B, int32_t H, int32_t W, const uint16_t* x, i
   else
     conv_res_planes_launch<3>(B, H, W, x, w, bias, act, scale, n_planes, q, tw, st);
   return launched("conv3x3_fwd_planes");
+}
+
+int qnn_conv3x3_fwd_pool(int32_t B, int32_t H, int32_t W, const uint16_t* x, int32_t c_in, const uint16_t* w,
+                         const float* bias, int32_t c_out, int32_t act, uint16_t* y, uint16_t* pool,
+                         void* hip_stream) {
+  if (B < 1 || H < 2 || W < 2 || !x || !w || !y || !pool) return bad("conv3x3_fwd_pool: bad size or null pointer");
+  if ((H | W) & 1) return bad("conv3x3_fwd_pool: H and W must be even");
+  if (c_in < 16 || c_in % 16 || c_out < 32 || c_out % 32) return bad("conv3x3_fwd_pool: c_in % 16, c_out % 32");
+  if (act != QNN_ACT_NONE && act != QNN_ACT_LEAKY) return bad("conv3x3_fwd_pool: unknown activation");
+  if (!a16(x) || !a16(w) || !a16(y) || !a16(pool)) return bad("conv3x3_fwd_pool: tensors must be 16-byte aligned");
+  const int64_t P64 = static_cast<int64_t>(B) * H * W;
+  if (P64 * (c_in > c_out ? c_in : c_out) >= (int64_t{1} << 31)) return bad("conv3x3_fwd_pool: tensor too large");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  // pooled in the resident-weight kernel's epilogue where that kernel runs
+  // (the same choice as qnn_conv3x3_fwd), else the two separate calls
+  {
+    const int tw = W % 32 == 0 ? 32 : 16;
+    const int64_t tiles = static_cast<int64_t>(B) * (W / tw) * ((H + 256 / tw - 1) / (256 / tw));
+    const bool narrow = c_out == 32;
+    const bool wide = c_out == 64 && (c_in == 32 || c_in == 64) && tiles >= 256;
+    if ((narrow || wide) && conv_res(B, H, W, x, c_in, w, bias, act, nullptr, y, false, c_out, c_out, c_out,
+                                     c_in == 64 ? 2 : 1, tw, 1.0f, st, pool))
+      return launched("conv3x3_fwd_pool");
+  }
+  const int rc = qnn_conv3x3_fwd(B, H, W, x, c_in, w, bias, c_out, act, y, 0, c_out, c_out, hip_stream);
+  if (rc != QNN_OK) return rc;
+  return qnn_avgpool2(B, H, W, c_out, y, pool, hip_stream);
 }
 
 #ifdef QNN_TUNE_HOOK

@@ -17,6 +17,7 @@ _SIGNATURES = {
     "qnn_conv3x3_fwd": [_i32, _i32, _i32, _vp, _i32, _vp, _vp, _i32, _i32, _vp, _i32, _i32, _i32, _vp],
     "qnn_conv3x3_fwd_fused": [_i32, _i32, _i32, _vp, _i32, _i32, _vp, _vp, _i32, _i32, _vp, _vp, _i32, _vp],
     "qnn_conv3x3_fwd_planes": [_i32, _i32, _i32, _vp, _i32, _vp, _vp, _i32, _i32, _vp, _i32, _vp, _vp],
+    "qnn_conv3x3_fwd_pool": [_i32, _i32, _i32, _vp, _i32, _vp, _vp, _i32, _i32, _vp, _vp, _vp],
     "qnn_conv3x3_flip": [_vp, _i32, _i32, _vp, _vp],
     "qnn_conv3x3_wgrad": [_i32, _i32, _i32, _vp, _i32, _vp, _i32, _vp, _vp, _vp, _vp],
     "qnn_leaky_bwd": [_i64, _vp, _vp, _vp, _vp],
@@ -81,6 +82,10 @@ def qnn_conv3x3_fwd_fused(B, H, W, x, c_in, up, w, bias, c_out, act, add, y, y_l
 def qnn_conv3x3_fwd_planes(B, H, W, x, c_in, w, bias, c_out, act, scale, n_planes, q, stream=None):
     _call("qnn_conv3x3_fwd_planes", B, H, W, _p(x), c_in, _p(w), _p(bias), c_out, act, _p(scale), n_planes, _p(q),
           _s(stream))
+
+
+def qnn_conv3x3_fwd_pool(B, H, W, x, c_in, w, bias, c_out, act, y, pool, stream=None):
+    _call("qnn_conv3x3_fwd_pool", B, H, W, _p(x), c_in, _p(w), _p(bias), c_out, act, _p(y), _p(pool), _s(stream))
 
 
 def qnn_conv3x3_flip(w, c_out, c_in, wt, stream=None):

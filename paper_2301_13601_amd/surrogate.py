@@ -215,13 +215,18 @@ class UNet:
         st = self.stream
         x = A["x"]
         for l in range(4):
-            if l > 0:
-                qnn.qnn_avgpool2(B, H >> (l - 1), W >> (l - 1), LEVELS[l - 1], x, A[f"p{l}"], st)
-                x = A[f"p{l}"]
             x = self._conv(S[f"e{l}a"], x, B, H, W)
-            x = self._conv(S[f"e{l}"], x, B, H, W)
-        qnn.qnn_avgpool2(B, H >> 3, W >> 3, LEVELS[3], x, A["p4"], st)
-        x = A["p4"]
+            s = S[f"e{l}"]
+            if fused:
+                # the level's pooled output from the convolution's own tiles
+                # where they allow it (qnn_conv3x3_fwd_pool, bitwise the two
+                # calls below)
+                qnn.qnn_conv3x3_fwd_pool(B, H >> l, W >> l, x, s.c_in, self.w(s), self.b(s), s.c_out, s.act,
+                                         A[s.name], A[f"p{l + 1}"], st)
+            else:
+                self._conv(s, x, B, H, W)
+                qnn.qnn_avgpool2(B, H >> l, W >> l, LEVELS[l], A[s.name], A[f"p{l + 1}"], st)
+            x = A[f"p{l + 1}"]
         for k in range(BOTTLENECK):
             x = self._conv(S[f"b{k}"], x, B, H, W)
         up_c = LEVELS[3]

@@ -149,3 +149,23 @@ def test_planes_conv_rejects_what_it_cannot_run_without_a_device(qla):
                 dict(B=1 << 12, H=1024, W=1024)]:
         assert call(**bad) == -1, bad
         assert "conv3x3_fwd_planes" in qla.qla_last_error()
+
+
+def test_pool_conv_rejects_what_it_cannot_run_without_a_device(qla):
+    L = ctypes.CDLL(qla.LIB_PATH)
+    f = L.qnn_conv3x3_fwd_pool
+    i, v = ctypes.c_int32, ctypes.c_void_p
+    f.argtypes = [i, i, i, v, i, v, v, i, i, v, v, v]
+    X, Wt, Y, P = 0x10000, 0x20000, 0x30000, 0x40000
+    ok = dict(B=1, H=32, W=64, x=X, ci=32, w=Wt, bias=None, co=32, act=0, y=Y, pool=P)
+
+    def call(**kw):
+        a = dict(ok, **kw)
+        return f(a["B"], a["H"], a["W"], a["x"], a["ci"], a["w"], a["bias"], a["co"], a["act"], a["y"], a["pool"],
+                 None)
+
+    for bad in [dict(H=31), dict(W=63), dict(H=1), dict(ci=24), dict(co=48), dict(act=2), dict(x=X + 2),
+                dict(y=Y + 8), dict(pool=P + 2), dict(pool=None), dict(y=None), dict(B=0),
+                dict(B=1 << 11, H=1024, W=1024)]:
+        assert call(**bad) == -1, bad
+        assert "conv3x3_fwd_pool" in qla.qla_last_error()

@@ -127,6 +127,31 @@ def test_conv_fused_is_bitwise_the_separate_steps(env, B, H, W, ci, co, up, with
     assert torch.equal(got.view(torch.int16), want.view(torch.int16))
 
 
+@pytest.mark.parametrize("B,H,W,ci,co", [(2, 16, 32, 32, 32), (3, 20, 48, 48, 32), (2, 6, 64, 32, 32),
+                                         (40, 32, 64, 32, 32), (16, 64, 64, 64, 64), (24, 48, 64, 32, 64),
+                                         (2, 16, 16, 128, 128), (3, 10, 24, 32, 32)])
+@pytest.mark.parametrize("act", [0, 1])
+def test_conv_pool_is_bitwise_conv_then_pool(env, B, H, W, ci, co, act):
+    """Convolution with the 2x2 pooling of its result: bitwise
+    qnn_conv3x3_fwd then qnn_avgpool2, pooled in the resident-weight epilogue
+    (32- and 16-wide tiles, partial and over-tall tiles, 64 channels as one
+    or two blocks) or by the two calls (128 channels, W not a multiple of
+    16)."""
+    torch, qnn = env
+    x, _ = bf(torch, rnd(60, (B, H, W, ci)))
+    w, _ = bf(torch, rnd(61, (co, 9, ci), 1 / np.sqrt(9 * ci)))
+    bias = torch.tensor(rnd(62, co).astype(np.float32)).cuda()
+    y0 = torch.empty((B, H, W, co), dtype=torch.bfloat16, device="cuda")
+    qnn.qnn_conv3x3_fwd(B, H, W, x, ci, w, bias, co, act, y0, 0, co, co)
+    p0 = torch.empty((B, H // 2, W // 2, co), dtype=torch.bfloat16, device="cuda")
+    qnn.qnn_avgpool2(B, H, W, co, y0, p0)
+    y1 = torch.full_like(y0, 3.0)
+    p1 = torch.full_like(p0, 3.0)
+    qnn.qnn_conv3x3_fwd_pool(B, H, W, x, ci, w, bias, co, act, y1, p1)
+    assert torch.equal(y1.view(torch.int16), y0.view(torch.int16))
+    assert torch.equal(p1.view(torch.int16), p0.view(torch.int16))
+
+
 @pytest.mark.parametrize("B,H,W,ci", [(2, 16, 32, 32), (3, 20, 48, 48), (2, 5, 64, 32), (40, 32, 64, 32)])
 @pytest.mark.parametrize("act", [0, 1])
 def test_conv_planes_is_bitwise_conv_then_unpack(env, B, H, W, ci, act):

@@ -1,7 +1,9 @@
 """The surrogate network at the size the inference benchmark runs it
-(lattices of 1024 x 1024, chunks of 8 lattices per pass): against the FP64
-oracle network on one lattice, and, for the whole 16-lattice batch, the
-translation property that holds at any size."""
+(lattices of 1024 x 1024, 16 lattices per pass): against the FP64 oracle
+network on one lattice, and, for the whole 16-lattice batch, the
+translation property that holds at any size. Also the convolution kernels
+next to the 31-bit element-offset limit, each against a kernel with its
+own indexing."""
 import numpy as np
 import pytest
 
@@ -75,3 +77,57 @@ def test_network_translation_equivariance_16x1024(env):
     net.predict(qs, ns, b)
     torch.cuda.synchronize()
     assert torch.equal(torch.roll(a, shifts=(48, 96), dims=(2, 3)), b)
+
+
+def _bf16_randn(torch, shape, scale, seed):
+    g = torch.Generator(device="cuda").manual_seed(seed)
+    return (torch.randn(shape, generator=g, device="cuda") * scale).to(torch.bfloat16)
+
+
+def test_resident_weight_kernels_at_the_offset_limit(env):
+    """32 lattices of 1024 x 1024 x 32 channels (2^30 elements, the largest
+    power of two under the limit): the resident-weight convolution and its
+    pooled form, bitwise against the pipelined kernel (the fused entry point
+    with neither upsampling nor skip) and the separate pooling."""
+    torch, _, _ = env
+    from paper_2301_13601_amd import qnn
+    B, H, W, C = 32, 1024, 1024, 32
+    _case(f"resident-weight conv and pool, {B}x{H}x{W}x{C}")
+    x = _bf16_randn(torch, (B, H, W, C), 0.5, 70)
+    w = _bf16_randn(torch, (C, 9, C), 1 / np.sqrt(9 * C), 71)
+    bias = torch.randn(C, device="cuda")
+    y_pipe = torch.empty((B, H, W, C), dtype=torch.bfloat16, device="cuda")
+    qnn.qnn_conv3x3_fwd_fused(B, H, W, x, C, 0, w, bias, C, 1, None, y_pipe, C)
+    y = torch.empty_like(y_pipe)
+    pool = torch.empty((B, H // 2, W // 2, C), dtype=torch.bfloat16, device="cuda")
+    qnn.qnn_conv3x3_fwd_pool(B, H, W, x, C, w, bias, C, 1, y, pool)
+    assert torch.equal(y.view(torch.int16), y_pipe.view(torch.int16))
+    del y
+    want = torch.empty_like(pool)
+    qnn.qnn_avgpool2(B, H, W, C, y_pipe, want)
+    assert torch.equal(pool.view(torch.int16), want.view(torch.int16))
+
+
+def test_window_kernel_at_the_offset_limit(env):
+    """16 lattices of 1024 x 1024, 64 -> 32 channels from a half-resolution
+    input plus a skip input (the upsampled input has 2^30 elements, the
+    limit's largest power of two): the window kernel bitwise against the
+    separate upsampling, pipelined convolution and addition."""
+    torch, _, _ = env
+    from paper_2301_13601_amd import qnn
+    B, H, W, ci, co = 16, 1024, 1024, 64, 32
+    _case(f"window conv, {B}x{H}x{W}, {ci}->{co} upsampled + skip")
+    x = _bf16_randn(torch, (B, H // 2, W // 2, ci), 0.5, 72)
+    w = _bf16_randn(torch, (co, 9, ci), 1 / np.sqrt(9 * ci), 73)
+    e = _bf16_randn(torch, (B, H, W, co), 1.0, 74)
+    bias = torch.randn(co, device="cuda")
+    got = torch.empty((B, H, W, co), dtype=torch.bfloat16, device="cuda")
+    qnn.qnn_conv3x3_fwd_fused(B, H, W, x, ci, 1, w, bias, co, 1, e, got, co)
+    u = torch.empty((B, H, W, ci), dtype=torch.bfloat16, device="cuda")
+    qnn.qnn_upsample2(B, H // 2, W // 2, ci, x, u)
+    d = torch.empty_like(got)
+    qnn.qnn_conv3x3_fwd(B, H, W, u, ci, w, bias, co, 1, d, 0, co, co)
+    del u
+    want = torch.empty_like(got)
+    qnn.qnn_add(d.numel(), d, e, want)
+    assert torch.equal(got.view(torch.int16), want.view(torch.int16))

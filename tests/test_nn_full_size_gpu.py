@@ -86,9 +86,10 @@ def _bf16_randn(torch, shape, scale, seed):
 
 def test_resident_weight_kernels_at_the_offset_limit(env):
     """32 lattices of 1024 x 1024 x 32 channels (2^30 elements, the largest
-    power of two under the limit): the resident-weight convolution and its
-    pooled form, bitwise against the pipelined kernel (the fused entry point
-    with neither upsampling nor skip) and the separate pooling."""
+    power of two under the limit): the resident-weight convolution, its
+    pooled form and its scaled-planes form, bitwise against the pipelined
+    kernel (the fused entry point with neither upsampling nor skip), the
+    separate pooling and the separate unpacking."""
     torch, _, _ = env
     from paper_2301_13601_amd import qnn
     B, H, W, C = 32, 1024, 1024, 32
@@ -106,6 +107,18 @@ def test_resident_weight_kernels_at_the_offset_limit(env):
     want = torch.empty_like(pool)
     qnn.qnn_avgpool2(B, H, W, C, y_pipe, want)
     assert torch.equal(pool.view(torch.int16), want.view(torch.int16))
+    del pool, want, y_pipe
+    # the output layer's planes against the FP32 result and the separate
+    # unpacking (whose indexing is its own)
+    scale = torch.rand(B, device="cuda") + 0.5
+    yf = torch.empty((B, H, W, 8), dtype=torch.float32, device="cuda")
+    qnn.qnn_conv3x3_fwd(B, H, W, x, C, w, bias, C, 0, yf, 1, 8, 6)
+    want_q = torch.empty((B, 6, H, W), dtype=torch.float32, device="cuda")
+    qnn.qnn_unpack_output(B, H, W, yf, 8, scale, want_q)
+    del yf
+    got_q = torch.empty_like(want_q)
+    qnn.qnn_conv3x3_fwd_planes(B, H, W, x, C, w, bias, C, 0, scale, 6, got_q)
+    assert torch.equal(got_q.view(torch.int32), want_q.view(torch.int32))
 
 
 def test_window_kernel_at_the_offset_limit(env):

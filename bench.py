@@ -204,7 +204,7 @@ def sweep_workload(args) -> dict:
     """Surrogate-accelerated sweep against plain QLA on the same GPU.
 
     Trains the U-net surrogate on QLA runs the library generates (2048 runs
-    at 256 x 256, snapshots every K = 256 steps), judges it on 256 held-out
+    at 256 x 256, snapshots every K = 256 steps), evaluates it on 256 held-out
     runs, then advances --sweep-lattices lattices of 1024 x 1024 (the
     batched scene family) by --steps steps four ways: plain QLA; the sweep
     with QLA checks at the first and every 4th jump and fallback at a 1e-3

@@ -1,5 +1,5 @@
 """Convolutional surrogate of K whole QLA steps, trained on the library's own
-runs, with plain QLA as its judge and fallback.
+runs, with plain QLA as its check and fallback.
 
 The network maps (Q(t), n) -> Q(t + K) on a periodic lattice (K = 256 by
 default). QLA is linear in Q for fixed n, so each sample is divided by its

@@ -53,7 +53,7 @@ def test_sweep_without_checks_uses_every_jump(env):
 
 def test_trained_network_error_and_sweep_gain(env):
     torch, scenes, S = env
-    _case("train 600 steps on 256 runs, judge on 32 held-out runs and a 4-lattice sweep")
+    _case("train 600 steps on 256 runs, evaluate on 32 held-out runs and a 4-lattice sweep")
     data = S.generate(256, seed=11, L=256, K=256, snaps=5)
     held = S.generate(32, seed=999, L=256, K=256, snaps=5)
     net = S.UNet(seed=0)

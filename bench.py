@@ -356,7 +356,7 @@ def unet_workload(args) -> dict:
                    "macs_per_pixel": S.macs_per_pixel(), "seconds_per_pixel": sec / pixels},
         "roofline": {"bound": "mfma", "achieved": flop / sec / 1e12, "peak": 2500.0, "unit": "TFLOP/s",
                      "frac": flop / sec / 1e12 / 2500.0, "traffic": None,
-                     "kernel": "whole network pass (the convolution kernels: ~85 % of it)"},
+                     "kernel": "whole network pass (the convolution kernels: ~90 % of it)"},
     }
     # training steps (forward, relative-L2 loss, backward, Adam) at batch 16
     # x 256^2 on pairs the library generates; flops per step: forward + data

@@ -57,6 +57,12 @@ class Conv:
         return self.c_out * 9 * self.c_in
 
 
+def default_chunk(H: int, W: int) -> int:
+    """Lattices per inference chunk: as many as the kernels' 31-bit element
+    offsets allow for the 48-channel packed input, at most 16, at least 1."""
+    return max(1, min(16, ((1 << 31) - 1) // (IN_CH * H * W)))
+
+
 def layer_specs() -> List[Conv]:
     L = qnn.QNN_ACT_LEAKY
     specs = [Conv("e0a", IN_CH, LEVELS[0], L, 0), Conv("e0", LEVELS[0], LEVELS[0], L, 0)]
@@ -264,7 +270,7 @@ class UNet:
         fewer, smaller launches leave the deep layers' grids short)."""
         B, _, H, W = q.shape
         if chunk <= 0:
-            chunk = max(1, min(16, ((1 << 31) - 1) // (IN_CH * H * W)))
+            chunk = default_chunk(H, W)
         for c0 in range(0, B, chunk):
             c1 = min(B, c0 + chunk)
             self.pack(c1 - c0, H, W, q[c0:c1], None, n[c0:c1], None)

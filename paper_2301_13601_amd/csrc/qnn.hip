@@ -2024,35 +2024,6 @@ int qnn_conv3x3_fwd_pool(int32_t B, int32_t H, int32_t W, const uint16_t* x, int
   return qnn_avgpool2(B, H, W, c_out, y, pool, hip_stream);
 }
 
-#ifdef QNN_TUNE_HOOK
-// geometry sweeps only (not part of the library's interface)
-int qnn_conv3x3_fwd_cfg(int32_t B, int32_t H, int32_t W, const uint16_t* x, int32_t c_in, const uint16_t* w,
-                        const float* bias, int32_t c_out, int32_t act, void* y, int32_t y_fp32, int32_t y_ld,
-                        int32_t c_store, int32_t mt, int32_t nt, float waves, void* hip_stream) {
-  if (!conv_pipe(mt, nt, B, H, W, x, c_in, 0, w, bias, act, nullptr, y, y_fp32 != 0, y_ld, c_store, c_out, waves,
-                 static_cast<hipStream_t>(hip_stream)))
-    return bad("conv3x3_fwd_cfg: geometry not supported");
-  return launched("conv3x3_fwd_cfg");
-}
-
-int qnn_conv3x3_fwd_res_cfg(int32_t B, int32_t H, int32_t W, const uint16_t* x, int32_t c_in, const uint16_t* w,
-                            const float* bias, int32_t c_out, int32_t act, void* y, int32_t y_fp32, int32_t y_ld,
-                            int32_t c_store, int32_t nt, int32_t tw, float waves, void* hip_stream) {
-  if (!conv_res(B, H, W, x, c_in, w, bias, act, nullptr, y, y_fp32 != 0, y_ld, c_store, c_out, nt, tw, waves,
-                static_cast<hipStream_t>(hip_stream)))
-    return bad("conv3x3_fwd_res_cfg: geometry not supported");
-  return launched("conv3x3_fwd_res_cfg");
-}
-
-int qnn_conv3x3_fwd_up_cfg(int32_t B, int32_t H, int32_t W, const uint16_t* x, int32_t c_in, const uint16_t* w,
-                           const float* bias, int32_t c_out, int32_t act, const uint16_t* add, uint16_t* y,
-                           int32_t y_ld, int32_t tw, float waves, void* hip_stream) {
-  if (!conv_up(B, H, W, x, c_in, w, bias, act, add, y, y_ld, c_out, tw, waves, static_cast<hipStream_t>(hip_stream)))
-    return bad("conv3x3_fwd_up_cfg: geometry not supported");
-  return launched("conv3x3_fwd_up_cfg");
-}
-#endif
-
 int qnn_conv3x3_flip(const uint16_t* w, int32_t c_out, int32_t c_in, uint16_t* wt, void* hip_stream) {
   if (!w || !wt || c_out < 1 || c_in < 1) return bad("conv3x3_flip: bad size or null pointer");
   const int64_t n = static_cast<int64_t>(c_out) * 9 * c_in;

@@ -94,6 +94,10 @@ def lib() -> ctypes.CDLL:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                               "or python -m paper_2301_13601_amd.build")
+        # torch first: its HIP runtime is then the one libqla.so binds to
+        # (a second copy of the runtime, loaded ahead of torch's, does not
+        # see the device torch has opened)
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         for name, (argtypes, restype) in _SIGNATURES.items():
             fn = getattr(L, name)

@@ -57,10 +57,23 @@ class Conv:
         return self.c_out * 9 * self.c_in
 
 
+def widest_per_pixel() -> int:
+    """Most elements per full-resolution pixel that one convolution reads
+    or writes at its own level: the packed input, and every layer's input
+    (for a decoder's first convolution, its 2x-upsampled input) and output,
+    divided by the 4^level pixels they are spread over. 64 for this network:
+    the level-1 output that decoder level 0 reads upsampled to full size."""
+    widest = IN_CH
+    for s in layer_specs():
+        widest = max(widest, -(-max(s.c_in, s.c_out) // 4 ** s.level))
+    return widest
+
+
 def default_chunk(H: int, W: int) -> int:
     """Lattices per inference chunk: as many as the kernels' 31-bit element
-    offsets allow for the 48-channel packed input, at most 16, at least 1."""
-    return max(1, min(16, ((1 << 31) - 1) // (IN_CH * H * W)))
+    offsets allow for the widest tensor of any layer, at most 16, at least
+    1."""
+    return max(1, min(16, ((1 << 31) - 1) // (widest_per_pixel() * H * W)))
 
 
 def layer_specs() -> List[Conv]:
@@ -266,7 +279,7 @@ class UNet:
     def predict(self, q, n, out_q, chunk: int = 0):
         """out_q[b] = network(q[b], n[b]) for lattices q [B][6][H][W] (FP32),
         in chunks of at most ``chunk`` lattices (0: as many as the kernels'
-        31-bit element offsets allow for the 48-channel input, at most 16;
+        31-bit element offsets allow for the widest layer tensor, at most 16;
         fewer, smaller launches leave the deep layers' grids short)."""
         B, _, H, W = q.shape
         if chunk <= 0:

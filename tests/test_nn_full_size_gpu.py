@@ -79,6 +79,34 @@ def test_network_translation_equivariance_16x1024(env):
     assert torch.equal(torch.roll(a, shifts=(48, 96), dims=(2, 3)), b)
 
 
+def test_predict_2048_in_chunks(env):
+    """Lattices of 2048 x 2048, the sweep's size: 8 of them take two chunks
+    (7 + 1, the offset limit of the upsampled 64-channel level-1 output).
+    Chunked prediction equals one-lattice-at-a-time prediction bitwise (each
+    lattice is scaled and computed on its own), and rolling the inputs by
+    multiples of 16 cells rolls the predictions bitwise."""
+    torch, scenes, S = env
+    L, B = 2048, 8
+    assert S.default_chunk(L, L) == 7
+    _case(f"{B} lattices of {L}x{L}, chunked vs single predictions")
+    q, n = _lattices(torch, scenes, B, L, 63)
+    net = S.UNet(seed=9)
+    a = torch.empty_like(q)
+    net.predict(q, n, a)
+    one = torch.empty_like(q)
+    net.predict(q, n, one, chunk=1)
+    torch.cuda.synchronize()
+    assert torch.equal(a, one)
+    assert torch.isfinite(a).all() and float(a.abs().max()) > 0
+    del one
+    qs = torch.roll(q[5:], shifts=(32, 2000), dims=(2, 3)).contiguous()
+    ns = torch.roll(n[5:], shifts=(32, 2000), dims=(2, 3)).contiguous()
+    b = torch.empty_like(qs)
+    net.predict(qs, ns, b)
+    torch.cuda.synchronize()
+    assert torch.equal(torch.roll(a[5:], shifts=(32, 2000), dims=(2, 3)), b)
+
+
 def _bf16_randn(torch, shape, scale, seed):
     g = torch.Generator(device="cuda").manual_seed(seed)
     return (torch.randn(shape, generator=g, device="cuda") * scale).to(torch.bfloat16)

@@ -118,9 +118,26 @@ __device__ __forceinline__ void pot_coef(float b, float& sb, float& hb) {
   }
 }
 
-// a' = cos(b) a + sgn * sin(b) p  ==  a - (1 - cos b) a + sgn sin(b) p
+// The potentials act once per half step and, unlike the collisions, are
+// not undone by a partner operator, so the rounding of their updates adds
+// up over a run. Both forms below therefore form the small increment first
+// and round the full value only once.
+//
+// a' = cos(b) a + sin(b) p  ==  a + (sin(b) p - (1 - cos b) a)
 __device__ __forceinline__ float pot_row(float a, float p, float sb, float hb) {
-  return fmaf(sb, p, fmaf(-hb, a, a));
+  return a + fmaf(sb, p, -(hb * a));
+}
+
+// Rotation of the pair (a, b) by SGN * phi (a' = cos a - sin b, b' = sin a +
+// cos b for SGN = +1) from s = sin(phi), h = 1 - cos(phi): each component
+// moves by its increment (-h a - s b, s a - h b), one rounding each.
+template <int SGN>
+__device__ __forceinline__ void rot_inc(float& a, float& b, float s, float h) {
+  const float sa = SGN > 0 ? s : -s;
+  const float da = fmaf(-h, a, -(sa * b));
+  const float db = fmaf(-h, b, sa * a);
+  a = a + da;
+  b = b + db;
 }
 
 // ---------------------------------------------------------------------------
@@ -242,8 +259,9 @@ struct Pipe {
   // collision coefficients (tan(theta_0/2), sin theta_0, tan(theta_2/2),
   // sin theta_2) of rows lag 1..4, slot = iteration mod 4
   float th[4][4][C];
-  // V_Y coefficients per row slot ((sin b, 1 - cos b) of beta_1 and beta_3,
-  // or (tan, sin) of the skew rotation angles), and whether the row has any
+  // V_Y coefficients per row slot ((sin phi, 1 - cos phi) of the applied
+  // angles of beta_1 and beta_3: phi = b for the printed potentials, b/2 for
+  // the skew rotations), and whether the row has any
   // nonzero y-difference of n_x or n_z (when it has none, beta_1 = beta_3 =
   // 0 and V_Y is exactly the identity)
   float vy[4][4][C];
@@ -283,14 +301,11 @@ struct YLags {
   static constexpr int before(int k) { return k == 0 ? 0 : after(k - 1); }
 };
 
-// Potential coefficients of an applied angle b: printed form (sin b,
-// 1 - cos b); skew form (tan(b/4), sin(b/2)) of the rotation by b/2.
+// Potential coefficients of an applied angle b: (sin phi, 1 - cos phi) with
+// phi = b for the printed form and phi = b/2 for the skew rotation by b/2.
 template <class O>
 __device__ __forceinline__ void vcoef(float b, float& c0, float& c1) {
-  if constexpr (O::SKEW)
-    rot_coef<O::WIDE>(0.5f * b, c0, c1);
-  else
-    pot_coef<O::WIDE>(b, c0, c1);
+  pot_coef<O::WIDE>(O::SKEW ? 0.5f * b : b, c0, c1);
 }
 
 // Prefetch of the rows a pipeline needs later: Q of row R+2*DIR (stage fed
@@ -506,8 +521,8 @@ __device__ __forceinline__ void process_row(Pipe<C>& p, const StepArgs& g, const
 #pragma unroll
     for (int k = 0; k < C; ++k) {
       if constexpr (O::SKEW) {
-        if constexpr (TM) rot<+1>(q4v[k], q2v[k], c20[k], c21[k]);
-        if constexpr (TE) rot<+1>(q1v[k], q5v[k], c00[k], c01[k]);
+        if constexpr (TM) rot_inc<+1>(q4v[k], q2v[k], c20[k], c21[k]);
+        if constexpr (TE) rot_inc<+1>(q1v[k], q5v[k], c00[k], c01[k]);
       } else {
         if constexpr (TM) q4v[k] = pot_row(q4v[k], -q2v[k], c20[k], c21[k]);
         if constexpr (TE) q5v[k] = pot_row(q5v[k], q1v[k], c00[k], c01[k]);
@@ -604,8 +619,8 @@ __device__ __forceinline__ void process_row(Pipe<C>& p, const StepArgs& g, const
 #pragma unroll
       for (int k = 0; k < C; ++k) {
         if constexpr (O::SKEW) {
-          if constexpr (TM) rot<+1>(b2[k], b3[k], p.vy[sl][2][k], p.vy[sl][3][k]);
-          if constexpr (TE) rot<-1>(a0[k], a5[k], p.vy[sl][0][k], p.vy[sl][1][k]);
+          if constexpr (TM) rot_inc<+1>(b2[k], b3[k], p.vy[sl][2][k], p.vy[sl][3][k]);
+          if constexpr (TE) rot_inc<-1>(a0[k], a5[k], p.vy[sl][0][k], p.vy[sl][1][k]);
         } else {
           if constexpr (TM) b3[k] = pot_row(b3[k], b2[k], p.vy[sl][2][k], p.vy[sl][3][k]);
           if constexpr (TE) a5[k] = pot_row(a5[k], -a0[k], p.vy[sl][0][k], p.vy[sl][1][k]);

@@ -10,12 +10,16 @@ QLA time step of the whole lattice. Inputs are resident in HBM before the
 timed region starts.
 
 Prints one JSON line with the site-update rate, the roofline of the step
-kernel (algorithmic bytes: 24 B read + 24 B written of FP32 state and 12 B
-of FP32 index per site-update) and the FP64 oracle timed on the host cores
-on a bounded sample of the same workload. For a single-polarisation
-workload it also times the polarised kernel (the E_z triple only: 12 B
-read + 12 B written + 4 B of n_z per site-update, results bitwise equal on
-that triple) and reports it beside, not as, the headline value.
+kernel and the FP64 oracle timed on the host cores on a bounded sample of
+the same workload. The step kernel's algorithmic HBM bytes are 24 B read +
+24 B written of FP32 state and 12 B of FP32 index per site and launch; a
+launch that fuses two steps moves them once for two site-updates, so the
+roofline's `frac` is that traffic's rate against the HBM peak, and
+`site_update_rate_frac` (site-updates/s x 60 B / peak) the same rate
+counted per site-update. For a single-polarisation workload it also times
+the polarised kernel (the E_z triple only: 12 B read + 12 B written + 4 B
+of n_z per site and launch, results bitwise equal on that triple) and
+reports it beside, not as, the headline value.
 """
 from __future__ import annotations
 
@@ -49,10 +53,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(triple: str = "all"):
-    """HBM bytes per step-kernel launch (triple "all" or "tm") from the
-    committed rocprofv3 counter runs, if they were taken on the current
-    kernel source."""
+def measured_record(triple: str = "all"):
+    """The committed counter summary of a step-kernel instance (triple
+    "all" or "tm"): HBM bytes per launch and, when recorded, the VALU busy
+    share; None unless it was taken on the current kernel source."""
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f)
@@ -60,7 +64,35 @@ def measured_traffic(triple: str = "all"):
         return None
     if rec.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
-    return rec.get("kernels", {}).get(triple, {}).get("bytes_per_launch")
+    return rec.get("kernels", {}).get(triple)
+
+
+def measured_traffic(triple: str = "all"):
+    """HBM bytes per step-kernel launch from the committed counter runs, if
+    they were taken on the current kernel source."""
+    rec = measured_record(triple)
+    return rec.get("bytes_per_launch") if rec else None
+
+
+def copy_bandwidth_gbs(dev, mib: int = 1024, reps: int = 5) -> float:
+    """Device-to-device copy rate of this GPU (bytes read + written per
+    second, best of a few 1 GiB copies): the practical HBM ceiling beside
+    the published peak."""
+    import torch
+    a = torch.empty(mib * (1 << 18), dtype=torch.float32, device=dev).fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1) / 1e3)
+    del a, b
+    return 2.0 * mib * (1 << 20) / best / 1e9
 
 
 _TRIPLE_NAMES = {"0": "all", "1": "tm", "2": "te"}
@@ -136,26 +168,47 @@ def make_workload(name: str, steps: int):
     return sc, desc
 
 
-def cpu_baseline(sc, sample_steps: int, sample_n: int, pot_mode: str = "eq28", v_form: str = "printed"):
+def cpu_baseline(sc, sample_steps: int, sample_n: int, pot_mode: str = "eq28", v_form: str = "printed",
+                 one_core_n: int = 1024, one_core_steps: int = 6):
     """The FP64 oracle on the host cores, on a sample of the workload: the
-    same scene generator at sample_n x sample_n for sample_steps steps."""
+    same scene generator at sample_n x sample_n for sample_steps steps on
+    every host thread; beside it the same on one thread (one_core_n^2 for
+    one_core_steps steps) and the whole 256 x 256, 500-step parity run (the
+    elliptic-object scene) on every thread."""
     from oracle import oracle as O
     from paper_2301_13601_amd import scenes
-    if sample_n == sc.nx:
-        n, q = sc.n, sc.q
-    else:
-        s2 = scenes.config_scale(seed=2, N=sample_n, steps=sample_steps)
-        n, q = s2.n, s2.q
-    n32 = n.astype(np.float32).astype(np.float64)
-    q32 = q.astype(np.float32).astype(np.float64)
+
+    def sample(N, steps):
+        if N == sc.nx:
+            return sc.n, sc.q
+        s2 = scenes.config_scale(seed=2, N=N, steps=steps)
+        return s2.n, s2.q
+
+    def timed(n, q, delta, steps, nthreads):
+        n32 = n.astype(np.float32).astype(np.float64)
+        q32 = q.astype(np.float32).astype(np.float64)
+        t0 = time.perf_counter()
+        O.run(n32, q32, delta, steps, pot_mode, "phys", nthreads=nthreads, v_form=v_form)
+        return time.perf_counter() - t0
+
     threads = O.threads(0)
-    t0 = time.perf_counter()
-    O.run(n32, q32, sc.delta, sample_steps, pot_mode, "phys", v_form=v_form)
-    dt = time.perf_counter() - t0
+    n, q = sample(sample_n, sample_steps)
+    dt = timed(n, q, sc.delta, sample_steps, threads)
     rate = sample_n * sample_n * sample_steps / dt
+    n1, q1 = sample(one_core_n, one_core_steps)
+    dt1 = timed(n1, q1, sc.delta, one_core_steps, 1)
+    O.threads(threads)
+    c1 = scenes.config_single()
+    dtc = timed(c1.n, c1.q, c1.delta, c1.steps, threads)
+    sites_c1 = c1.nx * c1.ny * c1.steps
     return {"value": rate, "unit": "site-updates/s", "cores": threads, "kind": "oracle",
             "sample": f"{sample_n}x{sample_n} lattice of the same scene family, {sample_steps} steps, "
-                      f"{dt:.1f} s wall, FP64, OpenMP over {threads} threads"}
+                      f"{dt:.1f} s wall, FP64, OpenMP over {threads} threads",
+            "one_core": {"value": one_core_n * one_core_n * one_core_steps / dt1, "unit": "site-updates/s",
+                         "cores": 1, "sample": f"{one_core_n}x{one_core_n}, {one_core_steps} steps, {dt1:.1f} s wall"},
+            "single_256_full_run": {"seconds": dtc, "value": sites_c1 / dtc, "unit": "site-updates/s",
+                                    "cores": threads,
+                                    "sample": "the whole 256x256 elliptic-object run, 500 steps (parity scene)"}}
 
 
 def is_tm_only(q) -> bool:
@@ -192,12 +245,16 @@ def time_polarised(make_sim, stream, sites: int, steps: int, warmup: int, traffi
     spp = sim.launch()["steps_per_pass"]
     avg = sum(a.elapsed_time(b) for a, b, _ in ev) / 1e3 / (steps // spp)
     sim.close()
-    achieved = spp * sites * TM_BYTES_PER_SITE / avg / 1e9
+    achieved = sites * TM_BYTES_PER_SITE / avg / 1e9
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "avg_launch_us": avg * 1e6,
+            "steps_per_launch": spp, "algo_bytes_per_launch": sites * TM_BYTES_PER_SITE,
+            "site_update_rate_frac": spp * sites * TM_BYTES_PER_SITE / avg / 1e9 / HBM_PEAK_GBS}
+    if traffic:
+        roof["traffic_gbs"] = traffic / avg / 1e9
+        roof["traffic_frac"] = roof["traffic_gbs"] / HBM_PEAK_GBS
     return {"polarisation": "tm (q2, q3, q4 = n_z E_z, B_x, B_y)", "steps": steps,
-            "value": sites * steps / wall, "unit": "site-updates/s",
-            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "avg_launch_us": avg * 1e6,
-                         "steps_per_launch": spp, "algo_bytes_per_site": TM_BYTES_PER_SITE}}
+            "value": sites * steps / wall, "unit": "site-updates/s", "roofline": roof}
 
 
 def sweep_workload(args) -> dict:
@@ -396,7 +453,7 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None,
-                    help="timed steps (default 20000; sweep 4096; unet_forward 20 passes)")
+                    help="timed steps (default 20000; batch_64 5000; sweep 4096; unet_forward 20 passes)")
     ap.add_argument("--warmup", type=int, default=None, help="untimed steps first (default 100; unet_forward 3)")
     ap.add_argument("--workload", default="cylinder_4096",
                     choices=["cylinder_4096", "single_256", "batch_64", "sweep", "unet_forward"])
@@ -422,7 +479,7 @@ def main():
                     help="summarise rocprofv3 counter CSVs into the committed traffic record and exit")
     args = ap.parse_args()
     if args.steps is None:
-        args.steps = {"sweep": 4096, "unet_forward": 20}.get(args.workload, 20000)
+        args.steps = {"sweep": 4096, "unet_forward": 20, "batch_64": 5000}.get(args.workload, 20000)
     if args.warmup is None:
         args.warmup = 3 if args.workload == "unet_forward" else 100
 
@@ -532,20 +589,29 @@ def main():
         del a, b
 
     value = sites * args.steps / wall
-    # one launch advances spp steps: spp site-updates per site, 60 B each
-    algo_bytes = spp * sites * ALGO_BYTES_PER_SITE
+    # Algorithmic HBM bytes of one launch: whatever number of steps a launch
+    # fuses (spp), it has to read Q and n once and write Q once, 60 B per
+    # site. Per site-update that is 60 / spp B.
+    algo_bytes = sites * ALGO_BYTES_PER_SITE
     achieved = algo_bytes / avg_launch_s / 1e9
     # the committed counters were taken on the default kernel instance
     default_kernel = args.pot_mode == "eq28" and args.v_form == "printed"
-    traffic = measured_traffic("all") if args.workload == "cylinder_4096" and default_kernel else None
+    rec = measured_record("all") if args.workload == "cylinder_4096" and default_kernel else None
+    traffic = rec.get("bytes_per_launch") if rec else None
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "kernel": "qla_step_kernel", "avg_launch_us": avg_launch_s * 1e6, "steps_per_launch": spp,
                 "algo_bytes_per_launch": algo_bytes,
-                # a launch of spp steps must still read Q and n once and write
-                # Q once: the HBM floor of one launch, and its share of peak
-                "min_hbm_bytes_per_launch": sites * ALGO_BYTES_PER_SITE,
-                "min_hbm_frac": sites * ALGO_BYTES_PER_SITE / avg_launch_s / 1e9 / HBM_PEAK_GBS}
+                "algo_bytes_per_site_update": ALGO_BYTES_PER_SITE / spp,
+                # the metric's %HBM roofline: site-updates/s x 60 B / peak. A
+                # rate, not a bandwidth: above 1 once a launch fuses steps
+                "site_update_rate_frac": spp * sites * ALGO_BYTES_PER_SITE / avg_launch_s / 1e9 / HBM_PEAK_GBS,
+                "copy_gbs": copy_bandwidth_gbs(dev)}
+    if traffic:
+        roofline["traffic_gbs"] = traffic / avg_launch_s / 1e9
+        roofline["traffic_frac"] = roofline["traffic_gbs"] / HBM_PEAK_GBS
+    if rec and "valu_busy" in rec:
+        roofline["valu_busy"] = rec["valu_busy"]
 
     out = {
         "metric": "lattice site-updates/s",

@@ -193,6 +193,23 @@ qla_status qla_step(qla_ctx *ctx, int64_t nsteps);
  * entry per lattice, in batch order. Synchronises the stream. */
 qla_status qla_energy(qla_ctx *ctx, qla_diag *out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * diagnostics of qla_energy for one state given by its buffers, with no
+ * context and no workspace. p gives the lattice (nx, ny; the other fields
+ * are checked as for qla_init but not used); d_n (3*ny*nx FP32) and d_q
+ * (6*ny*nx FP32) are laid out as for qla_init; d_out is device memory,
+ * 8-byte aligned, that receives one qla_diag with its step field set to
+ * `step`. Enqueued on hip_stream: two kernel launches, no synchronisation,
+ * no allocation, no memset, no copy. The per-block partial sums go to a
+ * static device buffer of 64 KiB per GPU (1024 blocks of partials, enough
+ * for every lattice size; it is held until the process ends). Calls that
+ * overlap on one GPU share that buffer and race: serialise them (one
+ * stream, or events). Errors: QLA_EINVAL for bad parameters or null or
+ * misaligned pointers, QLA_EDEVICE if a launch fails. */
+qla_status qla_energy_noalloc(const qla_params *p, const float *d_n, const float *d_q, int64_t step,
+                              qla_diag *d_out, void *hip_stream);
+
 /* Copy the current state of every lattice to dst, lattices back to back in
  * batch order, 6*ny*nx FP32 each.
  *   what = 0: Q as stored;  what = 1: (E, B) with E_c = q_c / n_c (Eq. (15));

@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -179,9 +180,9 @@ __global__ void __launch_bounds__(256) qla_diag_kernel(const float* __restrict__
   }
 }
 
-__global__ void qla_diag_final(double* __restrict__ parts, int count) {
-  // one wave; parts[count * kDiagVals ..] receives the folded values
-  double v[kDiagVals];
+// Sums and maxima of the per-block partials over `count` blocks, by one
+// wave; every lane ends with the folded values.
+__device__ __forceinline__ void diag_fold(const double* __restrict__ parts, int count, double (&v)[kDiagVals]) {
   for (int j = 0; j < kDiagVals; ++j) v[j] = 0.0;   // sums and maxima of non-negative values
   for (int k = threadIdx.x; k < count; k += blockDim.x) {
     const double* o = parts + static_cast<int64_t>(k) * kDiagVals;
@@ -190,8 +191,35 @@ __global__ void qla_diag_final(double* __restrict__ parts, int count) {
   }
   v[0] = wave_sum(v[0]); v[1] = wave_sum(v[1]); v[4] = wave_sum(v[4]); v[5] = wave_sum(v[5]);
   v[2] = wave_max(v[2]); v[3] = wave_max(v[3]); v[6] = wave_max(v[6]); v[7] = wave_max(v[7]);
+}
+
+__global__ void qla_diag_final(double* __restrict__ parts, int count) {
+  // one wave; parts[count * kDiagVals ..] receives the folded values
+  double v[kDiagVals];
+  diag_fold(parts, count, v);
   if (threadIdx.x == 0)
     for (int j = 0; j < kDiagVals; ++j) parts[static_cast<int64_t>(count) * kDiagVals + j] = v[j];
+}
+
+// One wave: the folded partials as a finished qla_diag in device memory
+// (the same conversion qla_energy makes on the host).
+__global__ void qla_diag_finish(const double* __restrict__ parts, int count, int64_t plane, int64_t step,
+                                qla_diag* __restrict__ out) {
+  double v[kDiagVals];
+  diag_fold(parts, count, v);
+  if (threadIdx.x == 0) {
+    qla_diag o;
+    o.step = step;
+    o.energy = v[0] / static_cast<double>(plane);
+    o.divB_l2 = sqrt(v[1]);
+    o.divB_max = v[2];
+    o.B_max = sqrt(v[3]);
+    o.B_l2 = sqrt(v[4]);
+    o.divD_l2 = sqrt(v[5]);
+    o.divD_max = v[6];
+    o.D_max = sqrt(v[7]);
+    *out = o;
+  }
 }
 
 // E_c = q_c / n_c for c < 3, B copied: (E, B) planes of Eq. (15).
@@ -219,6 +247,13 @@ __global__ void __launch_bounds__(256) qla_clear_kernel(float* __restrict__ q, i
 
 
 }  // namespace
+
+// Device buffer of qla_energy_noalloc: the per-block partials of one
+// diagnostics call, kDiagBlocks blocks of kDiagVals doubles (64 KiB). Each
+// GPU holds its own copy until the process ends; host code reaches it only
+// through the address hipGetSymbolAddress returns on that GPU.
+constexpr int kNoAllocDoubles = kDiagBlocks * kDiagVals;
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
 
 // ===========================================================================
 // Host side.
@@ -666,6 +701,29 @@ qla_status init_common(int32_t count, const qla_instance* inst, void* d_work, vo
   return QLA_OK;
 }
 
+// This device's address of `scratch`, looked up on the first call on each
+// device with that device current (every GPU holds its own copy).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+double* g_scratch[kMaxDevices] = {};
+
+qla_status device_scratch(double** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "querying the current device");
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(QLA_EINVAL, "qla: device %d is beyond the %d devices this library tracks", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(nullptr, e, "looking up the static diagnostics buffer");
+    g_scratch[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch[dev];
+  return QLA_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -769,6 +827,28 @@ qla_status qla_energy(qla_ctx* ctx, qla_diag* out) {
     o.divD_max = v[6];
     o.D_max = std::sqrt(v[7]);
   }
+  return QLA_OK;
+}
+
+qla_status qla_energy_noalloc(const qla_params* p, const float* d_n, const float* d_q, int64_t step,
+                              qla_diag* d_out, void* hip_stream) {
+  qla_status st = check_params(p);
+  if (st != QLA_OK) return st;
+  if (!d_n || !d_q || !d_out) return fail(QLA_EINVAL, "qla: null device pointer");
+  if ((reinterpret_cast<uintptr_t>(d_out) & 7) != 0) return fail(QLA_EINVAL, "qla: d_out must be 8-byte aligned");
+  const int64_t plane = static_cast<int64_t>(p->nx) * p->ny;
+  const int blocks = static_cast<int>(std::min<int64_t>((plane + 255) / 256, kDiagBlocks));
+  if (static_cast<int64_t>(blocks) * kDiagVals > kNoAllocDoubles)
+    return fail(QLA_EINVAL, "qla: %d diagnostics blocks exceed the static buffer of %d", blocks,
+                kNoAllocDoubles / kDiagVals);
+  double* parts = nullptr;
+  st = device_scratch(&parts);
+  if (st != QLA_OK) return st;
+  const hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  hipLaunchKernelGGL(qla_diag_kernel, dim3(blocks), dim3(256), 0, s, d_q, d_n, p->nx, p->ny, parts);
+  hipLaunchKernelGGL(qla_diag_finish, dim3(1), dim3(kWave), 0, s, parts, blocks, plane, step, d_out);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(nullptr, e, "launching the diagnostics");
   return QLA_OK;
 }
 

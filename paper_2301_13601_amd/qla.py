@@ -74,6 +74,8 @@ _SIGNATURES = {
     "qla_count": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
     "qla_step": ([ctypes.c_void_p, ctypes.c_int64], ctypes.c_int),
     "qla_energy": ([ctypes.c_void_p, ctypes.POINTER(Diag)], ctypes.c_int),
+    "qla_energy_noalloc": ([ctypes.POINTER(Params), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                            ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     "qla_fields": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
     "qla_fields_at": ([ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32],
                       ctypes.c_int),
@@ -173,6 +175,13 @@ def qla_energy(ctx, count: int = 1):
     _check(lib().qla_energy(ctx, d))
     out = [x.as_dict() for x in d]
     return out[0] if count == 1 else out
+
+
+def qla_energy_noalloc(params: Params, d_n: int, d_q: int, step: int, d_out: int, stream: int) -> None:
+    """Enqueue the diagnostics of the state at d_q into the qla_diag at
+    device address d_out (no allocation, no synchronisation)."""
+    _check(lib().qla_energy_noalloc(ctypes.byref(params), ctypes.c_void_p(d_n), ctypes.c_void_p(d_q),
+                                    int(step), ctypes.c_void_p(d_out), ctypes.c_void_p(stream)))
 
 
 def qla_fields(ctx, dst: int, what: int, dst_is_host: bool) -> None:

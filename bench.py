@@ -106,12 +106,19 @@ def _triple_of(kernel_name: str):
     return _TRIPLE_NAMES.get(m.group(1)) if m else None
 
 
-def summarize_counters(fetch_csv: str, write_csv: str, copy_mib: int, out_path: str) -> dict:
+SIMDS = 256 * 4                  # MI355X: 256 compute units of 4 SIMDs
+XCDS = 8                         # GRBM_GUI_ACTIVE sums the busy cycles of the 8 XCDs
+VALU_CYCLES = 4                  # a wave64 VALU instruction holds a 16-lane SIMD 4 cycles
+
+
+def summarize_counters(fetch_csv: str, write_csv: str, copy_mib: int, out_path: str, sq_csv: str = None) -> dict:
     """Turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per
     dispatch) of this script into HBM bytes per step-kernel launch, per
     kernel instance (all six components, TM triple), scaled by what the same
     counters read for the plain device copy of copy_mib MiB the runs include
-    (--calib-copy-mib)."""
+    (--calib-copy-mib). With a third run of SQ_INSTS_VALU and
+    GRBM_GUI_ACTIVE, also the share of the SIMDs' cycles that issued VALU
+    instructions during the step kernel (valu_busy)."""
     import csv
 
     def rows(path):
@@ -139,6 +146,19 @@ def summarize_counters(fetch_csv: str, write_csv: str, copy_mib: int, out_path: 
     for k in out["kernels"].values():
         if "fetch" in k and "write" in k:
             k["bytes_per_launch"] = k["fetch"]["bytes_per_launch"] + k["write"]["bytes_per_launch"]
+    if sq_csv:
+        per = {}
+        for r in rows(sq_csv):
+            t = _triple_of(r["Kernel_Name"])
+            if t is not None:
+                per.setdefault(t, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+        for t, cs in per.items():
+            valu = sum(cs["SQ_INSTS_VALU"]) / len(cs["SQ_INSTS_VALU"])
+            grbm = sum(cs["GRBM_GUI_ACTIVE"]) / len(cs["GRBM_GUI_ACTIVE"])
+            k = out["kernels"].setdefault(t, {})
+            k["sq_insts_valu_per_launch"] = valu
+            k["grbm_gui_active_per_launch"] = grbm
+            k["valu_busy"] = valu * VALU_CYCLES / (SIMDS * grbm / XCDS)
     with open(out_path, "w") as f:
         json.dump(out, f, indent=1)
     return out
@@ -475,8 +495,9 @@ def main():
                     help="steps of the polarised (E_z triple) kernel timed after the headline run; 0 skips")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one device copy of this many MiB (counter calibration)")
-    ap.add_argument("--counters", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_MIB"),
-                    help="summarise rocprofv3 counter CSVs into the committed traffic record and exit")
+    ap.add_argument("--counters", nargs="+", metavar="CSV",
+                    help="FETCH_CSV WRITE_CSV COPY_MIB [SQ_CSV]: summarise rocprofv3 counter CSVs into the "
+                         "committed traffic record and exit")
     args = ap.parse_args()
     if args.steps is None:
         args.steps = {"sweep": 4096, "unet_forward": 20, "batch_64": 5000}.get(args.workload, 20000)
@@ -484,7 +505,10 @@ def main():
         args.warmup = 3 if args.workload == "unet_forward" else 100
 
     if args.counters:
-        rec = summarize_counters(args.counters[0], args.counters[1], int(args.counters[2]), TRAFFIC_FILE)
+        c = args.counters
+        if len(c) not in (3, 4):
+            raise SystemExit("--counters takes FETCH_CSV WRITE_CSV COPY_MIB [SQ_CSV]")
+        rec = summarize_counters(c[0], c[1], int(c[2]), TRAFFIC_FILE, c[3] if len(c) == 4 else None)
         print(json.dumps(rec))
         return
 

@@ -281,44 +281,78 @@ def sweep_workload(args) -> dict:
     """Surrogate-accelerated sweep against plain QLA on the same GPU.
 
     Trains the U-net surrogate on QLA runs the library generates (2048 runs
-    at 256 x 256, snapshots every K = 256 steps), evaluates it on 256 held-out
-    runs, then advances --sweep-lattices lattices of 1024 x 1024 (the
-    batched scene family) by --steps steps four ways: plain QLA; the sweep
-    with QLA checks at the first and every 4th jump and fallback at a 1e-3
-    relative field or energy error; the same with a 0.25 tolerance (which
-    this network passes); and surrogate jumps with no checks.
-    value = plain QLA seconds / checked-sweep seconds, at the final field
-    error the record states (max over lattices of |Q - Q_plain| / |Q_plain|)."""
+    at 256 x 256, snapshots every K = 256 steps) or loads the weights a
+    previous run saved (--net-file), evaluates it on 256 held-out runs, then
+    advances --sweep-lattices lattices of --sweep-side^2 (the batched scene
+    family, seed 5) by --steps steps: plain QLA; the checked sweep (QLA
+    checks at the first and every --check-every-th jump, fallback when the
+    field or energy error of a check exceeds the tolerance) at each of
+    --tolerances; and surrogate jumps with no checks.
+    value = plain QLA seconds / checked-sweep seconds at the last (tightest)
+    tolerance, 1e-3 by default, at the final field error the record states
+    (max over lattices of |Q - Q_plain| / |Q_plain|)."""
     import torch
-    from paper_2301_13601_amd import scenes, surrogate as S
+    from paper_2301_13601_amd import qnn, scenes, surrogate as S
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     K = 256
-    t0 = time.perf_counter()
-    data = S.generate(2048, seed=11, L=256, K=K, snaps=9)
-    held = S.generate(256, seed=999, L=256, K=K, snaps=9)
-    gen_s = time.perf_counter() - t0
+    tols = [float(v) for v in args.tolerances.split(",")]
+    log = lambda msg: print(f"[sweep] {msg}", file=sys.stderr, flush=True)
+    last = [time.perf_counter()]
+
+    def tick(k):
+        # a progress line at most every 20 s of a long sweep
+        if time.perf_counter() - last[0] > 20.0:
+            last[0] = time.perf_counter()
+            log(f"  {k} steps")
     net = S.UNet(seed=0)
-    t0 = time.perf_counter()
-    S.train(net, data, steps=args.train_steps, batch=16, lr=1e-3, seed=1, log_every=0)
-    torch.cuda.synchronize()
-    train_s = time.perf_counter() - t0
+    netrec = {"train_runs": 2048}
+    if args.net_file and os.path.exists(args.net_file):
+        with np.load(args.net_file) as z:
+            net.load({k: z[k] for k in z.files})
+        netrec.update({"loaded_from": os.path.basename(args.net_file), "train_steps": int(net.t)})
+        log(f"network loaded from {args.net_file} ({net.t} Adam steps)")
+    else:
+        t0 = time.perf_counter()
+        data = S.generate(2048, seed=11, L=256, K=K, snaps=9)
+        netrec["data_seconds"] = time.perf_counter() - t0
+        log(f"data: {netrec['data_seconds']:.1f} s")
+        t0 = time.perf_counter()
+        S.train(net, data, steps=args.train_steps, batch=16, lr=args.lr, seed=1, log_every=5000,
+                log=lambda r: log(f"train step {r['step']} loss {r['loss']:.4f}"
+                                  + (f" rolled back, lr x{r['lr_scale']:g}" if r.get("rolled_back") else "")))
+        torch.cuda.synchronize()
+        netrec.update({"train_steps": args.train_steps, "peak_lr": args.lr, "train_seconds": time.perf_counter() - t0})
+        del data
+        if args.net_file:
+            np.savez(args.net_file, **net.state())
+    held = S.generate(256, seed=999, L=256, K=K, snaps=9)
     err = S.evaluate(net, held)
-    del data, held
+    del held
+    netrec.update({"heldout_median_error": float(np.median(err)), "heldout_p90_error": float(np.percentile(err, 90)),
+                   "macs_per_pixel": S.macs_per_pixel()})
+    log(f"held-out median error {netrec['heldout_median_error']:.4f}")
 
-    L = 1024
-    specs = scenes.batch_instance_specs(args.sweep_lattices, seed=5, sides=(L,))
-    scs = [scenes.scene_from_spec(sp, steps=args.steps) for sp in specs]
-    ns = [s.n.astype(np.float32) for s in scs]
-    qs = [s.q.astype(np.float32) for s in scs]
-    delta = scs[0].delta
-    steps = args.steps
+    L, B, steps = args.sweep_side, args.sweep_lattices, args.steps
+    specs = scenes.batch_instance_specs(B, seed=5, sides=(L,))
+    # one device tensor each for every lattice's n and initial Q, filled a
+    # lattice at a time (a 256 x 2048^2 batch would not fit host memory in
+    # FP64 at once); the lists hold views of them
+    n_all = torch.empty((B, 3, L, L), dtype=torch.float32, device=dev)
+    q_all = torch.empty((B, 6, L, L), dtype=torch.float32, device=dev)
+    for k, sp in enumerate(specs):
+        sc = scenes.scene_from_spec(sp, steps=steps)
+        n_all[k].copy_(torch.as_tensor(sc.n.astype(np.float32)))
+        q_all[k].copy_(torch.as_tensor(sc.q.astype(np.float32)))
+        delta = sc.delta
+    ns, qs = list(n_all), list(q_all)
+    log(f"{B} scenes of {L}x{L} on the device")
 
-    # forward throughput of the network on these lattices
-    B = len(ns)
-    cur = torch.as_tensor(np.stack(qs)).to(dev)
-    n_dev = torch.as_tensor(np.stack(ns)).to(dev)
+    # forward throughput of the network on these lattices (one chunk)
+    c = min(B, S.default_chunk(L, L))
+    cur = q_all[:c].clone()
+    n_dev = n_all[:c]
     out = torch.empty_like(cur)
     net.predict(cur, n_dev, out)
     torch.cuda.synchronize()
@@ -328,21 +362,46 @@ def sweep_workload(args) -> dict:
     e1.record(net.stream)
     torch.cuda.synchronize()
     fwd_s = e0.elapsed_time(e1) / 1e3
-    flops = 2.0 * S.macs_per_pixel() * B * L * L
-    del cur, out
+    del cur, out, n_dev
 
-    plain_s, plain = S.plain(ns, qs, delta, steps, stream=net.stream)
+    plain_out = torch.empty((B, 6, L, L), dtype=torch.float32, device=dev)
+    plain_s, _ = S.plain(ns, qs, delta, steps, stream=net.stream, out=plain_out,
+                         progress=lambda k: log(f"plain QLA: {k} steps"))
+    log(f"plain QLA {plain_s:.1f} s")
+    rel = torch.empty(B, dtype=torch.float64, device=dev)
+    en = torch.empty(B, dtype=torch.float64, device=dev)
+    work = torch.empty(qnn.qnn_compare_work_doubles(B), dtype=torch.float64, device=dev)
+    fin = torch.empty_like(plain_out)
 
-    def field_err(finals):
-        return max(float(np.linalg.norm(a.astype(np.float64) - b) / np.linalg.norm(b.astype(np.float64)))
-                   for a, b in zip(finals, plain))
+    def final_error():
+        qnn.qnn_compare(B, 6 * L * L, fin, plain_out, rel, en, work, net.stream)
+        return float(rel.max().item())
 
-    chk, chk_f = S.sweep(net, ns, qs, delta, steps, K=K, check_every=4, tol=1e-3)
-    loose, loose_f = S.sweep(net, ns, qs, delta, steps, K=K, check_every=4, tol=0.25)
-    free, free_f = S.sweep(net, ns, qs, delta, steps, K=K, check_every=0)
+    def record(res, tol=None):
+        r = {"seconds": res.seconds, "speedup": plain_s / res.seconds, "final_field_error": final_error(),
+             "jumps": res.jumps, "unchecked": res.unchecked, "checks": res.checks, "rejected": res.rejected,
+             "fell_back": res.fell_back, "max_check_error": res.max_check_error,
+             "max_check_energy": res.max_check_energy, "energy_change": res.energy_change}
+        if tol is not None:
+            r = {"tolerance": tol, **r}
+        return r
+
+    table = []
+    for tol in tols:
+        res, _ = S.sweep(net, ns, qs, delta, steps, K=K, window=args.sweep_window, check_every=args.check_every,
+                         tol=tol, out=fin, progress=tick)
+        table.append(record(res, tol))
+        log(f"tol {tol:g}: {table[-1]['speedup']:.2f}x, final error {table[-1]['final_field_error']:.3e}, "
+            f"fell back {res.fell_back}")
+    unchecked = None
+    if not args.no_unchecked:
+        free, _ = S.sweep(net, ns, qs, delta, steps, K=K, check_every=0, out=fin, progress=tick)
+        unchecked = record(free)
+        log(f"unchecked: {unchecked['speedup']:.2f}x, final error {unchecked['final_field_error']:.3e}")
+    stated = table[-1]
     return {
         "metric": "surrogate vs plain QLA speedup at stated field error",
-        "value": plain_s / chk.seconds,
+        "value": stated["speedup"],
         "unit": "x",
         "n_gpus": 1,
         "steps": steps,
@@ -352,27 +411,18 @@ def sweep_workload(args) -> dict:
         "vs_baseline": None,
         "dtype": "f32 QLA, bf16 x bf16 -> f32 network",
         "data": "synthetic",
-        "stated_error": field_err(chk_f),
-        "config": {"workload": f"sweep: {B} lattices of {L}x{L} (batched scene family, seed 5), "
-                               f"{steps} steps, surrogate jumps of K={K}, checks at the first and every "
-                               "4th jump, fallback at 1e-3 field or energy error",
-                   "fallback_tolerance": 1e-3},
-        "checked_sweep": {"seconds": chk.seconds, "jumps": chk.jumps, "unchecked": chk.unchecked,
-                          "checks": chk.checks, "rejected": chk.rejected, "fell_back": chk.fell_back,
-                          "max_check_error": chk.max_check_error, "max_check_energy": chk.max_check_energy},
-        "loose_checked_sweep": {"tolerance": 0.25, "seconds": loose.seconds, "speedup": plain_s / loose.seconds,
-                                "jumps": loose.jumps, "checks": loose.checks, "rejected": loose.rejected,
-                                "fell_back": loose.fell_back, "max_check_error": loose.max_check_error,
-                                "final_field_error": field_err(loose_f)},
-        "unchecked_sweep": {"seconds": free.seconds, "speedup": plain_s / free.seconds,
-                            "jumps": free.jumps, "final_field_error": field_err(free_f)},
+        "stated_error": stated["final_field_error"],
+        "config": {"workload": f"sweep: {B} lattices of {L}x{L} (batched scene family, seed 5), {steps} steps, "
+                               f"surrogate jumps of K={K}, QLA windows of {args.sweep_window} steps, checks at the "
+                               f"first and every {args.check_every}th jump, fallback at {stated['tolerance']:g} "
+                               "field or energy error",
+                   "fallback_tolerance": stated["tolerance"]},
+        "checked_sweeps": table,
+        "unchecked_sweep": unchecked,
         "plain_qla": {"seconds": plain_s, "site_updates_per_s": B * L * L * steps / plain_s},
-        "network": {"train_runs": 2048, "train_steps": args.train_steps, "train_seconds": train_s,
-                    "data_seconds": gen_s, "heldout_median_error": float(np.median(err)),
-                    "heldout_p90_error": float(np.percentile(err, 90)),
-                    "macs_per_pixel": S.macs_per_pixel(),
-                    "forward_seconds_per_pixel": fwd_s / (B * L * L),
-                    "forward_tflops": flops / fwd_s / 1e12,
+        "network": {**netrec,
+                    "forward_seconds_per_pixel": fwd_s / (c * L * L),
+                    "forward_tflops": 2.0 * S.macs_per_pixel() * c * L * L / fwd_s / 1e12,
                     "qla_seconds_per_site_for_K_steps": plain_s / steps * K / (B * L * L)},
     }
 
@@ -478,7 +528,16 @@ def main():
     ap.add_argument("--workload", default="cylinder_4096",
                     choices=["cylinder_4096", "single_256", "batch_64", "sweep", "unet_forward"])
     ap.add_argument("--train-steps", type=int, default=20000, help="sweep workload: network training steps")
-    ap.add_argument("--sweep-lattices", type=int, default=16, help="sweep workload: lattices of 1024 x 1024")
+    ap.add_argument("--lr", type=float, default=1e-3, help="sweep workload: peak Adam learning rate")
+    ap.add_argument("--sweep-lattices", type=int, default=16, help="sweep workload: lattices per sweep")
+    ap.add_argument("--sweep-side", type=int, default=1024, help="sweep workload: lattice side")
+    ap.add_argument("--sweep-window", type=int, default=0, help="sweep workload: QLA steps after each jump")
+    ap.add_argument("--check-every", type=int, default=4, help="sweep workload: QLA check every n-th jump")
+    ap.add_argument("--tolerances", default="1e-1,3e-2,1e-2,3e-3,1e-3",
+                    help="sweep workload: fallback tolerances of the checked sweeps (the last is the stated one)")
+    ap.add_argument("--no-unchecked", action="store_true", help="sweep workload: skip the unchecked sweep")
+    ap.add_argument("--net-file", default="",
+                    help="sweep workload: load the network from this .npz if it exists, else train and save it")
     ap.add_argument("--unet-lattices", type=int, default=16, help="unet_forward workload: lattices of 1024 x 1024")
     ap.add_argument("--cpu-unet-side", type=int, default=1024, help="unet_forward: side of the oracle's sample")
     ap.add_argument("--pot-mode", choices=["eq28", "eq23"], default="eq28",

@@ -415,19 +415,44 @@ def generate(runs: int, seed: int, L: int = 256, K: int = 256, snaps: int = 9, c
 
 
 def train(net: UNet, data: Dataset, steps: int, batch: int = 16, lr: float = 1e-3, seed: int = 0,
-          log_every: int = 100, log=None) -> List[Dict]:
-    """Adam on random pairs of ``data`` with a cosine learning-rate decay."""
+          log_every: int = 100, log=None, guard_every: int = 500) -> List[Dict]:
+    """Adam on random pairs of ``data`` with a cosine learning-rate decay.
+
+    Every ``guard_every`` steps the batch loss is read back: if it is not
+    finite or has jumped above 20 times the lowest loss seen at these
+    reads, the parameters and Adam moments return to the last good read
+    and the learning rate is halved from then on (a divergence guard)."""
     import torch
 
     rng = np.random.default_rng(seed)
     pairs = data.pairs()
     hist = []
     dev = net.device
+    good = None
+    best = math.inf
+    scale = 1.0
     for it in range(steps):
         sel = pairs[rng.integers(0, len(pairs), batch)]
         idx = torch.as_tensor(sel.T.copy()).to(dev)
-        rate = lr * 0.5 * (1.0 + math.cos(math.pi * it / max(steps, 1)))
-        net.train_step(data.q, idx[0], data.n, idx[1], data.q, idx[2], batch, data.L, data.L, max(rate, lr * 0.02))
+        rate = lr * scale * 0.5 * (1.0 + math.cos(math.pi * it / max(steps, 1)))
+        net.train_step(data.q, idx[0], data.n, idx[1], data.q, idx[2], batch, data.L, data.L,
+                       max(rate, lr * scale * 0.02))
+        if guard_every and (it + 1) % guard_every == 0:
+            loss = float(net.loss.item())
+            if not math.isfinite(loss) or loss > 20.0 * best:
+                if good is not None:
+                    for dst, src in zip((net.p, net.m, net.v), good[:3]):
+                        dst.copy_(src)
+                    net.t = good[3]
+                    qnn.qnn_to_bf16(net.n_params, net.p, net.pb, net.stream)
+                scale *= 0.5
+                rec = {"step": it, "loss": loss, "rolled_back": True, "lr_scale": scale}
+                hist.append(rec)
+                if log:
+                    log(rec)
+            else:
+                best = min(best, loss)
+                good = (net.p.clone(), net.m.clone(), net.v.clone(), net.t)
         if log_every and (it % log_every == 0 or it == steps - 1):
             rec = {"step": it, "loss": float(net.loss.item()), "lr": rate}
             hist.append(rec)
@@ -464,13 +489,42 @@ class SweepResult:
     seconds: float
     max_check_error: float
     max_check_energy: float
+    windows: int = 0     # QLA correction windows run
+    window_steps: int = 0
+    energy_change: float = 0.0   # max over lattices of |E(end)/E(0) - 1| (Eq. (27))
+
+
+def _shape(a) -> Tuple[int, ...]:
+    return tuple(int(v) for v in a.shape)
+
+
+def _export(batch, dst) -> None:
+    for k in range(batch.count):
+        qla.qla_fields_at(batch.ctx, k, dst[k].data_ptr(), 0, False)
+
+
+def _stacked(ts):
+    """ts as one [B][...] tensor: the tensor they are consecutive views of,
+    if they are (no copy of a large batch), else a stacked copy."""
+    import torch
+    base = ts[0]._base
+    if (base is not None and base.dim() == ts[0].dim() + 1 and base.shape[0] == len(ts) and base.is_contiguous()
+            and all(x.data_ptr() == base[k].data_ptr() and x.shape == base.shape[1:] for k, x in enumerate(ts))):
+        return base
+    return torch.stack(ts)
+
+
+def _energies(batch) -> np.ndarray:
+    return np.array([d["energy"] for d in batch.diagnostics()])
 
 
 def sweep(net: UNet, n_list: Sequence, q_list: Sequence, delta: float, total_steps: int, K: int = 256,
           window: int = 0, check_every: int = 4, tol: float = 1e-3, max_rejects: int = 1,
-          device: str = "cuda:0") -> Tuple[SweepResult, List[np.ndarray]]:
-    """Advance lattices (all the same size, sides multiples of 16) by
-    ``total_steps`` QLA steps, replacing runs of K steps by surrogate jumps.
+          device: str = "cuda:0", v_form: str = "printed", energy_tol: Optional[float] = None,
+          out=None, progress=None) -> Tuple[SweepResult, Optional[List[np.ndarray]]]:
+    """Advance lattices (all the same size, sides multiples of 16; numpy
+    arrays or device tensors) by ``total_steps`` QLA steps, replacing runs of
+    K steps by surrogate jumps.
 
     The first jump and then every ``check_every``-th jump is also run by
     plain QLA from the saved pre-jump state: the QLA result is kept, and if
@@ -479,27 +533,34 @@ def sweep(net: UNet, n_list: Sequence, q_list: Sequence, delta: float, total_ste
     ``max_rejects`` rejections the sweep falls back to plain QLA for the
     rest of the run. Other jumps take the surrogate's prediction
     (``check_every`` <= 0: no checks at all). ``window`` plain QLA steps
-    follow each jump. Returns the result record and the final states."""
+    follow each jump. A check measures the error of one jump from the
+    current state; it does not bound the error earlier unchecked jumps have
+    left in that state. ``energy_tol``: a check also fails when some
+    lattice's energy (Eq. (27)) has moved from its initial value by more
+    than this fraction -- a test for the energy-conserving skew potentials
+    (``v_form="skew"``); the printed potentials change the energy by design.
+    ``out``: a device tensor [B][6][H][W] that receives the final states
+    instead of a host copy (None is then returned in their place).
+    ``progress``: called with the step count after every jump and every
+    chunk of at most 5000 plain steps."""
     import torch
 
     dev = torch.device(device)
     stream = net.stream
     B = len(n_list)
-    _, H, W = np.asarray(n_list[0]).shape
-    batch = qla.Batch(list(n_list), list(q_list), [delta] * B, "eq28", "phys", device=device, stream=stream)
+    _, H, W = _shape(n_list[0])
+    batch = qla.Batch(list(n_list), list(q_list), [delta] * B, "eq28", "phys", device=device, stream=stream,
+                      v_form=v_form)
     cur = torch.empty((B, 6, H, W), dtype=torch.float32, device=dev)
     pred = torch.empty_like(cur)
-    ref = torch.empty_like(cur)
-    n_dev = torch.stack([t.view(3, H, W) for t in batch.n])
+    ref = torch.empty_like(cur) if check_every > 0 else None
+    n_dev = _stacked([t.view(3, H, W) for t in batch.n])
     rel = torch.empty(B, dtype=torch.float64, device=dev)
     en = torch.empty(B, dtype=torch.float64, device=dev)
     cmp_work = torch.empty(qnn.qnn_compare_work_doubles(B), dtype=torch.float64, device=dev)
+    e0 = _energies(batch)
 
-    def export(dst):
-        for k in range(B):
-            qla.qla_fields_at(batch.ctx, k, dst[k].data_ptr(), 0, False)
-
-    jumps = unchecked = checks = rejected = 0
+    jumps = unchecked = checks = rejected = windows = window_steps = 0
     max_err = max_en = 0.0
     fell_back = False
     t = 0
@@ -507,20 +568,27 @@ def sweep(net: UNet, n_list: Sequence, q_list: Sequence, delta: float, total_ste
     t0 = time.perf_counter()
     while t < total_steps:
         if fell_back or t + K > total_steps:
-            batch.step(total_steps - t)
-            t = total_steps
+            while t < total_steps:
+                k = min(5000, total_steps - t)
+                batch.step(k)
+                t += k
+                if progress is not None:
+                    progress(t)
             break
-        export(cur)
+        _export(batch, cur)
         net.predict(cur, n_dev, pred)
         jumps += 1
         if check_every > 0 and (jumps == 1 or jumps % check_every == 0):
             checks += 1
             batch.step(K)                        # QLA from the saved pre-jump state
-            export(ref)
+            _export(batch, ref)
             qnn.qnn_compare(B, 6 * H * W, pred, ref, rel, en, cmp_work, stream)
             r, e = rel.cpu().numpy(), en.cpu().numpy()
             max_err, max_en = max(max_err, float(r.max())), max(max_en, float(e.max()))
-            if float(r.max()) > tol or float(e.max()) > tol:
+            bad = float(r.max()) > tol or float(e.max()) > tol
+            if energy_tol is not None:
+                bad = bad or float(np.abs(_energies(batch) / e0 - 1.0).max()) > energy_tol
+            if bad:
                 rejected += 1
                 fell_back = rejected >= max_rejects
         else:
@@ -532,26 +600,52 @@ def sweep(net: UNet, n_list: Sequence, q_list: Sequence, delta: float, total_ste
             w = min(window, total_steps - t)
             batch.step(w)
             t += w
+            windows += 1
+            window_steps += w
+        if progress is not None:
+            progress(t)
     torch.cuda.synchronize(dev)
     secs = time.perf_counter() - t0
-    finals = batch.fields("Q")
+    change = float(np.abs(_energies(batch) / e0 - 1.0).max())
+    if out is not None:
+        _export(batch, out)
+        torch.cuda.synchronize(dev)
+        finals = None
+    else:
+        finals = batch.fields("Q")
     batch.close()
-    return SweepResult(total_steps, jumps, unchecked, checks, rejected, fell_back, secs, max_err, max_en), finals
+    res = SweepResult(total_steps, jumps, unchecked, checks, rejected, fell_back, secs, max_err, max_en, windows,
+                      window_steps, change)
+    return res, finals
 
 
 def plain(n_list: Sequence, q_list: Sequence, delta: float, total_steps: int, device: str = "cuda:0",
-          stream=None) -> Tuple[float, List[np.ndarray]]:
-    """Plain QLA for the same lattices: (seconds, final states)."""
+          stream=None, v_form: str = "printed", out=None, progress=None) -> Tuple[float, Optional[List[np.ndarray]]]:
+    """Plain QLA for the same lattices: (seconds, final states; None when
+    ``out``, a device tensor [B][6][H][W], receives them). ``progress``:
+    called with the step count after every chunk of at most 5000 steps."""
     import torch
 
     dev = torch.device(device)
     batch = qla.Batch(list(n_list), list(q_list), [delta] * len(n_list), "eq28", "phys", device=device,
-                      stream=stream)
+                      stream=stream, v_form=v_form)
     torch.cuda.synchronize(dev)
     t0 = time.perf_counter()
-    batch.step(total_steps)
+    done = 0
+    while done < total_steps:
+        k = min(5000, total_steps - done)
+        batch.step(k)
+        done += k
+        if progress is not None:
+            torch.cuda.synchronize(dev)
+            progress(done)
     torch.cuda.synchronize(dev)
     secs = time.perf_counter() - t0
-    finals = batch.fields("Q")
+    if out is not None:
+        _export(batch, out)
+        torch.cuda.synchronize(dev)
+        finals = None
+    else:
+        finals = batch.fields("Q")
     batch.close()
     return secs, finals

@@ -449,11 +449,14 @@ def test_network_forward_fused_is_bitwise_unfused(env, H, W):
 def test_whole_network_forward_and_gradients(env):
     """GPU U-net (BF16 storage, FP32 accumulation) against the FP64 oracle
     network. Forward: the oracle rounds to BF16 where the GPU stores BF16.
-    Backward: the oracle runs on the GPU's saved activations (so both use
-    the same leaky-ReLU masks: a pre-activation within rounding of zero can
-    otherwise land on either side) and rounds stored activation gradients to
-    BF16 as the GPU does; per-layer weight and bias gradients then agree to
-    a few parts in a thousand."""
+    Every activation the GPU saves for its backward pass is checked against
+    the oracle's. Backward: the oracle runs on the GPU's saved activations
+    (so both use the same leaky-ReLU masks: a pre-activation within rounding
+    of zero can otherwise land on either side) and rounds stored activation
+    gradients to BF16 as the GPU does; per-layer weight and bias gradients
+    then agree to a few parts in a thousand; on the oracle's own activations
+    the whole gradient agrees to a few percent. Also reports the forward's
+    distance from the same network in exact arithmetic (the BF16 floor)."""
     torch, qnn = env
     from paper_2301_13601_amd import surrogate as S
 
@@ -480,12 +483,24 @@ def test_whole_network_forward_and_gradients(env):
     for name, r in act.items():
         if name in net.act and name != "out":
             gpu_act[name] = net.act[name].float().cpu().numpy().astype(np.float64).reshape(r.shape)
+            # the buffers the backward pass reads hold this forward's values
+            assert np.linalg.norm(gpu_act[name] - r) <= 2e-2 * np.linalg.norm(r), name
+    # the BF16 floor of this network: the same weights and input in exact
+    # arithmetic (no BF16 rounding anywhere)
+    exact, _ = N.unet_forward(p, xr, bf16=False)
+    floor = np.linalg.norm(got - exact[..., :6]) / np.linalg.norm(exact[..., :6])
+    print(f"  forward vs exact FP64 network: relative L2 {floor:.3e}")
+    assert floor <= 5e-2
     dout = rnd(23, (B, H, W, 32)) * 0.1
     dout[..., 6:] = 0
     dt, dr = bf(torch, dout)
     net.backward(B, H, W, dt.view(-1))
     g = net.g.cpu().numpy().astype(np.float64)
     rg = N.unet_backward(pr, gpu_act, dr, bf16=True)
+    # and on the oracle's own activations: the leaky-ReLU masks may differ
+    # where a pre-activation is within rounding of zero, so the bar is looser
+    rg_own = N.unet_backward(pr, act, dr, bf16=True)
+    assert np.linalg.norm(g - rg_own) <= 5e-2 * np.linalg.norm(rg_own)
     off = 0
     for name, ci, co, _, _ in N.unet_layers():
         n_w = co * 9 * ci

@@ -958,9 +958,19 @@ __global__ void __launch_bounds__(256) wgrad_lds_kernel(int P, int H, int W, con
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int tid = threadIdx.x;
-  const int co0 = blockIdx.x * 32 * A;
-  const int kb0 = blockIdx.y * 128;
-  const int split = blockIdx.z;
+  // Blocks are dealt round-robin to the 8 XCDs. Regroup them so that each
+  // XCD takes a contiguous run of (channel block, column block, pixel range)
+  // triples, pixel range slowest: the blocks that read the same pixels for
+  // other taps and channels then run on the same XCD and share its L2.
+  const int ncx = gridDim.x, ncy = gridDim.y;
+  const int nblk = ncx * ncy * static_cast<int>(gridDim.z);
+  const int id = blockIdx.x + ncx * (blockIdx.y + ncy * blockIdx.z);
+  const int per = nblk / 8, rem = nblk % 8, xcd = id % 8, k8 = id / 8;
+  const int logical = (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + k8;
+  const int bx = logical % ncx, by = (logical / ncx) % ncy;
+  const int co0 = bx * 32 * A;
+  const int kb0 = by * 128;
+  const int split = logical / (ncx * ncy);
   const int K = 9 * cin;
   const int pbeg = split * pps;
   const int pend = min(P, pbeg + pps);
@@ -1038,7 +1048,7 @@ __global__ void __launch_bounds__(256) wgrad_lds_kernel(int P, int H, int W, con
   float bsum[A];
 #pragma unroll
   for (int a = 0; a < A; ++a) bsum[a] = 0.0f;
-  const bool want_bias = bpart && blockIdx.y == 0 && wave == 0;
+  const bool want_bias = bpart && by == 0 && wave == 0;
   if (pbeg < pend) fetch(pbeg);
   for (int pc = pbeg; pc < pend; pc += kWtChunk) {
     __syncthreads();      // every wave is done with the previous chunk

@@ -573,6 +573,7 @@ def sweep(net: UNet, n_list: Sequence, q_list: Sequence, delta: float, total_ste
                 batch.step(k)
                 t += k
                 if progress is not None:
+                    torch.cuda.synchronize(dev)    # report steps done, not steps enqueued
                     progress(t)
             break
         _export(batch, cur)
@@ -603,6 +604,7 @@ def sweep(net: UNet, n_list: Sequence, q_list: Sequence, delta: float, total_ste
             windows += 1
             window_steps += w
         if progress is not None:
+            torch.cuda.synchronize(dev)
             progress(t)
     torch.cuda.synchronize(dev)
     secs = time.perf_counter() - t0

@@ -1,6 +1,7 @@
 """The perturbation-parameter study harness: its scene is the 256 x 256 run
-at delta = 0.3 (CPU), and a short run of the study logs what it promises
-(GPU)."""
+at delta = 0.3 (CPU); a short run of the study logs what it promises, and
+its runs at delta = 0.3 (all placements, polarisations and potential forms,
+500 steps) and at delta = 0.1 (4500 steps) match the FP64 oracle (GPU)."""
 import numpy as np
 import pytest
 
@@ -36,3 +37,56 @@ def test_short_study_runs_and_skew_conserves_energy():
         assert all(key in e for e in r["log"])
         if r["v_form"] == "skew":
             assert abs(r["log"][-1]["energy_rel"]) < 1e-5
+
+
+def _oracle_e_and_energy(delta, mode, pol, form, steps):
+    from oracle import oracle as O
+    n, q = delta_study.scene(delta, pol)
+    n64, q64 = n.astype(np.float64), q.astype(np.float64)
+    want = O.run(n64, q64, delta, steps, mode, "phys", v_form=form)
+    comp = 2 if pol == "Ez" else 1
+    return want[comp] / n64[comp], O.energy(want) / O.energy(q64) - 1.0
+
+
+def _gpu_or_skip():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("form", ["printed", "skew"])
+@pytest.mark.parametrize("mode", ["eq23", "eq28"])
+@pytest.mark.parametrize("pol", ["Ez", "Ey"])
+def test_study_run_matches_the_oracle_at_delta_03(pol, mode, form):
+    """The study's own composition (polarised context, logged steps) at its
+    coarsest spacing over the published 500 steps: the final field (the
+    study samples every cell at delta = 0.3) and the logged energy change
+    against the FP64 oracle."""
+    _gpu_or_skip()
+    print(f"[delta study] delta 0.3 {pol} {mode} {form}", flush=True)
+    r = delta_study.run_one(0.3, mode, pol, 45.0, 2, form)
+    assert r["steps"] == 500
+    e_want, drift_want = _oracle_e_and_energy(0.3, mode, pol, form, r["steps"])
+    err = float(np.abs(r["_sample"] - e_want).max() / np.abs(e_want).max())
+    drift = r["log"][-1]["energy_rel"]
+    print(f"  max rel field err {err:.3e}; energy change gpu {drift:+.6e} oracle {drift_want:+.6e}")
+    assert err <= 1e-5
+    assert abs(drift - drift_want) <= 1e-5 * (1.0 + abs(drift_want))
+
+
+@pytest.mark.gpu
+def test_study_run_matches_the_oracle_at_delta_01():
+    """delta = 0.1 (768 x 768) over the published 4500 steps, printed
+    potentials, Eq. (28), E_z: the bar is the 500-step 1e-5 grown with the
+    square root of the step count (3e-5)."""
+    _gpu_or_skip()
+    print("[delta study] delta 0.1 Ez eq28 printed, 4500 steps", flush=True)
+    r = delta_study.run_one(0.1, "eq28", "Ez", 45.0, 1, "printed", coarse=0.1)
+    assert r["steps"] == 4500
+    e_want, drift_want = _oracle_e_and_energy(0.1, "eq28", "Ez", "printed", r["steps"])
+    err = float(np.abs(r["_sample"] - e_want).max() / np.abs(e_want).max())
+    drift = r["log"][-1]["energy_rel"]
+    print(f"  max rel field err {err:.3e}; energy change gpu {drift:+.6e} oracle {drift_want:+.6e}")
+    assert err <= 1e-5 * (4500 / 500) ** 0.5
+    assert abs(drift - drift_want) <= 1e-5 * (1.0 + abs(drift_want))

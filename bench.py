@@ -102,7 +102,7 @@ def _triple_of(kernel_name: str):
     """Field triple of a step-kernel instance from its demangled name
     (the fifth option of its KOpt), or None for other kernels."""
     import re
-    m = re.search(r"qla_step_kernel<\d+, (?:qla_dev::)?KOpt<[^,]+, [^,]+, [^,]+, [^,]+, (\d+), \d+>", kernel_name)
+    m = re.search(r"qla_step_kernel<\d+, (?:qla_dev::)?KOpt<[^,]+, [^,]+, [^,]+, [^,]+, (\d+), \d+(?:, \d+)?>", kernel_name)
     return _TRIPLE_NAMES.get(m.group(1)) if m else None
 
 

@@ -133,12 +133,18 @@ typedef struct qla_ctx qla_ctx;   /* opaque */
  *                    wave runs the step twice in one march over its rows
  *                    (temporal blocking: Q and n cross HBM once per two
  *                    steps); an odd remainder of a qla_step call runs as one
- *                    one-step launch. */
+ *                    one-step launch.
+ *   stream_loads     1: read the state rows with the non-temporal cache
+ *                    policy, 2: with the default policy (0 asks for the
+ *                    library's default: 1 for a single lattice, 2 for a
+ *                    batch). Six-component contexts only; TM and TE
+ *                    contexts always use the default policy (reported 2). */
 typedef struct {
     int32_t seg_rows;
     int32_t waves_per_block;
     int32_t graph_steps;
     int32_t steps_per_pass;
+    int32_t stream_loads;
 } qla_launch;
 
 /* One lattice of a batch: its parameters and caller-owned device buffers

@@ -2,8 +2,8 @@
 
 For a set of lattice shapes (one lattice or a batch) and the potential
 placement, time a small set of launch geometries (steps per launch, segment
-height, waves per block, steps per replayed graph) on the GPU and keep the
-fastest. Results
+height, waves per block, steps per replayed graph, cache policy of the state
+loads) on the GPU and keep the fastest. Results
 are cached as JSON keyed by GPU architecture, placement and shapes, so a
 second call for the same key measures nothing.
 
@@ -24,7 +24,7 @@ DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "qla_autotune.js
 
 def _key(arch: str, pot_mode: str, beta_scale: str, shapes: Sequence[Tuple[int, int]]) -> str:
     h = hashlib.sha256(json.dumps(sorted(shapes)).encode()).hexdigest()[:16]
-    return f"{arch}|{pot_mode}|{beta_scale}|n{len(shapes)}|{h}|spp12w"
+    return f"{arch}|{pot_mode}|{beta_scale}|n{len(shapes)}|{h}|spp12ws"
 
 
 def candidates(default_seg: int, max_ny: int, steps_per_pass: int = 1) -> List[Dict[str, int]]:
@@ -37,14 +37,17 @@ def candidates(default_seg: int, max_ny: int, steps_per_pass: int = 1) -> List[D
             segs.add(s)
     out = []
     # a two-step block is always one producer/consumer pair: waves_per_block
-    # only shapes one-step launches
+    # only shapes one-step launches; two-step launches try both cache
+    # policies of the state loads (non-temporal pays off for tall segments)
     wpbs = (1, 2) if steps_per_pass == 1 else (1,)
+    pols = (2,) if steps_per_pass == 1 else (1, 2)
     for s in sorted(segs):
         for wpb in wpbs:
-            out.append({"seg_rows": s, "waves_per_block": wpb, "graph_steps": 32,
-                        "steps_per_pass": steps_per_pass})
+            for pol in pols:
+                out.append({"seg_rows": s, "waves_per_block": wpb, "graph_steps": 32,
+                            "steps_per_pass": steps_per_pass, "stream_loads": pol})
     out.append({"seg_rows": default_seg, "waves_per_block": 1, "graph_steps": 1,
-                "steps_per_pass": steps_per_pass})
+                "steps_per_pass": steps_per_pass, "stream_loads": 2})
     return out
 
 

@@ -545,6 +545,10 @@ qla_status plan_step(qla_ctx* c) {
   ch.vec = vec;
   ch.fields = c->polarisation;
   ch.skew = c->v_form;
+  // non-temporal state loads: asked for, or by default for a single lattice
+  // (tall segments; a batch of narrow lattices rereads more halo rows)
+  ch.stream = c->polarisation == QLA_POL_BOTH &&
+              (c->launch.stream_loads == 1 || (c->launch.stream_loads == 0 && c->count == 1));
   using Pick = StepImpl (*)(const qla_dev::StepChoice&);
   static constexpr Pick kPick[2][3] = {
       {qla_dev::pick_step_m0_f0, qla_dev::pick_step_m0_f1, qla_dev::pick_step_m0_f2},
@@ -555,7 +559,7 @@ qla_status plan_step(qla_ctx* c) {
     qla_status st = plan_geometry(c, steps, wpb);
     if (st != QLA_OK) return st;
   }
-  c->planned = qla_launch{c->geo[spp - 1].seg_rows, wpb, gsteps, spp};
+  c->planned = qla_launch{c->geo[spp - 1].seg_rows, wpb, gsteps, spp, ch.stream ? 1 : 2};
   return QLA_OK;
 }
 
@@ -691,7 +695,7 @@ qla_status init_common(int32_t count, const qla_instance* inst, void* d_work, vo
     return hip_fail(nullptr, e == hipSuccess ? hipErrorInvalidDevice : e, "querying the device");
   }
   c->cus = cus;
-  c->launch = qla_launch{0, 0, 0, 0};
+  c->launch = qla_launch{0, 0, 0, 0, 0};
   st = plan_step(c);
   if (st != QLA_OK) {
     delete c;
@@ -929,7 +933,7 @@ qla_status qla_set_launch(qla_ctx* ctx, const qla_launch* req) {
   if (!req) return fail(QLA_EINVAL, "qla: null launch pointer");
   if (req->seg_rows < 0 || req->seg_rows > (1 << 28) || req->waves_per_block < 0 ||
       req->waves_per_block > 4 || req->graph_steps < 0 || req->graph_steps > 4096 ||
-      req->steps_per_pass < 0 || req->steps_per_pass > 2)
+      req->steps_per_pass < 0 || req->steps_per_pass > 2 || req->stream_loads < 0 || req->stream_loads > 2)
     return fail(QLA_EINVAL, "qla: launch fields out of range");
   const qla_launch keep = ctx->launch;
   ctx->launch = *req;

@@ -178,11 +178,12 @@ constexpr uint32_t kNoStore = 0x80000000u;    // beyond any row extent
 // Cache policy of a buffer access (the instruction's cache-policy bits):
 // default, or non-temporal ("nt"): the line is not kept for reuse. The step
 // writes every row once and no wave of the launch reads it back, so stores
-// are non-temporal; the six-component state rows are read non-temporally
-// too. Measured per two-step launch on the 4096^2 cylinder: 241.5 -> 235.7
-// us for the stores, -> 225.7 us with the state loads; non-temporal index
-// loads and, for the TM triple, state loads were slower, so those keep the
-// default policy.
+// are non-temporal. State rows are read non-temporally as a launch option
+// (KOpt::STREAM, six components): per two-step launch on the 4096^2
+// cylinder 241.5 -> 235.7 us for the stores, -> 225.7 us with the state
+// loads, but a batch of narrow lattices in 128-row segments, whose
+// neighbouring segments reread their halo rows from L2, ran 8 % slower with
+// them. Non-temporal index loads, and TM state loads, were slower.
 constexpr int kCacheDefault = 0;
 constexpr int kCacheStream = 2;
 
@@ -242,7 +243,10 @@ __device__ __forceinline__ bool wave_any(bool v) { return __any(v) != 0; }
 //   SKEW    0: the potentials of Eq. (21)/(22) as printed; 1: their
 //           skew-symmetric part, a rotation by half the angle in the same
 //           pairs (an orthogonal, energy-conserving variant)
-template <int MODE_, bool POT_, bool WIDE_, bool VEC_, int FIELDS_, int SKEW_>
+//   STREAM  state rows are loaded non-temporally (six components only;
+//           faster for tall segments, slower where neighbouring segments
+//           reread many halo rows)
+template <int MODE_, bool POT_, bool WIDE_, bool VEC_, int FIELDS_, int SKEW_, int STREAM_ = 0>
 struct KOpt {
   static constexpr int MODE = MODE_;
   static constexpr bool POT = POT_;
@@ -250,6 +254,7 @@ struct KOpt {
   static constexpr bool VEC = VEC_;
   static constexpr int FIELDS = FIELDS_;
   static constexpr bool SKEW = SKEW_ != 0;
+  static constexpr bool STREAM = STREAM_ != 0;
   static constexpr bool TE = FIELDS_ != 1;     // (q0, q1, q5) live
   static constexpr bool TM = FIELDS_ != 2;     // (q2, q3, q4) live
   static constexpr bool live(int c) { return (c == 0 || c == 1 || c == 5) ? TE : TM; }
@@ -325,7 +330,7 @@ __device__ __forceinline__ void load_q(const StepArgs& g, const float* row, cons
                                        float (&qld)[6][C]) {
 #pragma unroll
   for (int c = 0; c < 6; ++c)
-    if (O::live(c)) load_row<C, O::VEC, O::FIELDS == 0 ? kCacheStream : kCacheDefault>(row + c * g.plane, g.nx, xo, qld[c]);
+    if (O::live(c)) load_row<C, O::VEC, O::STREAM ? kCacheStream : kCacheDefault>(row + c * g.plane, g.nx, xo, qld[c]);
 }
 
 template <int C, class O>
@@ -1250,6 +1255,7 @@ struct StepChoice {
   bool vec;
   int fields;      // 0 all, 1 TM, 2 TE
   int skew;        // 0 printed potentials, 1 skew-symmetric
+  bool stream;     // non-temporal state loads (six components only)
 };
 
 // One translation unit per (placement, field triple) instantiates these.
@@ -1258,6 +1264,13 @@ StepImpl pick_step(const StepChoice& ch) {
   constexpr int C = 2;
   auto pick_pot = [&](auto vecc, auto widec) -> StepImpl {
     constexpr bool V = decltype(vecc)::value, Wd = decltype(widec)::value;
+    if constexpr (FIELDS == 0) {
+      if (ch.stream) {
+        if (!ch.pot) return impl<C, KOpt<MODE, false, Wd, V, FIELDS, 0, 1>>();
+        if (ch.skew) return impl<C, KOpt<MODE, true, Wd, V, FIELDS, 1, 1>>();
+        return impl<C, KOpt<MODE, true, Wd, V, FIELDS, 0, 1>>();
+      }
+    }
     if (!ch.pot) return impl<C, KOpt<MODE, false, Wd, V, FIELDS, 0>>();
     if (ch.skew) return impl<C, KOpt<MODE, true, Wd, V, FIELDS, 1>>();
     return impl<C, KOpt<MODE, true, Wd, V, FIELDS, 0>>();

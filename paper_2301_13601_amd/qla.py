@@ -49,7 +49,8 @@ class Diag(ctypes.Structure):
 
 class Launch(ctypes.Structure):
     _fields_ = [("seg_rows", ctypes.c_int32), ("waves_per_block", ctypes.c_int32),
-                ("graph_steps", ctypes.c_int32), ("steps_per_pass", ctypes.c_int32)]
+                ("graph_steps", ctypes.c_int32), ("steps_per_pass", ctypes.c_int32),
+                ("stream_loads", ctypes.c_int32)]
 
     def as_dict(self) -> Dict[str, int]:
         return {name: int(getattr(self, name)) for name, _ in self._fields_}
@@ -203,8 +204,8 @@ def qla_get_launch(ctx) -> Dict[str, int]:
 
 
 def qla_set_launch(ctx, seg_rows: int = 0, waves_per_block: int = 0, graph_steps: int = 0,
-                   steps_per_pass: int = 0) -> None:
-    req = Launch(int(seg_rows), int(waves_per_block), int(graph_steps), int(steps_per_pass))
+                   steps_per_pass: int = 0, stream_loads: int = 0) -> None:
+    req = Launch(int(seg_rows), int(waves_per_block), int(graph_steps), int(steps_per_pass), int(stream_loads))
     _check(lib().qla_set_launch(ctx, ctypes.byref(req)))
 
 
@@ -268,8 +269,8 @@ class Simulation:
         return qla_get_launch(self.ctx)
 
     def set_launch(self, seg_rows: int = 0, waves_per_block: int = 0, graph_steps: int = 0,
-                   steps_per_pass: int = 0) -> None:
-        qla_set_launch(self.ctx, seg_rows, waves_per_block, graph_steps, steps_per_pass)
+                   steps_per_pass: int = 0, stream_loads: int = 0) -> None:
+        qla_set_launch(self.ctx, seg_rows, waves_per_block, graph_steps, steps_per_pass, stream_loads)
 
     def state_tensor(self):
         """The device tensor that holds the current state (no copy)."""
@@ -350,8 +351,8 @@ class Batch:
         return qla_get_launch(self.ctx)
 
     def set_launch(self, seg_rows: int = 0, waves_per_block: int = 0, graph_steps: int = 0,
-                   steps_per_pass: int = 0) -> None:
-        qla_set_launch(self.ctx, seg_rows, waves_per_block, graph_steps, steps_per_pass)
+                   steps_per_pass: int = 0, stream_loads: int = 0) -> None:
+        qla_set_launch(self.ctx, seg_rows, waves_per_block, graph_steps, steps_per_pass, stream_loads)
 
     def close(self) -> None:
         if self.ctx is not None:

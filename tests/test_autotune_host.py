@@ -17,3 +17,12 @@ def test_candidate_segments_are_multiples_of_four_within_the_lattice():
                 assert 8 <= c["seg_rows"] <= max(8, ny + 3) or c["seg_rows"] == default
     # one candidate replays no graph (every launch on its own)
     assert any(c["graph_steps"] == 1 for c in autotune.candidates(152, 4096, 2))
+
+
+def test_two_step_candidates_try_both_cache_policies():
+    c2 = autotune.candidates(152, 4096, steps_per_pass=2)
+    assert {c["stream_loads"] for c in c2} == {1, 2}
+    segs = {c["seg_rows"] for c in c2 if c["graph_steps"] == 32}
+    for s in segs:
+        assert {c["stream_loads"] for c in c2 if c["seg_rows"] == s and c["graph_steps"] == 32} == {1, 2}
+    assert all(c["stream_loads"] == 2 for c in autotune.candidates(152, 4096, steps_per_pass=1))

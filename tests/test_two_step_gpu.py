@@ -148,3 +148,35 @@ def test_steps_per_pass_is_validated(qla):
     with pytest.raises(qla.QlaError):
         sim.set_launch(steps_per_pass=3)
     sim.close()
+
+
+@pytest.mark.parametrize("spp", [1, 2])
+@pytest.mark.parametrize("mode", ["eq23", "eq28"])
+def test_state_load_cache_policy_is_bitwise(qla, spp, mode):
+    """Non-temporal and default state loads give the same bits; a single
+    lattice defaults to non-temporal loads, a batch to the default policy,
+    and a TM context always uses the default."""
+    n = scenes.smooth_random_profile(300, 210, 41, 1.0, 3.0).astype(np.float32)
+    q = scenes.random_state(300, 210, 42).astype(np.float32)
+    _case(f"state-load cache policy, {spp} step(s) per launch, {mode}")
+    outs = []
+    for pol in (1, 2):
+        sim = qla.Simulation(n, q, 0.3, mode)
+        assert sim.launch()["stream_loads"] == 1
+        sim.set_launch(steps_per_pass=spp, stream_loads=pol)
+        assert sim.launch()["stream_loads"] == pol
+        sim.step(11)
+        outs.append(sim.fields("Q"))
+        sim.close()
+    assert np.array_equal(outs[0], outs[1])
+    b = qla.Batch([n, n], [q, q], [0.3, 0.3], mode)
+    assert b.launch()["stream_loads"] == 2
+    b.set_launch(steps_per_pass=spp, stream_loads=1)
+    b.step(11)
+    for f in b.fields("Q"):
+        assert np.array_equal(f, outs[0])
+    b.close()
+    tm = qla.Simulation(n, q, 0.3, mode, polarisation="tm")
+    tm.set_launch(stream_loads=1)
+    assert tm.launch()["stream_loads"] == 2
+    tm.close()

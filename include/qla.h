@@ -138,13 +138,19 @@ typedef struct qla_ctx qla_ctx;   /* opaque */
  *                    policy, 2: with the default policy (0 asks for the
  *                    library's default: 1 for a single lattice, 2 for a
  *                    batch). Six-component contexts only; TM and TE
- *                    contexts always use the default policy (reported 2). */
+ *                    contexts always use the default policy (reported 2).
+ *   vacuum_rows      1 (default): a wave does not fetch the index row of
+ *                    its 128 columns when every index there that the step
+ *                    uses is exactly 1 (vacuum; qla_init records, per row,
+ *                    the columns where it is not), 2: every index row is
+ *                    fetched. */
 typedef struct {
     int32_t seg_rows;
     int32_t waves_per_block;
     int32_t graph_steps;
     int32_t steps_per_pass;
     int32_t stream_loads;
+    int32_t vacuum_rows;
 } qla_launch;
 
 /* One lattice of a batch: its parameters and caller-owned device buffers
@@ -165,7 +171,10 @@ qla_status qla_workspace_size(const qla_params *p, size_t *bytes);
 qla_status qla_batch_workspace_size(int32_t count, const qla_instance *inst, size_t *bytes);
 
 /* Bind the caller's buffers and validate n.
- *   d_n        3*ny*nx FP32, n_x, n_y, n_z; read by every step, never written
+ *   d_n        3*ny*nx FP32, n_x, n_y, n_z; read by every step, never
+ *              written, and not to be changed by the caller while the
+ *              context lives (qla_init records its angle ranges and, per
+ *              row, the columns where it differs from 1, in d_work)
  *   d_q        6*ny*nx FP32, holds Q at step 0 on entry
  *   d_q_pong   6*ny*nx FP32 scratch state; steps alternate between the two
  *   d_work     qla_workspace_size() bytes, 256-byte aligned

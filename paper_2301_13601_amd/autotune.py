@@ -24,7 +24,7 @@ DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "qla_autotune.js
 
 def _key(arch: str, pot_mode: str, beta_scale: str, shapes: Sequence[Tuple[int, int]]) -> str:
     h = hashlib.sha256(json.dumps(sorted(shapes)).encode()).hexdigest()[:16]
-    return f"{arch}|{pot_mode}|{beta_scale}|n{len(shapes)}|{h}|spp12ws"
+    return f"{arch}|{pot_mode}|{beta_scale}|n{len(shapes)}|{h}|spp12wsv"
 
 
 def candidates(default_seg: int, max_ny: int, steps_per_pass: int = 1) -> List[Dict[str, int]]:

@@ -115,6 +115,50 @@ __global__ void qla_scan_final(ScanPartial* __restrict__ parts, int count) {
 }
 
 // ---------------------------------------------------------------------------
+// Vacuum spans of n at init: per row, the first and last column at which
+// one of the index planes in `planes` (bit c: plane c) differs from 1, or
+// (nx, -1) for a row of vacuum. The step kernel takes a row's index window
+// as 1 without reading it when the window lies outside the span.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) qla_span_kernel(const float* __restrict__ n, int nx, int ny,
+                                                       int planes, int* __restrict__ span) {
+  const int64_t plane = static_cast<int64_t>(nx) * ny;
+  __shared__ int sh[2][256 / kWave];
+  for (int y = blockIdx.x; y < ny; y += gridDim.x) {
+    int lo = nx, hi = -1;
+    for (int x = threadIdx.x; x < nx; x += blockDim.x) {
+      const int64_t s = static_cast<int64_t>(y) * nx + x;
+      bool other = false;
+      for (int c = 0; c < 3; ++c)
+        if ((planes >> c) & 1) other = other || n[c * plane + s] != 1.0f;
+      if (other) {
+        lo = min(lo, x);
+        hi = max(hi, x);
+      }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      lo = min(lo, __shfl_xor(lo, o));
+      hi = max(hi, __shfl_xor(hi, o));
+    }
+    const int w = threadIdx.x / kWave;
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+      sh[0][w] = lo;
+      sh[1][w] = hi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int k = 1; k < static_cast<int>(blockDim.x / kWave); ++k) {
+        lo = min(lo, sh[0][k]);
+        hi = max(hi, sh[1][k]);
+      }
+      span[2 * y] = lo;
+      span[2 * y + 1] = hi;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Diagnostics (Eq. (27), div B, div D): per-block FP64 partials, then one
 // block folds them.
 // ---------------------------------------------------------------------------
@@ -282,11 +326,17 @@ constexpr int out_cols(int steps) { return (kWave - 2 * ((4 * steps + kCols - 1)
 size_t align256(size_t v) { return (v + 255) & ~static_cast<size_t>(255); }
 
 // workspace layout: diagnostics partials | scan partials | lattice
-// descriptors of the one-step launch | of the two-step launch
+// descriptors of the one-step launch | of the two-step launch | the vacuum
+// spans of each lattice's rows
 size_t diag_bytes() { return align256(static_cast<size_t>(kDiagBlocks + 1) * kDiagVals * sizeof(double)); }
 size_t scan_bytes() { return align256(static_cast<size_t>(kDiagBlocks + 1) * sizeof(ScanPartial)); }
 size_t desc_bytes(int count) { return align256(sizeof(InstDesc) * count); }
-size_t work_bytes(int count) { return diag_bytes() + scan_bytes() + 2 * desc_bytes(count); }
+size_t span_bytes(int ny) { return align256(2 * sizeof(int) * static_cast<size_t>(ny)); }
+size_t work_bytes(int count, const qla_instance* inst) {
+  size_t b = diag_bytes() + scan_bytes() + 2 * desc_bytes(count);
+  for (int i = 0; i < count; ++i) b += span_bytes(inst[i].p.ny);
+  return b;
+}
 
 }  // namespace
 
@@ -307,6 +357,7 @@ struct qla_ctx {
   std::vector<qla_params> p;
   std::vector<const float*> n;
   std::vector<float*> buf[2];
+  std::vector<int*> span;  // per lattice: its rows' vacuum spans (workspace)
   int cur;                 // which buffer (0 or 1) holds the current state
   void* work;
   hipStream_t stream;
@@ -513,6 +564,7 @@ qla_status plan_geometry(qla_ctx* c, int steps, int wpb) {
     d.first_block = first;
     d.a4 = static_cast<float>(p.delta / 4.0);
     d.kb = static_cast<float>(kb_of(p));
+    d.span = c->span[i];
     first += d.nstrips * ((d.nsegs + wpb - 1) / wpb);
     tallest = std::max(tallest, d.seg_rows);
   }
@@ -559,13 +611,15 @@ qla_status plan_step(qla_ctx* c) {
     qla_status st = plan_geometry(c, steps, wpb);
     if (st != QLA_OK) return st;
   }
-  c->planned = qla_launch{c->geo[spp - 1].seg_rows, wpb, gsteps, spp, ch.stream ? 1 : 2};
+  c->planned = qla_launch{c->geo[spp - 1].seg_rows, wpb, gsteps, spp, ch.stream ? 1 : 2,
+                          c->launch.vacuum_rows == 2 ? 2 : 1};
   return QLA_OK;
 }
 
 BatchArgs batch_args(const qla_ctx* c, int steps, int parity) {
   const auto& geo = c->geo[steps - 1];
-  return BatchArgs{geo.d_desc, c->count, parity, steps == 2 ? 1 : static_cast<int>(geo.block.x / kWave)};
+  return BatchArgs{geo.d_desc, c->count, parity, steps == 2 ? 1 : static_cast<int>(geo.block.x / kWave),
+                   c->planned.vacuum_rows == 2 ? 1 : 0};
 }
 
 // One launch advancing `steps` (1 or 2) time steps from buffer `parity`.
@@ -625,6 +679,12 @@ qla_status scan_instance(qla_ctx* c, int i, double* theta_max, double* bmax) {
     return fail(QLA_EINVAL, "qla: lattice %d: every refractive index must be finite and > 0", i);
   *theta_max = std::max(*theta_max, p.delta / (4.0 * res.nmin));
   *bmax = std::max(*bmax, res.bmax);
+  // the index planes the step reads: n_x, n_y for the TE triple, n_z for TM
+  const int planes = c->polarisation == QLA_POL_TM ? 4 : (c->polarisation == QLA_POL_TE ? 3 : 7);
+  hipLaunchKernelGGL(qla_span_kernel, dim3(std::min(p.ny, 4096)), dim3(256), 0, c->stream, c->n[i], p.nx, p.ny,
+                     planes, c->span[i]);
+  e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(nullptr, e, "summarising n");
   return QLA_OK;
 }
 
@@ -657,6 +717,11 @@ qla_status init_common(int32_t count, const qla_instance* inst, void* d_work, vo
       c->n.push_back(inst[i].d_n);
       c->buf[0].push_back(inst[i].d_q);
       c->buf[1].push_back(inst[i].d_q_pong);
+    }
+    char* s = static_cast<char*>(d_work) + diag_bytes() + scan_bytes() + 2 * desc_bytes(count);
+    for (int i = 0; i < count; ++i) {
+      c->span.push_back(reinterpret_cast<int*>(s));
+      s += span_bytes(inst[i].p.ny);
     }
   } catch (...) {
     delete c;
@@ -695,7 +760,7 @@ qla_status init_common(int32_t count, const qla_instance* inst, void* d_work, vo
     return hip_fail(nullptr, e == hipSuccess ? hipErrorInvalidDevice : e, "querying the device");
   }
   c->cus = cus;
-  c->launch = qla_launch{0, 0, 0, 0, 0};
+  c->launch = qla_launch{0, 0, 0, 0, 0, 0};
   st = plan_step(c);
   if (st != QLA_OK) {
     delete c;
@@ -736,7 +801,8 @@ qla_status qla_workspace_size(const qla_params* p, size_t* bytes) {
   qla_status st = check_params(p);
   if (st != QLA_OK) return st;
   if (!bytes) return fail(QLA_EINVAL, "qla: null bytes pointer");
-  *bytes = work_bytes(1);
+  const qla_instance one{*p, nullptr, nullptr, nullptr};
+  *bytes = work_bytes(1, &one);
   return QLA_OK;
 }
 
@@ -744,7 +810,7 @@ qla_status qla_batch_workspace_size(int32_t count, const qla_instance* inst, siz
   qla_status st = check_batch(count, inst);
   if (st != QLA_OK) return st;
   if (!bytes) return fail(QLA_EINVAL, "qla: null bytes pointer");
-  *bytes = work_bytes(count);
+  *bytes = work_bytes(count, inst);
   return QLA_OK;
 }
 
@@ -933,7 +999,8 @@ qla_status qla_set_launch(qla_ctx* ctx, const qla_launch* req) {
   if (!req) return fail(QLA_EINVAL, "qla: null launch pointer");
   if (req->seg_rows < 0 || req->seg_rows > (1 << 28) || req->waves_per_block < 0 ||
       req->waves_per_block > 4 || req->graph_steps < 0 || req->graph_steps > 4096 ||
-      req->steps_per_pass < 0 || req->steps_per_pass > 2 || req->stream_loads < 0 || req->stream_loads > 2)
+      req->steps_per_pass < 0 || req->steps_per_pass > 2 || req->stream_loads < 0 || req->stream_loads > 2 ||
+      req->vacuum_rows < 0 || req->vacuum_rows > 2)
     return fail(QLA_EINVAL, "qla: launch fields out of range");
   const qla_launch keep = ctx->launch;
   ctx->launch = *req;

@@ -31,6 +31,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <climits>
 #include <cstdint>
 #include <type_traits>
 
@@ -148,10 +149,18 @@ struct StepArgs {
   const float* __restrict__ qin;   // 6 planes
   float* __restrict__ qout;        // 6 planes
   const float* __restrict__ n;     // 3 planes
+  // per row y: the first and last column at which an index plane the step
+  // reads differs from 1 (nx and -1 for a row of vacuum)
+  const int* __restrict__ span;
   int64_t plane;                   // nx * ny
   int nx, ny;
   float a4;                        // delta / 4                    (Eq. (24))
   float kb;                        // kappa * frac / 2             (Eq. (25))
+  // the wave's column window as a vacuum test (vacuum_span): a row is
+  // vacuum for the wave if its span ends before wa, starts after wb, or lies
+  // within the gap (g0, g1) that a window wrapping around the lattice
+  // leaves open
+  int wa, wb, g0, g1;
 };
 
 // Columns of a strip: a pass of STEPS steps has an x support of 4*STEPS
@@ -333,13 +342,54 @@ __device__ __forceinline__ void load_q(const StepArgs& g, const float* row, cons
     if (O::live(c)) load_row<C, O::VEC, O::STREAM ? kCacheStream : kCacheDefault>(row + c * g.plane, g.nx, xo, qld[c]);
 }
 
+// n of a row whose window is vacuum (every index the step uses is 1 on
+// the wave's columns) is not fetched: its loads get an empty extent, so the
+// hardware returns 0 without touching memory, and fix_n puts the 1 the row
+// holds in their place once they have landed. The loads stay in the
+// instruction stream either way, so the march keeps one schedule (and one
+// set of waits) for both kinds of row; skipping the instructions with a
+// branch measured slower. Scattering scenes are mostly vacuum, and the
+// index is a fifth of the bytes a site moves per launch. No wave reads an
+// index row that is vacuum on its window.
 template <int C, class O>
 __device__ __forceinline__ void load_n(const StepArgs& g, const float* row, const uint32_t (&xo)[C],
-                                       float (&nld)[3][C]) {
+                                       float (&nld)[3][C], bool vacuum) {
+  const int extent = vacuum ? 0 : g.nx;
 #pragma unroll
   for (int c = 0; c < 3; ++c)
-    if (O::nlive(c)) load_row<C, O::VEC>(row + c * g.plane, g.nx, xo, nld[c]);
+    if (O::nlive(c)) load_row<C, O::VEC>(row + c * g.plane, extent, xo, nld[c]);
 }
+
+template <int C, class O>
+__device__ __forceinline__ void fix_n(float (&nld)[3][C], bool vacuum) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+    if (O::nlive(c)) {
+#pragma unroll
+      for (int k = 0; k < C; ++k) nld[c][k] = vacuum ? 1.0f : nld[c][k];
+    }
+}
+
+// The columns [lo, hi] of a row at which an index the step uses is not 1
+// (lo > hi: none), read for the whole wave. The span table does not change
+// during a launch, so it is read through the constant address space: a
+// scalar load, which the wave waits for without waiting on its vector
+// loads in flight. The marches read a row's span one iteration before they
+// test it, so that the load's latency hides behind that iteration's work.
+struct Span {
+  int lo, hi;
+};
+typedef const __attribute__((address_space(4))) int ConstInt;
+__device__ __forceinline__ Span row_span(const StepArgs& g, int r) {
+  const ConstInt* s = (const ConstInt*)(g.span);
+  const int ru = __builtin_amdgcn_readfirstlane(r);
+  return Span{s[2 * ru], s[2 * ru + 1]};
+}
+// Whether the wave's window of a row with span sp holds only vacuum.
+__device__ __forceinline__ bool vacuum_span(const StepArgs& g, Span sp) {
+  return sp.hi < g.wa || sp.lo > g.wb || (sp.lo > g.g0 && sp.hi < g.g1);
+}
+__device__ __forceinline__ bool vacuum_row(const StepArgs& g, int r) { return vacuum_span(g, row_span(g, r)); }
 
 // Where a pipeline's row coefficients (Eq. (24), (25)) come from.
 enum { kCoefCompute = 0, kCoefExport = 1, kCoefImport = 2 };
@@ -882,24 +932,32 @@ __device__ __forceinline__ void pipe_clear(Pipe<C>& p) {
 }
 
 // The n window of a pipeline whose first ingested row is R0: rows R0-DIR
-// (n_x, n_z), R0, R0+DIR, R0+2*DIR.
+// (n_x, n_z), R0, R0+DIR, R0+2*DIR (rows of vacuum keep the 1 pipe_clear
+// put there).
 template <int C, class O, int DIR>
 __device__ __forceinline__ void prime_n(Pipe<C>& p, const StepArgs& g, const uint32_t (&xo)[C], int64_t R0) {
   constexpr bool VEC = O::VEC;
   const int64_t nx64 = g.nx;
-  const float* nm = g.n + wrap_index(R0 - DIR, g.ny) * nx64;
-  const float* n0 = g.n + wrap_index(R0, g.ny) * nx64;
-  const float* n1 = g.n + wrap_index(R0 + DIR, g.ny) * nx64;
-  const float* n2 = g.n + wrap_index(R0 + 2 * DIR, g.ny) * nx64;
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    if (!O::nlive(c)) continue;
-    load_row<C, VEC>(n0 + c * g.plane, g.nx, xo, p.ncur[c]);
-    load_row<C, VEC>(n1 + c * g.plane, g.nx, xo, p.nnext[c]);
-    load_row<C, VEC>(n2 + c * g.plane, g.nx, xo, p.nn2[c]);
+  const int rm = wrap_index(R0 - DIR, g.ny);
+  const int r0 = wrap_index(R0, g.ny);
+  const int r1 = wrap_index(R0 + DIR, g.ny);
+  const int r2 = wrap_index(R0 + 2 * DIR, g.ny);
+  if (!vacuum_row(g, r0)) load_n<C, O>(g, g.n + r0 * nx64, xo, p.ncur, false);
+  if (!vacuum_row(g, r1)) load_n<C, O>(g, g.n + r1 * nx64, xo, p.nnext, false);
+  if (!vacuum_row(g, r2)) load_n<C, O>(g, g.n + r2 * nx64, xo, p.nn2, false);
+  if (!vacuum_row(g, rm)) {
+    const float* nm = g.n + rm * nx64;
+    if (O::nlive(0)) load_row<C, VEC>(nm + 0 * g.plane, g.nx, xo, p.nprev[0]);
+    if (O::nlive(2)) load_row<C, VEC>(nm + 2 * g.plane, g.nx, xo, p.nprev[1]);
   }
-  if (O::nlive(0)) load_row<C, VEC>(nm + 0 * g.plane, g.nx, xo, p.nprev[0]);
-  if (O::nlive(2)) load_row<C, VEC>(nm + 2 * g.plane, g.nx, xo, p.nprev[1]);
+}
+
+// Row iterations of a march of STEPS steps over a segment of seg_h rows:
+// the segment and 4 rows of y support per step on each side, in whole
+// groups of four.
+template <int STEPS>
+__device__ __forceinline__ int march_iters(int seg_h) {
+  return ((seg_h + 8 * STEPS) + 3) & ~3;
 }
 
 template <int DIR>
@@ -934,19 +992,25 @@ __device__ __forceinline__ void march(const StepArgs& g, const uint32_t (&xo)[C]
   // rows in flight: Q of R+2*DIR, n of R+3*DIR (wrapped incrementally)
   int rq = wrap_index(R0 + 2 * DIR, g.ny);
   int rn = wrap_index(R0 + 3 * DIR, g.ny);
-  const int iters = ((seg_h + 8) + 3) & ~3;
+  Span sn = row_span(g, rn);
+  const int iters = march_iters<1>(seg_h);
   float unused[6][C];
   const CoefIO<C> io{nullptr, nullptr, nullptr, nullptr, 0};
   for (int i = 0; i < iters; i += 4) {
 #define QLA_ITER(S)                                                                            \
   {                                                                                            \
     float qld[6][C], nld[3][C];                                                                \
+    const int rn1 = next_row<DIR>(rn, g.ny);                                                   \
+    const Span sn1 = row_span(g, rn1);   /* a row ahead */                                     \
     load_q<C, O>(g, g.qin + rq * nx64, xo, qld);                                               \
-    load_n<C, O>(g, g.n + rn * nx64, xo, nld);                                                 \
+    const bool vac = vacuum_span(g, sn);                                                       \
+    load_n<C, O>(g, g.n + rn * nx64, xo, nld, vac);                                            \
     process_row<C, O, DIR, S, false, 4, kCoefCompute>(p, g, so, edge_lane, i + S, seg_h, y0, unused, io); \
+    fix_n<C, O>(nld, vac);                                                                     \
     advance<C, O, true>(p, qld, nld);                                                          \
     rq = next_row<DIR>(rq, g.ny);                                                              \
-    rn = next_row<DIR>(rn, g.ny);                                                              \
+    rn = rn1;                                                                                  \
+    sn = sn1;                                                                                  \
   }
     QLA_ITER(0)
     QLA_ITER(1)
@@ -1000,7 +1064,7 @@ __device__ __forceinline__ void march2(const StepArgs& g, const uint32_t (&xo)[C
   pipe_clear(p);
   const int64_t RA = DIR > 0 ? static_cast<int64_t>(y0) - 8 : static_cast<int64_t>(y0) + seg_h + 7;
   const int64_t nx64 = g.nx;
-  const int iters = ((seg_h + 16) + 3) & ~3;
+  const int iters = march_iters<2>(seg_h);
   float unused[6][C];
   constexpr int NR = Ring<C, O>::NR;
   // Eq. (23): this wave's (q1, q4) row slots start at zero, like the
@@ -1034,13 +1098,17 @@ __device__ __forceinline__ void march2(const StepArgs& g, const uint32_t (&xo)[C
     }
     int rq = wrap_index(RA + 2 * DIR, g.ny);
     int rn = wrap_index(RA + 3 * DIR, g.ny);
+    Span sn = row_span(g, rn);
     int r6 = 0;   // iteration mod NR
     for (int i = 0; i < iters; i += 4) {
 #define QLA_ITER_A(S)                                                                          \
   {                                                                                            \
     float qld[6][C], nld[3][C], e[6][C];                                                       \
+    const int rn1 = next_row<DIR>(rn, g.ny);                                                   \
+    const Span sn1 = row_span(g, rn1);   /* a row ahead */                                     \
     load_q<C, O>(g, g.qin + rq * nx64, xo, qld);                                               \
-    load_n<C, O>(g, g.n + rn * nx64, xo, nld);                                                 \
+    const bool vac = vacuum_span(g, sn);                                                       \
+    load_n<C, O>(g, g.n + rn * nx64, xo, nld, vac);                                            \
     /* the ring entries of slot S hold the row four iterations old: the row */                \
     /* the consumer takes in this iteration */                                                 \
     _Pragma("unroll") for (int k = 0; k < C; ++k) {                                            \
@@ -1073,9 +1141,11 @@ __device__ __forceinline__ void march2(const StepArgs& g, const uint32_t (&xo)[C
       if (!O::live(c)) continue;                                                               \
       _Pragma("unroll") for (int k = 0; k < C; ++k) ring.q[(S) & 1][M::q(c)][lane * C + k] = e[c][k]; \
     }                                                                                          \
+    fix_n<C, O>(nld, vac);                                                                     \
     advance<C, O, true>(p, qld, nld);                                                          \
     rq = next_row<DIR>(rq, g.ny);                                                              \
-    rn = next_row<DIR>(rn, g.ny);                                                              \
+    rn = rn1;                                                                                  \
+    sn = sn1;                                                                                  \
     r6 = r6 == NR - 1 ? 0 : r6 + 1;                                                            \
     __syncthreads();                                                                           \
   }
@@ -1134,7 +1204,7 @@ struct InstDesc {
   int nstrips, nsegs;
   int first_block;       // blocks of the lattices before this one
   float a4, kb;
-  int pad[2];
+  const int* span;       // 2 * ny ints: per row, first and last non-vacuum column
 };
 static_assert(sizeof(InstDesc) == 72, "descriptor layout");
 
@@ -1143,6 +1213,7 @@ struct BatchArgs {
   int count;             // lattices in the batch
   int parity;            // state buffer holding the input of this step
   int waves_per_block;
+  int read_all_n;        // 1: read every index row (no vacuum rows taken as 1)
 };
 
 // STEPS time steps per launch (1, or 2 with temporal blocking).
@@ -1179,6 +1250,7 @@ __global__ void __launch_bounds__(256) qla_step_kernel(BatchArgs ba) {
   g.qin = d.q[ba.parity];
   g.qout = const_cast<float*>(d.q[ba.parity ^ 1]);
   g.n = d.n;
+  g.span = d.span;
   g.plane = d.plane;
   g.nx = d.nx;
   g.ny = d.ny;
@@ -1189,6 +1261,33 @@ __global__ void __launch_bounds__(256) qla_step_kernel(BatchArgs ba) {
   const int seg_h = min(d.seg_rows, g.ny - y0);
   const int x0 = strip * Cl::kOut;
   const int64_t col0 = static_cast<int64_t>(x0) - Cl::kHaloLanes * C + lane * C;
+  {
+    // the columns the wave loads, [wa, wb] taken periodically
+    int wa = x0 - Cl::kHaloLanes * C;
+    int wb = wa + kWave * C - 1;
+    int g0 = INT_MAX, g1 = INT_MIN;
+    if (ba.read_all_n != 0) {          // never vacuum
+      wa = INT_MIN;
+      wb = INT_MAX;
+    } else if (wb - wa + 1 >= g.nx) {  // every column: only a row without a span
+      wa = 0;
+      wb = INT_MAX;
+    } else if (wa < 0) {               // [0, wb] and [wa + nx, nx - 1]
+      g0 = wb;
+      g1 = wa + g.nx;
+      wa = 0;
+      wb = INT_MAX;
+    } else if (wb >= g.nx) {           // [wa, nx - 1] and [0, wb - nx]
+      g0 = wb - g.nx;
+      g1 = wa;
+      wa = 0;
+      wb = INT_MAX;
+    }
+    g.wa = wa;
+    g.wb = wb;
+    g.g0 = g0;
+    g.g1 = g1;
+  }
   // byte offsets of the lane's columns within a row: loads wrap
   // periodically, stores only for output columns of this strip
   uint32_t xo[C], so[C];

@@ -50,7 +50,7 @@ class Diag(ctypes.Structure):
 class Launch(ctypes.Structure):
     _fields_ = [("seg_rows", ctypes.c_int32), ("waves_per_block", ctypes.c_int32),
                 ("graph_steps", ctypes.c_int32), ("steps_per_pass", ctypes.c_int32),
-                ("stream_loads", ctypes.c_int32)]
+                ("stream_loads", ctypes.c_int32), ("vacuum_rows", ctypes.c_int32)]
 
     def as_dict(self) -> Dict[str, int]:
         return {name: int(getattr(self, name)) for name, _ in self._fields_}
@@ -204,8 +204,9 @@ def qla_get_launch(ctx) -> Dict[str, int]:
 
 
 def qla_set_launch(ctx, seg_rows: int = 0, waves_per_block: int = 0, graph_steps: int = 0,
-                   steps_per_pass: int = 0, stream_loads: int = 0) -> None:
-    req = Launch(int(seg_rows), int(waves_per_block), int(graph_steps), int(steps_per_pass), int(stream_loads))
+                   steps_per_pass: int = 0, stream_loads: int = 0, vacuum_rows: int = 0) -> None:
+    req = Launch(int(seg_rows), int(waves_per_block), int(graph_steps), int(steps_per_pass), int(stream_loads),
+                 int(vacuum_rows))
     _check(lib().qla_set_launch(ctx, ctypes.byref(req)))
 
 
@@ -269,8 +270,9 @@ class Simulation:
         return qla_get_launch(self.ctx)
 
     def set_launch(self, seg_rows: int = 0, waves_per_block: int = 0, graph_steps: int = 0,
-                   steps_per_pass: int = 0, stream_loads: int = 0) -> None:
-        qla_set_launch(self.ctx, seg_rows, waves_per_block, graph_steps, steps_per_pass, stream_loads)
+                   steps_per_pass: int = 0, stream_loads: int = 0, vacuum_rows: int = 0) -> None:
+        qla_set_launch(self.ctx, seg_rows, waves_per_block, graph_steps, steps_per_pass, stream_loads,
+                       vacuum_rows)
 
     def state_tensor(self):
         """The device tensor that holds the current state (no copy)."""
@@ -351,8 +353,9 @@ class Batch:
         return qla_get_launch(self.ctx)
 
     def set_launch(self, seg_rows: int = 0, waves_per_block: int = 0, graph_steps: int = 0,
-                   steps_per_pass: int = 0, stream_loads: int = 0) -> None:
-        qla_set_launch(self.ctx, seg_rows, waves_per_block, graph_steps, steps_per_pass, stream_loads)
+                   steps_per_pass: int = 0, stream_loads: int = 0, vacuum_rows: int = 0) -> None:
+        qla_set_launch(self.ctx, seg_rows, waves_per_block, graph_steps, steps_per_pass, stream_loads,
+                       vacuum_rows)
 
     def close(self) -> None:
         if self.ctx is not None:

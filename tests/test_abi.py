@@ -169,3 +169,33 @@ def test_pool_conv_rejects_what_it_cannot_run_without_a_device(qla):
                 dict(B=1 << 11, H=1024, W=1024)]:
         assert call(**bad) == -1, bad
         assert "conv3x3_fwd_pool" in qla.qla_last_error()
+
+
+def header_struct_fields(name, header=HEADER):
+    """Field names, in order, of `typedef struct { ... } name;` in a header."""
+    text = re.sub(r"/\*.*?\*/", "", open(header).read(), flags=re.S)
+    m = re.search(r"typedef struct\s*\{([^}]*)\}\s*" + name + r"\s*;", text)
+    assert m, name
+    fields = []
+    for decl in m.group(1).split(";"):
+        decl = decl.strip()
+        if decl:
+            fields += [re.sub(r"[*\s]", "", v) for v in re.sub(r"^[\w\s]*?\s(?=\**\w+(\s*,|$))", "", decl).split(",")]
+    return fields
+
+
+@pytest.mark.parametrize("cname,pyname", [("qla_params", "Params"), ("qla_diag", "Diag"),
+                                          ("qla_launch", "Launch"), ("qla_instance", "Instance")])
+def test_python_structures_mirror_the_header(cname, pyname):
+    """The ctypes structures the binding passes across the ABI have the
+    header's fields in the header's order."""
+    from paper_2301_13601_amd import qla as q
+    assert [f for f, _ in getattr(q, pyname)._fields_] == header_struct_fields(cname)
+
+
+def test_workspace_holds_two_ints_per_row(qla):
+    """The workspace grows by the vacuum spans of n: two int32 per row
+    (per lattice in a batch), whatever the row length."""
+    base = qla.qla_workspace_size(qla.make_params(300, 256, 0.3))
+    assert qla.qla_workspace_size(qla.make_params(300, 512, 0.3)) - base == 8 * 256
+    assert qla.qla_workspace_size(qla.make_params(4096, 256, 0.3)) == base

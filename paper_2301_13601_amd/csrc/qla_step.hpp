@@ -296,18 +296,12 @@ struct Pipe {
   bool fx[4];
   float q14[4][3][C];
   // the ingested row R and the rows in flight: Q of R and R+DIR, n of R-DIR
-  // (x and z components), R, R+DIR and R+2*DIR
+  // (x and z components), R and R+DIR
   float q[6][C];
   float q1[6][C];
   float nprev[2][C];
   float ncur[3][C];
   float nnext[3][C];
-  float nn2[3][C];
-};
-
-struct RowBases {
-  const float* qld;    // Q row R+2*DIR (plane 0)
-  const float* nld;    // n row R+3*DIR (plane 0)
 };
 
 // Lag (in rows) of the y-pipeline after each of its 8 stream stages. A stage
@@ -333,7 +327,7 @@ __device__ __forceinline__ void vcoef(float b, float& c0, float& c1) {
 }
 
 // Prefetch of the rows a pipeline needs later: Q of row R+2*DIR (stage fed
-// from memory only) and n of row R+3*DIR.
+// from memory only) and n of row R+2*DIR.
 template <int C, class O>
 __device__ __forceinline__ void load_q(const StepArgs& g, const float* row, const uint32_t (&xo)[C],
                                        float (&qld)[6][C]) {
@@ -867,8 +861,9 @@ __device__ __forceinline__ void process_row(Pipe<C>& p, const StepArgs& g, const
 }
 
 // Advance a pipeline's row window by one row: n rows shift by one (nld is
-// n of row R+3*DIR); with FEED, Q rows too (qld is Q of row R+2*DIR), else
-// the caller puts the next ingested row into p.q.
+// n of row R+2*DIR, first used at the end of the next row's iteration);
+// with FEED, Q rows too (qld is Q of row R+2*DIR), else the caller puts the
+// next ingested row into p.q.
 template <int C, class O, bool FEED>
 __device__ __forceinline__ void advance(Pipe<C>& p, const float (&qld)[6][C], const float (&nld)[3][C]) {
 #pragma unroll
@@ -879,8 +874,7 @@ __device__ __forceinline__ void advance(Pipe<C>& p, const float (&qld)[6][C], co
     for (int c = 0; c < 3; ++c) {
       if (!O::nlive(c)) continue;
       p.ncur[c][k] = p.nnext[c][k];
-      p.nnext[c][k] = p.nn2[c][k];
-      p.nn2[c][k] = nld[c][k];
+      p.nnext[c][k] = nld[c][k];
     }
     if constexpr (FEED) {
 #pragma unroll
@@ -926,14 +920,14 @@ __device__ __forceinline__ void pipe_clear(Pipe<C>& p) {
 #pragma unroll
   for (int c = 0; c < 3; ++c)
 #pragma unroll
-    for (int k = 0; k < C; ++k) p.ncur[c][k] = p.nnext[c][k] = p.nn2[c][k] = 1.0f;
+    for (int k = 0; k < C; ++k) p.ncur[c][k] = p.nnext[c][k] = 1.0f;
 #pragma unroll
   for (int k = 0; k < C; ++k) p.nprev[0][k] = p.nprev[1][k] = 1.0f;
 }
 
 // The n window of a pipeline whose first ingested row is R0: rows R0-DIR
-// (n_x, n_z), R0, R0+DIR, R0+2*DIR (rows of vacuum keep the 1 pipe_clear
-// put there).
+// (n_x, n_z), R0 and R0+DIR (rows of vacuum keep the 1 pipe_clear put
+// there).
 template <int C, class O, int DIR>
 __device__ __forceinline__ void prime_n(Pipe<C>& p, const StepArgs& g, const uint32_t (&xo)[C], int64_t R0) {
   constexpr bool VEC = O::VEC;
@@ -941,10 +935,8 @@ __device__ __forceinline__ void prime_n(Pipe<C>& p, const StepArgs& g, const uin
   const int rm = wrap_index(R0 - DIR, g.ny);
   const int r0 = wrap_index(R0, g.ny);
   const int r1 = wrap_index(R0 + DIR, g.ny);
-  const int r2 = wrap_index(R0 + 2 * DIR, g.ny);
   if (!vacuum_row(g, r0)) load_n<C, O>(g, g.n + r0 * nx64, xo, p.ncur, false);
   if (!vacuum_row(g, r1)) load_n<C, O>(g, g.n + r1 * nx64, xo, p.nnext, false);
-  if (!vacuum_row(g, r2)) load_n<C, O>(g, g.n + r2 * nx64, xo, p.nn2, false);
   if (!vacuum_row(g, rm)) {
     const float* nm = g.n + rm * nx64;
     if (O::nlive(0)) load_row<C, VEC>(nm + 0 * g.plane, g.nx, xo, p.nprev[0]);
@@ -989,9 +981,9 @@ __device__ __forceinline__ void march(const StepArgs& g, const uint32_t (&xo)[C]
     }
     prime_n<C, O, DIR>(p, g, xo, R0);
   }
-  // rows in flight: Q of R+2*DIR, n of R+3*DIR (wrapped incrementally)
+  // rows in flight: Q and n of R+2*DIR (wrapped incrementally)
   int rq = wrap_index(R0 + 2 * DIR, g.ny);
-  int rn = wrap_index(R0 + 3 * DIR, g.ny);
+  int rn = rq;
   Span sn = row_span(g, rn);
   const int iters = march_iters<1>(seg_h);
   float unused[6][C];
@@ -1097,7 +1089,7 @@ __device__ __forceinline__ void march2(const StepArgs& g, const uint32_t (&xo)[C
       prime_n<C, O, DIR>(p, g, xo, RA);
     }
     int rq = wrap_index(RA + 2 * DIR, g.ny);
-    int rn = wrap_index(RA + 3 * DIR, g.ny);
+    int rn = rq;
     Span sn = row_span(g, rn);
     int r6 = 0;   // iteration mod NR
     for (int i = 0; i < iters; i += 4) {

@@ -135,10 +135,9 @@ typedef struct qla_ctx qla_ctx;   /* opaque */
  *                    steps); an odd remainder of a qla_step call runs as one
  *                    one-step launch.
  *   stream_loads     1: read the state rows with the non-temporal cache
- *                    policy, 2: with the default policy (0 asks for the
- *                    library's default: 1 for a single lattice, 2 for a
- *                    batch). Six-component contexts only; TM and TE
- *                    contexts always use the default policy (reported 2).
+ *                    policy, 2: with the default policy (the default).
+ *                    Six-component contexts only; TM and TE contexts
+ *                    always use the default policy (reported 2).
  *   vacuum_rows      1 (default): a wave does not fetch the index row of
  *                    its 128 columns when every index there that the step
  *                    uses is exactly 1 (vacuum; qla_init records, per row,

@@ -597,10 +597,9 @@ qla_status plan_step(qla_ctx* c) {
   ch.vec = vec;
   ch.fields = c->polarisation;
   ch.skew = c->v_form;
-  // non-temporal state loads: asked for, or by default for a single lattice
-  // (tall segments; a batch of narrow lattices rereads more halo rows)
-  ch.stream = c->polarisation == QLA_POL_BOTH &&
-              (c->launch.stream_loads == 1 || (c->launch.stream_loads == 0 && c->count == 1));
+  // non-temporal state loads only when asked for: with the index rows of
+  // vacuum skipped they no longer pay off on a single lattice either
+  ch.stream = c->polarisation == QLA_POL_BOTH && c->launch.stream_loads == 1;
   using Pick = StepImpl (*)(const qla_dev::StepChoice&);
   static constexpr Pick kPick[2][3] = {
       {qla_dev::pick_step_m0_f0, qla_dev::pick_step_m0_f1, qla_dev::pick_step_m0_f2},

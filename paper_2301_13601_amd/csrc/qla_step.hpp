@@ -187,12 +187,14 @@ constexpr uint32_t kNoStore = 0x80000000u;    // beyond any row extent
 // Cache policy of a buffer access (the instruction's cache-policy bits):
 // default, or non-temporal ("nt"): the line is not kept for reuse. The step
 // writes every row once and no wave of the launch reads it back, so stores
-// are non-temporal. State rows are read non-temporally as a launch option
-// (KOpt::STREAM, six components): per two-step launch on the 4096^2
-// cylinder 241.5 -> 235.7 us for the stores, -> 225.7 us with the state
-// loads, but a batch of narrow lattices in 128-row segments, whose
-// neighbouring segments reread their halo rows from L2, ran 8 % slower with
-// them. Non-temporal index loads, and TM state loads, were slower.
+// are non-temporal (per two-step launch on the 4096^2 cylinder 241.5 ->
+// 235.7 us). State rows can be read non-temporally as a launch option
+// (KOpt::STREAM, six components): that took the cylinder to 225.7 us while
+// every index row was fetched, but once index rows of vacuum are skipped
+// the default policy is 1 % faster there, and a batch of narrow lattices in
+// 128-row segments, whose neighbouring segments reread their halo rows from
+// L2, ran 8 % slower with it. Non-temporal index loads, and TM state loads,
+// were slower.
 constexpr int kCacheDefault = 0;
 constexpr int kCacheStream = 2;
 
@@ -252,9 +254,8 @@ __device__ __forceinline__ bool wave_any(bool v) { return __any(v) != 0; }
 //   SKEW    0: the potentials of Eq. (21)/(22) as printed; 1: their
 //           skew-symmetric part, a rotation by half the angle in the same
 //           pairs (an orthogonal, energy-conserving variant)
-//   STREAM  state rows are loaded non-temporally (six components only;
-//           faster for tall segments, slower where neighbouring segments
-//           reread many halo rows)
+//   STREAM  state rows are loaded non-temporally (six components only; a
+//           launch option the autotuner tries)
 template <int MODE_, bool POT_, bool WIDE_, bool VEC_, int FIELDS_, int SKEW_, int STREAM_ = 0>
 struct KOpt {
   static constexpr int MODE = MODE_;

@@ -153,16 +153,16 @@ def test_steps_per_pass_is_validated(qla):
 @pytest.mark.parametrize("spp", [1, 2])
 @pytest.mark.parametrize("mode", ["eq23", "eq28"])
 def test_state_load_cache_policy_is_bitwise(qla, spp, mode):
-    """Non-temporal and default state loads give the same bits; a single
-    lattice defaults to non-temporal loads, a batch to the default policy,
-    and a TM context always uses the default."""
+    """Non-temporal and default state loads give the same bits; single
+    lattices and batches default to the default policy, and a TM context
+    always uses it."""
     n = scenes.smooth_random_profile(300, 210, 41, 1.0, 3.0).astype(np.float32)
     q = scenes.random_state(300, 210, 42).astype(np.float32)
     _case(f"state-load cache policy, {spp} step(s) per launch, {mode}")
     outs = []
     for pol in (1, 2):
         sim = qla.Simulation(n, q, 0.3, mode)
-        assert sim.launch()["stream_loads"] == 1
+        assert sim.launch()["stream_loads"] == 2
         sim.set_launch(steps_per_pass=spp, stream_loads=pol)
         assert sim.launch()["stream_loads"] == pol
         sim.step(11)

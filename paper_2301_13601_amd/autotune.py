@@ -38,7 +38,7 @@ def candidates(default_seg: int, max_ny: int, steps_per_pass: int = 1) -> List[D
     out = []
     # a two-step block is always one producer/consumer pair: waves_per_block
     # only shapes one-step launches; two-step launches try both cache
-    # policies of the state loads (non-temporal pays off for tall segments)
+    # policies of the state loads (which one wins depends on the lattices)
     wpbs = (1, 2) if steps_per_pass == 1 else (1,)
     pols = (2,) if steps_per_pass == 1 else (1, 2)
     for s in sorted(segs):

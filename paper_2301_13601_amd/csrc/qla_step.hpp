@@ -366,11 +366,9 @@ __device__ __forceinline__ void fix_n(float (&nld)[3][C], bool vacuum) {
 }
 
 // The columns [lo, hi] of a row at which an index the step uses is not 1
-// (lo > hi: none), read for the whole wave. The span table does not change
-// during a launch, so it is read through the constant address space: a
-// scalar load, which the wave waits for without waiting on its vector
-// loads in flight. The marches read a row's span one iteration before they
-// test it, so that the load's latency hides behind that iteration's work.
+// (lo > hi: none), read for the whole wave when a march primes its index
+// window. The span table does not change during a launch, so it is read
+// through the constant address space: a scalar load.
 struct Span {
   int lo, hi;
 };
@@ -385,6 +383,18 @@ __device__ __forceinline__ bool vacuum_span(const StepArgs& g, Span sp) {
   return sp.hi < g.wa || sp.lo > g.wb || (sp.lo > g.g0 && sp.hi < g.g1);
 }
 __device__ __forceinline__ bool vacuum_row(const StepArgs& g, int r) { return vacuum_span(g, row_span(g, r)); }
+
+// Whether the wave's window is vacuum on each of the next 64 index rows a
+// march loads, from row r on in direction DIR: bit k for row r + k*DIR
+// (taken periodically). Each lane tests one row's span and a ballot
+// gathers the answers, so a march that refreshes the mask every 64 rows
+// tests a row with a shift, with no memory access and no wait per row (a
+// scalar load per row waited on the LDS operations in flight too).
+template <int DIR>
+__device__ __forceinline__ uint64_t vacuum_mask(const StepArgs& g, int r) {
+  const int rr = wrap_index(static_cast<int64_t>(r) + DIR * static_cast<int>(__lane_id()), g.ny);
+  return __ballot(vacuum_span(g, Span{g.span[2 * rr], g.span[2 * rr + 1]}));
+}
 
 // Where a pipeline's row coefficients (Eq. (24), (25)) come from.
 enum { kCoefCompute = 0, kCoefExport = 1, kCoefImport = 2 };
@@ -985,25 +995,24 @@ __device__ __forceinline__ void march(const StepArgs& g, const uint32_t (&xo)[C]
   // rows in flight: Q and n of R+2*DIR (wrapped incrementally)
   int rq = wrap_index(R0 + 2 * DIR, g.ny);
   int rn = rq;
-  Span sn = row_span(g, rn);
+  uint64_t vmask = 0;   // vacuum flags of the index rows to load (vacuum_mask)
   const int iters = march_iters<1>(seg_h);
   float unused[6][C];
   const CoefIO<C> io{nullptr, nullptr, nullptr, nullptr, 0};
   for (int i = 0; i < iters; i += 4) {
+    if ((i & 63) == 0) vmask = vacuum_mask<DIR>(g, rn);
 #define QLA_ITER(S)                                                                            \
   {                                                                                            \
     float qld[6][C], nld[3][C];                                                                \
-    const int rn1 = next_row<DIR>(rn, g.ny);                                                   \
-    const Span sn1 = row_span(g, rn1);   /* a row ahead */                                     \
     load_q<C, O>(g, g.qin + rq * nx64, xo, qld);                                               \
-    const bool vac = vacuum_span(g, sn);                                                       \
+    const bool vac = (vmask & 1) != 0;                                                         \
+    vmask >>= 1;                                                                               \
     load_n<C, O>(g, g.n + rn * nx64, xo, nld, vac);                                            \
     process_row<C, O, DIR, S, false, 4, kCoefCompute>(p, g, so, edge_lane, i + S, seg_h, y0, unused, io); \
     fix_n<C, O>(nld, vac);                                                                     \
     advance<C, O, true>(p, qld, nld);                                                          \
     rq = next_row<DIR>(rq, g.ny);                                                              \
-    rn = rn1;                                                                                  \
-    sn = sn1;                                                                                  \
+    rn = next_row<DIR>(rn, g.ny);                                                              \
   }
     QLA_ITER(0)
     QLA_ITER(1)
@@ -1091,16 +1100,16 @@ __device__ __forceinline__ void march2(const StepArgs& g, const uint32_t (&xo)[C
     }
     int rq = wrap_index(RA + 2 * DIR, g.ny);
     int rn = rq;
-    Span sn = row_span(g, rn);
+    uint64_t vmask = 0;   // vacuum flags of the index rows to load (vacuum_mask)
     int r6 = 0;   // iteration mod NR
     for (int i = 0; i < iters; i += 4) {
+      if ((i & 63) == 0) vmask = vacuum_mask<DIR>(g, rn);
 #define QLA_ITER_A(S)                                                                          \
   {                                                                                            \
     float qld[6][C], nld[3][C], e[6][C];                                                       \
-    const int rn1 = next_row<DIR>(rn, g.ny);                                                   \
-    const Span sn1 = row_span(g, rn1);   /* a row ahead */                                     \
     load_q<C, O>(g, g.qin + rq * nx64, xo, qld);                                               \
-    const bool vac = vacuum_span(g, sn);                                                       \
+    const bool vac = (vmask & 1) != 0;                                                         \
+    vmask >>= 1;                                                                               \
     load_n<C, O>(g, g.n + rn * nx64, xo, nld, vac);                                            \
     /* the ring entries of slot S hold the row four iterations old: the row */                \
     /* the consumer takes in this iteration */                                                 \
@@ -1137,8 +1146,7 @@ __device__ __forceinline__ void march2(const StepArgs& g, const uint32_t (&xo)[C
     fix_n<C, O>(nld, vac);                                                                     \
     advance<C, O, true>(p, qld, nld);                                                          \
     rq = next_row<DIR>(rq, g.ny);                                                              \
-    rn = rn1;                                                                                  \
-    sn = sn1;                                                                                  \
+    rn = next_row<DIR>(rn, g.ny);                                                              \
     r6 = r6 == NR - 1 ? 0 : r6 + 1;                                                            \
     __syncthreads();                                                                           \
   }

@@ -1217,6 +1217,18 @@ struct BatchArgs {
   int read_all_n;        // 1: read every index row (no vacuum rows taken as 1)
 };
 
+// Row pos of the order 0, 8, 16, ..., 1, 9, 17, ..., 7, 15, ... of the rows
+// 0 .. n-1 (a permutation).
+__device__ __forceinline__ int interleave8(int pos, int n) {
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const int cnt = (n - r + 7) / 8;   // rows r, r + 8, ... below n
+    if (pos < cnt) return r + 8 * pos;
+    pos -= cnt;
+  }
+  return n;   // pos >= n: no row
+}
+
 // STEPS time steps per launch (1, or 2 with temporal blocking).
 template <int C, class O, int STEPS>
 __global__ void __launch_bounds__(256) qla_step_kernel(BatchArgs ba) {
@@ -1225,8 +1237,10 @@ __global__ void __launch_bounds__(256) qla_step_kernel(BatchArgs ba) {
   // wave index within the block, as a wave-uniform (scalar) value
   const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x / kWave));
   // blocks are dealt round-robin to the 8 XCDs; regroup them so that each
-  // XCD gets a contiguous band of work (neighbouring strips and segments
-  // share halo data through that XCD's L2)
+  // XCD gets a contiguous band of work (neighbouring strips share halo
+  // columns through that XCD's L2), the band's rows of blocks taken from
+  // the lattice eight rows apart (so that every XCD gets a share of an
+  // object's rows, which take longest)
   const int nblk = gridDim.x;
   const int b = blockIdx.x;
   const int per = nblk / 8;
@@ -1243,8 +1257,10 @@ __global__ void __launch_bounds__(256) qla_step_kernel(BatchArgs ba) {
   const InstDesc& d = ba.desc[lo];
   const int local = logical - d.first_block;
   const int strip = local % d.nstrips;
+  const int brows = STEPS == 2 ? d.nsegs : (d.nsegs + ba.waves_per_block - 1) / ba.waves_per_block;
+  const int brow = interleave8(local / d.nstrips, brows);
   // a two-step block is one producer/consumer pair of waves on one segment
-  const int seg = STEPS == 2 ? local / d.nstrips : (local / d.nstrips) * ba.waves_per_block + wave;
+  const int seg = STEPS == 2 ? brow : brow * ba.waves_per_block + wave;
   if (seg >= d.nsegs) return;
 
   StepArgs g;
